@@ -1,0 +1,201 @@
+/*
+ * sc_api.h -- C ABI of the MI355X (gfx950) collision-resolution library.
+ *
+ * The library implements the data-parallel core of the collision method of
+ * Yan, Corona, Malhotra, Veerapaneni and Shelley, "A scalable computational
+ * platform for particulate Stokes suspensions" (arXiv:1909.06623), section 3:
+ * the close-pair set A(C, delta), the contact Jacobian D, the LCP data
+ * q = Phi/dt + D^T U_nc, and the Barzilai-Borwein projected gradient descent
+ * (Algorithm 1) of min 1/2 gamma^T M gamma + q^T gamma over gamma >= 0 with
+ * M = D^T Mob D, where Mob is a block-diagonal per-particle ("dry") mobility.
+ * An implicit adjoint of the converged solve is provided as well.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers (hipMalloc'd or equivalent) in
+ *     FP64 unless typed otherwise; indices are int32. Arrays are row-major.
+ *     Structs themselves are passed by host pointer.
+ *   - The caller owns every buffer. No entry point allocates device memory:
+ *     scratch comes from a caller-provided workspace of at least
+ *     sc_workspace_bytes(n, capacity) bytes, 256-byte aligned.
+ *   - `stream` is a hipStream_t (NULL = the null stream). Work is enqueued on
+ *     it in order. Entry points that must report a count or a status to the
+ *     host (build_contacts, solve_lcp, solve_lcp_adjoint) synchronise that
+ *     stream before returning; the others do not.
+ *   - A particle's 6-vectors (velocity, force) are (x, y, z, wx, wy, wz):
+ *     translational part, then rotational part (section 2 stacks U and F
+ *     per particle in this order).
+ *   - Return value: one of the SC_* codes below. On an error return nothing
+ *     is guaranteed about output arrays unless stated.
+ */
+#ifndef SC_API_H
+#define SC_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define SC_OK                0  /* success */
+#define SC_NOT_CONVERGED     1  /* max_iter reached; outputs hold the last iterate */
+#define SC_ERR_INVALID      -1  /* NULL pointer, negative size, bad option */
+#define SC_ERR_CAPACITY     -2  /* more contacts than capacity; count holds the need */
+#define SC_ERR_NONFINITE    -3  /* NaN/Inf in an input or an iterate */
+#define SC_ERR_BOX          -4  /* periodic side < 2 x interaction range */
+#define SC_ERR_HIP          -5  /* a HIP runtime call failed */
+#define SC_ERR_WORKSPACE    -6  /* workspace too small or misaligned */
+
+/* ---------------------------------------------------------------- data */
+
+/* Rigid particles (section 3.1: each particle has a centre c and an
+ * orientation; a spherocylinder needs only its unit axis p). A sphere is a
+ * particle with half_len == 0 (its axis is ignored). */
+typedef struct sc_particles {
+    int32_t n;              /* number of particles, >= 0 */
+    int32_t reserved;
+    const double *pos;      /* [n][3] centres c */
+    const double *axis;     /* [n][3] unit axes p */
+    const double *radius;   /* [n] radius R > 0 (spheres: the radius; rods: D/2) */
+    const double *half_len; /* [n] half segment length h >= 0 (0 = sphere) */
+    const double *mob;      /* [n][4] dry mobility (a_par, a_perp, b_par, b_perp) > 0:
+                               U = a_par pp^T F + a_perp (I - pp^T) F,
+                               W = b_par pp^T T + b_perp (I - pp^T) T */
+} sc_particles;
+
+/* Simulation box. periodic != 0: minimum-image convention on [lo, lo+len)
+ * (positions may lie anywhere; they are wrapped for binning only).
+ * periodic == 0: free space; len only sizes the search grid (particles
+ * outside [lo, lo+len) are still found). */
+typedef struct sc_box {
+    double lo[3];
+    double len[3];
+    int32_t periodic;
+    int32_t reserved;
+} sc_box;
+
+/* Contacts: one constraint per close pair i < j (section 3.1), in canonical
+ * order (by i, then j). Caller-allocated; every per-contact array has
+ * `capacity` rows. Column l of D (Eq. Dmatdef) places (-n_l, -tau_i,l) on
+ * particle i and (+n_l, +tau_j,l) on particle j, where n_l is the unit
+ * normal from i's closest point to j's and tau_k,l = (x_k,l - c_k) x n_l is
+ * the moment arm of contact point x_k,l; then D_l^T U = dPhi_l/dt under
+ * rigid velocities U (Eq. Dtranspose). */
+typedef struct sc_contacts {
+    int32_t capacity;       /* rows allocated (>= 0) */
+    int32_t count;          /* OUT (host): number of contacts n_c */
+    int32_t *ci;            /* [capacity] particle i */
+    int32_t *cj;            /* [capacity] particle j (> i) */
+    double *phi;            /* [capacity] minimum separation Phi_l (<= delta) */
+    double *q;              /* [capacity] LCP vector q_l = Phi_l/dt + D_l^T U_nc */
+    double *frame;          /* [9][capacity] component-major rows:
+                               n_x n_y n_z, tau_i (x y z), tau_j (x y z) */
+    int32_t *i_ptr;         /* [n+1] contacts of particle k as i: [i_ptr[k], i_ptr[k+1]) */
+    int32_t *j_ptr;         /* [n+1] offsets into j_list for particle k as j */
+    int32_t *j_list;        /* [capacity] contact indices with cj == k, ascending */
+    int32_t n_parallel;     /* OUT (host): pairs resolved by the parallel-axes rule */
+    int32_t n_zero_dist;    /* OUT (host): pairs with coincident cores (n := +x) */
+    int32_t n_borderline;   /* OUT (host): pairs with |Phi - delta| < 1e-12 */
+    int32_t grid[3];        /* OUT (host): search cells per axis used */
+} sc_contacts;
+
+typedef struct sc_solve_opts {
+    double tol;             /* absolute tolerance on ||min(gamma, g)||_2 (> 0) */
+    int32_t max_iter;       /* j_max of Algorithm 1 (>= 0) */
+    int32_t bb;             /* step rule: 1 = BB1, 2 = BB2, 3 = BB1 odd / BB2 even */
+    int32_t warm_start;     /* 1: gamma holds gamma_0 on entry; 0: gamma_0 = 0 */
+    int32_t check_every;    /* iterations between host polls of convergence (0 = auto) */
+} sc_solve_opts;
+
+typedef struct sc_stats {
+    int32_t status;         /* SC_OK, SC_NOT_CONVERGED or SC_ERR_NONFINITE */
+    int32_t iters;          /* descent steps taken (j at exit) */
+    int32_t mvops;          /* products M x evaluated (section 6.2 accounting) */
+    int32_t n_active;       /* |{l : gamma_l > 0}| at exit */
+    double residual;        /* ||min(gamma, g)||_2 at exit */
+    double alpha;           /* last step size */
+    int32_t n_degenerate;   /* step sizes kept because a BB denominator was <= 0 */
+    int32_t reserved;
+    double loop_ms;         /* GPU time of the iteration loop (HIP events on `stream`) */
+} sc_stats;
+
+typedef struct sc_adjoint_opts {
+    double tol;             /* CG stopping tolerance, relative to ||b_A|| */
+    int32_t max_iter;       /* CG iteration cap */
+    int32_t reserved;
+} sc_adjoint_opts;
+
+/* ---------------------------------------------------------------- calls */
+
+/* Bytes of workspace any entry point needs for n particles and `capacity`
+ * contact rows. Pure host arithmetic. */
+size_t sc_workspace_bytes(int32_t n, int32_t capacity);
+
+/* u[k] = Mob_k f[k] for every particle (the dry block-diagonal mobility that
+ * stands in for the paper's mobility solve, section 2). f, u: [n][6].
+ * Does not synchronise. */
+int sc_apply_mobility(const sc_particles *p, const double *f, double *u,
+                      void *stream);
+
+/* Close-pair set A(C, delta) = {(i, j), i < j : Phi_ij <= delta} (section
+ * 3.2), its contact frames (Eq. Dmatdef, Eq. Dtranspose), the particle-major
+ * incidence (i_ptr, j_ptr, j_list) and q = Phi/dt + D^T u_nc (LCP LCPdef,
+ * scaled by 1/dt). Phi is the minimum separation of the two cores (a point
+ * for a sphere, the segment c +- h p for a spherocylinder) minus both radii.
+ * u_nc: [n][6] non-collisional velocities. Writes c->count; if it exceeds
+ * c->capacity returns SC_ERR_CAPACITY with c->count = the required rows and
+ * no contact written. SC_ERR_BOX if periodic and a side is below twice the
+ * interaction range 2 max(R + h) + delta. Synchronises `stream`. */
+int sc_build_contacts(const sc_particles *p, const sc_box *box, double delta,
+                      const double *u_nc, double dt, sc_contacts *c,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* y = M x = D^T Mob D x for x, y of c->count entries: one matrix-free
+ * product ("MVOP", LCP LCPdef and section 6.2). Does not synchronise. */
+int sc_mvop(const sc_particles *p, const sc_contacts *c, const double *x,
+            double *y, void *ws, size_t ws_bytes, void *stream);
+
+/* BBPGD, Algorithm 1 (section 3.3.1): from gamma_0 (zero, or the contents of
+ * gamma if opts->warm_start), g_0 = M gamma_0 + q, alpha_0 = g0^T g0 /
+ * g0^T M g0, then gamma_j = max(0, gamma_{j-1} - alpha_{j-1} g_{j-1}),
+ * g_j = M gamma_j + q, stopping when ||min(gamma_j, g_j)||_2 < tol (Eq.
+ * mmapnorm), with the BB1/BB2 step of Algorithm 1 step 15. A non-positive
+ * BB denominator keeps the previous step (g0^T M g0 <= 0 takes 1/max_l
+ * M_ll). gamma, g: [c->count], OUT: the last iterate and M gamma + q.
+ * f_c, u_c: [n][6] or NULL; OUT: contact forces D gamma and velocities
+ * Mob D gamma (section 3.2, procedure step 3). st: host pointer, OUT.
+ * Returns SC_OK, SC_NOT_CONVERGED (outputs hold the last iterate) or an
+ * error. Synchronises `stream`. */
+int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
+                 const sc_solve_opts *opts, double *gamma, double *g,
+                 double *f_c, double *u_c, sc_stats *st, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/* Implicit adjoint of a converged solve (not in the paper: it differentiates
+ * the LCP of LCP LCPdef on its active set A = {gamma > 0}, section 3.2).
+ * Given dL/dgamma [count] and dL/dF_c [n][6] (either may be NULL = zero),
+ * solves M_AA w_A = b_A with b = dL/dgamma + D^T dL/dF_c and w = 0 off A by
+ * conjugate gradients, then writes dL_dq = -w [count] and dL_dpos [n][3],
+ * the gradient with respect to the centres with orientations, radii,
+ * mobility and u_nc held fixed. gamma must be the solve's output for the
+ * same contacts. st (host, OUT): iters = CG iterations, residual = final
+ * relative CG residual, n_active = |A|. Synchronises `stream`. */
+int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
+                         const sc_contacts *c, const double *u_nc, double dt,
+                         const double *gamma, const double *dL_dgamma,
+                         const double *dL_df, double *dL_dq, double *dL_dpos,
+                         const sc_adjoint_opts *opts, sc_stats *st, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/* Static string describing a return code. */
+const char *sc_strerror(int code);
+
+/* Library ABI version (major * 100 + minor). */
+int sc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SC_API_H */

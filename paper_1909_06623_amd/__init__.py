@@ -1,0 +1,13 @@
+"""MI355X-native collision resolution for rigid-particle suspensions.
+
+Contact detection and Barzilai-Borwein projected gradient descent for the
+collision LCP of Yan et al. (arXiv:1909.06623, section 3), as hand-written HIP
+kernels for gfx950 behind a C ABI (include/sc_api.h). This package is the thin
+Python binding: PyTorch provides device memory and streams only.
+"""
+from ._abi import ScError, LIB_PATH  # noqa: F401
+from .api import (Box, Contacts, Particles, Workspace, apply_mobility,  # noqa: F401
+                  build_contacts, mvop, solve_lcp, solve_lcp_adjoint)
+
+__all__ = ["Box", "Contacts", "Particles", "Workspace", "apply_mobility",
+           "build_contacts", "mvop", "solve_lcp", "solve_lcp_adjoint", "ScError"]

@@ -1,0 +1,110 @@
+"""ctypes view of the C ABI declared in include/sc_api.h (structs, codes,
+function signatures). Loading fails loudly if the HIP library is not built:
+there is no fallback implementation."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libscgpu.so")
+
+SC_OK = 0
+SC_NOT_CONVERGED = 1
+SC_ERR_INVALID = -1
+SC_ERR_CAPACITY = -2
+SC_ERR_NONFINITE = -3
+SC_ERR_BOX = -4
+SC_ERR_HIP = -5
+SC_ERR_WORKSPACE = -6
+
+c_dp = ctypes.c_void_p  # device pointers travel as plain addresses
+
+
+class sc_particles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pos", c_dp), ("axis", c_dp), ("radius", c_dp),
+                ("half_len", c_dp), ("mob", c_dp)]
+
+
+class sc_box(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("len", ctypes.c_double * 3),
+                ("periodic", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class sc_contacts(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int32), ("count", ctypes.c_int32),
+                ("ci", c_dp), ("cj", c_dp), ("phi", c_dp), ("q", c_dp),
+                ("frame", c_dp), ("i_ptr", c_dp), ("j_ptr", c_dp),
+                ("j_list", c_dp), ("n_parallel", ctypes.c_int32),
+                ("n_zero_dist", ctypes.c_int32), ("n_borderline", ctypes.c_int32),
+                ("grid", ctypes.c_int32 * 3)]
+
+
+class sc_solve_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("bb", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("check_every", ctypes.c_int32)]
+
+
+class sc_stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("mvops", ctypes.c_int32), ("n_active", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("n_degenerate", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("loop_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class sc_adjoint_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+P = ctypes.POINTER
+SIGNATURES = {
+    "sc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "sc_apply_mobility": (ctypes.c_int, [P(sc_particles), c_dp, c_dp, c_dp]),
+    "sc_build_contacts": (ctypes.c_int, [P(sc_particles), P(sc_box), ctypes.c_double,
+                                         c_dp, ctypes.c_double, P(sc_contacts), c_dp,
+                                         ctypes.c_size_t, c_dp]),
+    "sc_mvop": (ctypes.c_int, [P(sc_particles), P(sc_contacts), c_dp, c_dp, c_dp,
+                               ctypes.c_size_t, c_dp]),
+    "sc_solve_lcp": (ctypes.c_int, [P(sc_particles), P(sc_contacts), P(sc_solve_opts),
+                                    c_dp, c_dp, c_dp, c_dp, P(sc_stats), c_dp,
+                                    ctypes.c_size_t, c_dp]),
+    "sc_solve_lcp_adjoint": (ctypes.c_int, [P(sc_particles), P(sc_box), P(sc_contacts),
+                                            c_dp, ctypes.c_double, c_dp, c_dp, c_dp,
+                                            c_dp, c_dp, P(sc_adjoint_opts), P(sc_stats),
+                                            c_dp, ctypes.c_size_t, c_dp]),
+    "sc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "sc_version": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"HIP library {LIB_PATH} is not built; run "
+                "`python -c 'import __graft_entry__ as g; g.build()'` first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class ScError(RuntimeError):
+    def __init__(self, fn, code):
+        self.code = code
+        msg = lib().sc_strerror(code).decode()
+        super().__init__(f"{fn} failed with code {code}: {msg}")

@@ -1,0 +1,277 @@
+"""Python binding of the C ABI with the same names: build_contacts,
+solve_lcp, solve_lcp_adjoint (plus apply_mobility and mvop).
+
+Only argument marshalling happens here: PyTorch supplies device memory and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels. Inputs are float64 tensors on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional
+
+import torch
+
+from . import _abi as A
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(fn, rc, allow=(A.SC_OK,)):
+    if rc not in allow:
+        raise A.ScError(fn, rc)
+    return rc
+
+
+def _dev(t, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    if not t.is_cuda:
+        t = t.cuda()
+    return t.to(dtype).contiguous()
+
+
+@dataclasses.dataclass
+class Particles:
+    """Rigid particles: centres, unit axes, radii, half segment lengths
+    (0 = sphere) and dry mobility coefficients (a_par, a_perp, b_par,
+    b_perp), all float64 on the GPU."""
+    pos: torch.Tensor
+    axis: torch.Tensor
+    radius: torch.Tensor
+    half_len: torch.Tensor
+    mob: torch.Tensor
+
+    @property
+    def n(self):
+        return int(self.pos.shape[0])
+
+    @classmethod
+    def from_arrays(cls, pos, axis, radius, half_len, mob):
+        return cls(_dev(pos), _dev(axis), _dev(radius), _dev(half_len), _dev(mob))
+
+    @classmethod
+    def from_suspension(cls, s):
+        return cls.from_arrays(s.pos, s.axis, s.radius, s.half_len, s.mob)
+
+    def c(self, pos=None):
+        pos = self.pos if pos is None else pos
+        return A.sc_particles(self.n, 0, pos.data_ptr(), self.axis.data_ptr(),
+                              self.radius.data_ptr(), self.half_len.data_ptr(),
+                              self.mob.data_ptr())
+
+
+@dataclasses.dataclass
+class Box:
+    len: tuple
+    lo: tuple = (0.0, 0.0, 0.0)
+    periodic: bool = True
+
+    def c(self):
+        b = A.sc_box()
+        for k in range(3):
+            b.lo[k] = float(self.lo[k])
+            b.len[k] = float(self.len[k])
+        b.periodic = 1 if self.periodic else 0
+        return b
+
+
+class Workspace:
+    """Caller-owned scratch for the library (one device byte buffer, grown
+    on demand, 256-byte aligned)."""
+
+    def __init__(self):
+        self.buf = None
+        self.base = 0
+        self.size = 0
+
+    def get(self, n, capacity):
+        need = int(A.lib().sc_workspace_bytes(int(n), int(capacity)))
+        if self.buf is None or self.size < need:
+            self.buf = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+            addr = self.buf.data_ptr()
+            self.base = (addr + 255) // 256 * 256
+            self.size = need + 256 - (self.base - addr)
+        return ctypes.c_void_p(self.base), ctypes.c_size_t(self.size)
+
+
+_default_ws = {}
+
+
+def default_workspace():
+    dev = torch.cuda.current_device()
+    if dev not in _default_ws:
+        _default_ws[dev] = Workspace()
+    return _default_ws[dev]
+
+
+class Contacts:
+    """Close pairs (i < j, canonical order) with their frames, q and the
+    particle-major incidence, in caller-allocated device arrays."""
+
+    def __init__(self, n, capacity):
+        self.n = int(n)
+        self.capacity = int(capacity)
+        cap = max(1, self.capacity)
+        dev = "cuda"
+        self.ci = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.cj = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.phi = torch.empty(cap, dtype=torch.float64, device=dev)
+        self.q = torch.empty(cap, dtype=torch.float64, device=dev)
+        self.frame = torch.empty((9, cap), dtype=torch.float64, device=dev)
+        self.i_ptr = torch.empty(self.n + 1, dtype=torch.int32, device=dev)
+        self.j_ptr = torch.empty(self.n + 1, dtype=torch.int32, device=dev)
+        self.j_list = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.count = 0
+        self.n_parallel = self.n_zero_dist = self.n_borderline = 0
+        self.grid = (0, 0, 0)
+
+    def c(self):
+        s = A.sc_contacts()
+        s.capacity = self.capacity
+        s.count = self.count
+        for name in ("ci", "cj", "phi", "q", "frame", "i_ptr", "j_ptr", "j_list"):
+            setattr(s, name, getattr(self, name).data_ptr())
+        s.n_parallel = self.n_parallel
+        s.n_zero_dist = self.n_zero_dist
+        s.n_borderline = self.n_borderline
+        return s
+
+    def _take(self, s):
+        self.count = int(s.count)
+        self.n_parallel = int(s.n_parallel)
+        self.n_zero_dist = int(s.n_zero_dist)
+        self.n_borderline = int(s.n_borderline)
+        self.grid = tuple(int(g) for g in s.grid)
+
+    # views of the first `count` rows
+    @property
+    def i(self):
+        return self.ci[: self.count]
+
+    @property
+    def j(self):
+        return self.cj[: self.count]
+
+    @property
+    def nrm(self):
+        return self.frame[0:3, : self.count].T
+
+    @property
+    def tau_i(self):
+        return self.frame[3:6, : self.count].T
+
+    @property
+    def tau_j(self):
+        return self.frame[6:9, : self.count].T
+
+
+def apply_mobility(particles: Particles, f: torch.Tensor) -> torch.Tensor:
+    """u = Mob f per particle (the dry block-diagonal mobility)."""
+    f = _dev(f)
+    u = torch.empty_like(f)
+    pc = particles.c()
+    _check("sc_apply_mobility",
+           A.lib().sc_apply_mobility(ctypes.byref(pc), _ptr(f), _ptr(u), _stream()))
+    return u
+
+
+def build_contacts(particles: Particles, box: Box, delta: float, u_nc: torch.Tensor,
+                   dt: float, capacity: Optional[int] = None,
+                   workspace: Optional[Workspace] = None) -> Contacts:
+    """Close-pair set, contact frames, incidence and q (grows the contact
+    arrays and retries when the capacity is too small)."""
+    u_nc = _dev(u_nc)
+    ws = workspace or default_workspace()
+    n = particles.n
+    cap = int(capacity) if capacity is not None else max(64, 8 * n)
+    pc, bc = particles.c(), box.c()
+    while True:
+        con = Contacts(n, cap)
+        cc = con.c()
+        wsp, wsn = ws.get(n, cap)
+        rc = A.lib().sc_build_contacts(ctypes.byref(pc), ctypes.byref(bc), float(delta),
+                                       _ptr(u_nc), float(dt), ctypes.byref(cc), wsp, wsn,
+                                       _stream())
+        con._take(cc)
+        if rc == A.SC_ERR_CAPACITY:
+            cap = int(cc.count)
+            continue
+        _check("sc_build_contacts", rc)
+        return con
+
+
+def mvop(particles: Particles, contacts: Contacts, x: torch.Tensor,
+         workspace: Optional[Workspace] = None) -> torch.Tensor:
+    """y = D^T Mob D x (one matrix-free product)."""
+    x = _dev(x)
+    y = torch.empty(max(1, contacts.count), dtype=torch.float64, device="cuda")
+    ws = workspace or default_workspace()
+    wsp, wsn = ws.get(particles.n, contacts.capacity)
+    pc, cc = particles.c(), contacts.c()
+    _check("sc_mvop", A.lib().sc_mvop(ctypes.byref(pc), ctypes.byref(cc), _ptr(x), _ptr(y),
+                                      wsp, wsn, _stream()))
+    return y[: contacts.count]
+
+
+def solve_lcp(particles: Particles, contacts: Contacts, tol: float = 1e-6,
+              max_iter: int = 100000, bb: int = 1, gamma0: Optional[torch.Tensor] = None,
+              want_fc: bool = False, check_every: int = 0,
+              workspace: Optional[Workspace] = None, raise_on_nonconverged=False):
+    """BBPGD (Algorithm 1). Returns (gamma, g, stats dict, f_c, u_c); f_c and
+    u_c are None unless want_fc."""
+    nc = contacts.count
+    gamma = torch.zeros(max(1, nc), dtype=torch.float64, device="cuda")
+    if gamma0 is not None and nc:
+        gamma[:nc] = _dev(gamma0)
+    g = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
+    f_c = u_c = None
+    if want_fc:
+        f_c = torch.empty((particles.n, 6), dtype=torch.float64, device="cuda")
+        u_c = torch.empty((particles.n, 6), dtype=torch.float64, device="cuda")
+    opts = A.sc_solve_opts(float(tol), int(max_iter), int(bb), 1 if gamma0 is not None else 0,
+                           int(check_every))
+    st = A.sc_stats()
+    ws = workspace or default_workspace()
+    wsp, wsn = ws.get(particles.n, contacts.capacity)
+    pc, cc = particles.c(), contacts.c()
+    rc = A.lib().sc_solve_lcp(ctypes.byref(pc), ctypes.byref(cc), ctypes.byref(opts),
+                              _ptr(gamma), _ptr(g), _ptr(f_c), _ptr(u_c), ctypes.byref(st),
+                              wsp, wsn, _stream())
+    allow = (A.SC_OK,) if raise_on_nonconverged else (A.SC_OK, A.SC_NOT_CONVERGED,
+                                                      A.SC_ERR_NONFINITE)
+    _check("sc_solve_lcp", rc, allow)
+    return gamma[:nc], g[:nc], st.as_dict(), f_c, u_c
+
+
+def solve_lcp_adjoint(particles: Particles, box: Box, contacts: Contacts,
+                      u_nc: torch.Tensor, dt: float, gamma: torch.Tensor,
+                      dL_dgamma: Optional[torch.Tensor] = None,
+                      dL_df: Optional[torch.Tensor] = None, tol: float = 1e-10,
+                      max_iter: int = 100000, workspace: Optional[Workspace] = None):
+    """Implicit adjoint of a converged solve: returns (dL_dq, dL_dpos, stats)."""
+    nc = contacts.count
+    u_nc = _dev(u_nc)
+    gamma = _dev(gamma)
+    dLg = None if dL_dgamma is None else _dev(dL_dgamma)
+    dLf = None if dL_df is None else _dev(dL_df)
+    dq = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
+    dpos = torch.empty((particles.n, 3), dtype=torch.float64, device="cuda")
+    opts = A.sc_adjoint_opts(float(tol), int(max_iter), 0)
+    st = A.sc_stats()
+    ws = workspace or default_workspace()
+    wsp, wsn = ws.get(particles.n, contacts.capacity)
+    pc, bc, cc = particles.c(), box.c(), contacts.c()
+    rc = A.lib().sc_solve_lcp_adjoint(ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(cc),
+                                      _ptr(u_nc), float(dt), _ptr(gamma), _ptr(dLg),
+                                      _ptr(dLf), _ptr(dq), _ptr(dpos), ctypes.byref(opts),
+                                      ctypes.byref(st), wsp, wsn, _stream())
+    _check("sc_solve_lcp_adjoint", rc, (A.SC_OK, A.SC_NOT_CONVERGED))
+    return dq[:nc], dpos, st.as_dict()

@@ -1,0 +1,28 @@
+// sc_api.hip -- library-level entry points: workspace sizing, error text,
+// version.
+#include "sc_common.hpp"
+
+extern "C" size_t sc_workspace_bytes(int32_t n, int32_t capacity) {
+    if (n < 0 || capacity < 0) return 0;
+    size_t a = sc::contacts_ws_bytes(n, capacity);
+    size_t b = sc::solve_ws_bytes(n, capacity);
+    size_t c = sc::adjoint_ws_bytes(n, capacity);
+    size_t m = a > b ? a : b;
+    return m > c ? m : c;
+}
+
+extern "C" const char *sc_strerror(int code) {
+    switch (code) {
+    case SC_OK: return "ok";
+    case SC_NOT_CONVERGED: return "not converged within max_iter (outputs hold the last iterate)";
+    case SC_ERR_INVALID: return "invalid argument";
+    case SC_ERR_CAPACITY: return "contact capacity too small (count holds the required rows)";
+    case SC_ERR_NONFINITE: return "non-finite value in an input or an iterate";
+    case SC_ERR_BOX: return "periodic box side below twice the interaction range";
+    case SC_ERR_HIP: return "HIP runtime error";
+    case SC_ERR_WORKSPACE: return "workspace too small or not 256-byte aligned";
+    default: return "unknown status code";
+    }
+}
+
+extern "C" int sc_version(void) { return 100; }

@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, every
+function declared in include/sc_api.h is exported, and argument validation
+rejects bad calls before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sc_api.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for fn in ("sc_build_contacts", "sc_solve_lcp", "sc_solve_lcp_adjoint",
+               "sc_workspace_bytes", "sc_strerror"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1909_06623_amd import _abi as A
+    L = A.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert set(_declared()) == set(A.SIGNATURES)
+
+
+def test_strerror_and_version():
+    from paper_1909_06623_amd import _abi as A
+    L = A.lib()
+    assert L.sc_version() >= 100
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert L.sc_strerror(code) != b"unknown status code"
+    assert L.sc_strerror(42) == b"unknown status code"
+
+
+def test_workspace_bytes_monotone():
+    from paper_1909_06623_amd import _abi as A
+    L = A.lib()
+    a = L.sc_workspace_bytes(1000, 5000)
+    b = L.sc_workspace_bytes(2000, 5000)
+    c = L.sc_workspace_bytes(2000, 10000)
+    assert 0 < a < b < c
+    assert L.sc_workspace_bytes(-1, 10) == 0
+
+
+def test_invalid_arguments_rejected_without_device_work():
+    from paper_1909_06623_amd import _abi as A
+    L = A.lib()
+    assert L.sc_build_contacts(None, None, 0.1, None, 1e-3, None, None, 0, None) == A.SC_ERR_INVALID
+    p = A.sc_particles(-5, 0, 0, 0, 0, 0, 0)
+    assert L.sc_apply_mobility(ctypes.byref(p), None, None, None) == A.SC_ERR_INVALID
+    p0 = A.sc_particles(0, 0, 0, 0, 0, 0, 0)
+    assert L.sc_apply_mobility(ctypes.byref(p0), None, None, None) == A.SC_OK
+    c = A.sc_contacts()
+    c.capacity, c.count = 5, 10  # count beyond capacity
+    opts = A.sc_solve_opts(1e-6, 100, 1, 0, 0)
+    st = A.sc_stats()
+    assert L.sc_solve_lcp(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(opts), None, None,
+                          None, None, ctypes.byref(st), None, 0, None) == A.SC_ERR_INVALID
+    c.count = 0
+    bad = A.sc_solve_opts(-1.0, 100, 1, 0, 0)
+    assert L.sc_solve_lcp(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(bad), None, None,
+                          None, None, ctypes.byref(st), None, 0, None) == A.SC_ERR_INVALID
+    bad = A.sc_solve_opts(1e-6, 100, 7, 0, 0)
+    assert L.sc_solve_lcp(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(bad), None, None,
+                          None, None, ctypes.byref(st), None, 0, None) == A.SC_ERR_INVALID
+    box = A.sc_box()
+    assert L.sc_build_contacts(ctypes.byref(p0), ctypes.byref(box), 0.1, None, 1e-3,
+                               ctypes.byref(c), None, 0, None) == A.SC_ERR_INVALID
+
+
+def test_product_path_has_no_cpu_fallback():
+    """The binding raises when the HIP library is missing instead of
+    computing anything on the CPU, and never imports the oracle."""
+    import paper_1909_06623_amd._abi as A
+    import paper_1909_06623_amd.api as api
+    src = open(api.__file__).read() + open(A.__file__).read()
+    assert "oracle" not in src.replace("oracle.", "")
+    saved = A._lib, A.LIB_PATH
+    try:
+        A._lib = None
+        A.LIB_PATH = "/nonexistent/libscgpu.so"
+        with pytest.raises(RuntimeError):
+            A.lib()
+    finally:
+        A._lib, A.LIB_PATH = saved

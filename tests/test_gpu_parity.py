@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars:
+* contact lists: bit-exact set and order equality (index work); frames, Phi
+  and q equal to rounding (the two sides evaluate the same closed forms in
+  possibly different operation orders);
+* one product M x and a fixed number of BBPGD steps: relative 1e-12 / 1e-9;
+* converged solves: the tolerance of the workload (||min(gamma, g)|| < tol),
+  relative gamma error <= 1e-6 where M is SPD (checked at a tight tolerance
+  when the SPD error bound of Eq. abserrcqp at the workload tolerance is
+  looser than that), and the unique quantities g and D gamma where it is
+  only semidefinite (randomly overlapping spheres);
+* bitwise reproducibility run to run.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _sc():
+    import paper_1909_06623_amd as sc
+    return sc
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _setup_gpu(s, capacity=None):
+    sc = _sc()
+    P = sc.Particles.from_suspension(s)
+    box = sc.Box(tuple(s.box), lo=tuple(s.lo), periodic=bool(s.periodic))
+    u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, capacity=capacity)
+    return P, box, u_nc, con
+
+
+def _contacts_equal(con, c):
+    assert con.count == c.nc
+    assert con.n_borderline == 0
+    np.testing.assert_array_equal(con.i.cpu().numpy(), c.i)
+    np.testing.assert_array_equal(con.j.cpu().numpy(), c.j)
+    phi = con.phi[: con.count].cpu().numpy()
+    np.testing.assert_allclose(phi, c.phi, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(con.nrm.cpu().numpy(), c.nrm, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(con.tau_i.cpu().numpy(), c.tau_i, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(con.tau_j.cpu().numpy(), c.tau_j, rtol=0, atol=1e-12)
+
+
+CASES = {
+    "spheres1000": lambda: W.workload(1),
+    "rods5000": lambda: W.rods(5000, seed=W.SEED_BASE + 2),
+    "mixed": lambda: W.rods_and_spheres(3000, 600, seed=W.SEED_BASE + 3),
+    "rods_small_box": lambda: W.rods(600, seed=17, min_side=2.2),
+    "spheres_dense": lambda: W.spheres(700, 0.4, seed=18),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_contacts_and_q(name):
+    s = CASES[name]()
+    _say(f"contacts {name} N={s.n}")
+    P, box, u_nc, con = _setup_gpu(s)
+    c, u_orc, q_orc = O.setup(s)
+    np.testing.assert_allclose(u_nc.cpu().numpy(), u_orc, rtol=1e-14, atol=1e-15)
+    _contacts_equal(con, c)
+    q = con.q[: con.count].cpu().numpy()
+    np.testing.assert_allclose(q, q_orc, rtol=1e-12, atol=1e-9)
+    # incidence: j-side lists are the contacts with cj == k, ascending
+    jp = con.j_ptr.cpu().numpy()
+    jl = con.j_list[: con.count].cpu().numpy()
+    order = np.argsort(c.j, kind="stable")
+    np.testing.assert_array_equal(jl, order)
+    np.testing.assert_array_equal(np.diff(jp), np.bincount(c.j, minlength=s.n))
+    ip = con.i_ptr.cpu().numpy()
+    np.testing.assert_array_equal(np.diff(ip), np.bincount(c.i, minlength=s.n))
+
+
+def test_non_periodic_contacts():
+    s = W.rods_and_spheres(1500, 300, seed=23)
+    s.periodic = 0
+    s.pos = s.pos * 1.2 - 1.0
+    _say("contacts non-periodic")
+    P, box, u_nc, con = _setup_gpu(s)
+    c, u_orc, q_orc = O.setup(s)
+    _contacts_equal(con, c)
+
+
+@pytest.mark.parametrize("name", ["spheres1000", "mixed"])
+def test_mvop(name):
+    s = CASES[name]()
+    _say(f"mvop {name}")
+    sc = _sc()
+    P, box, u_nc, con = _setup_gpu(s)
+    c, u_orc, q_orc = O.setup(s)
+    x = np.random.default_rng(5).standard_normal(c.nc)
+    y = sc.mvop(P, con, torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = O.mvop(s, c, x)
+    np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("bb", [1, 2, 3])
+def test_fixed_steps_match(bb):
+    s = W.rods(3000, seed=31)
+    _say(f"fixed steps bb={bb}")
+    sc = _sc()
+    P, box, u_nc, con = _setup_gpu(s)
+    c, u_orc, q_orc = O.setup(s)
+    gam, g, st, _, _ = sc.solve_lcp(P, con, tol=s.tol, max_iter=6, bb=bb)
+    go, gg, sto = O.bbpgd(s, c, q_orc, max_iter=6, bb=bb)
+    assert st["status"] == 1 and sto.status == 1
+    assert (st["iters"], st["mvops"]) == (6, 8)
+    np.testing.assert_allclose(gam.cpu().numpy(), go, rtol=1e-9, atol=1e-9 * np.abs(go).max())
+    np.testing.assert_allclose(g.cpu().numpy(), gg, rtol=1e-9, atol=1e-9 * np.abs(gg).max())
+    assert st["alpha"] == pytest.approx(sto.alpha, rel=1e-9)
+
+
+def _kkt(gam, g, tol):
+    assert np.all(gam >= 0.0)
+    assert np.linalg.norm(np.minimum(gam, g)) < tol
+    assert np.all(g >= -tol)
+    assert np.all(np.abs(gam * g) <= tol * np.maximum(1.0, np.maximum(gam, np.abs(g))))
+
+
+@pytest.mark.parametrize("name", ["rods5000", "mixed", "rods_small_box"])
+def test_converged_solve_spd(name):
+    s = CASES[name]()
+    _say(f"solve {name}")
+    sc = _sc()
+    P, box, u_nc, con = _setup_gpu(s)
+    c, u_orc, q_orc = O.setup(s)
+    gam, g, st, f_c, u_c = sc.solve_lcp(P, con, tol=s.tol, want_fc=True)
+    assert st["status"] == 0
+    gam, g = gam.cpu().numpy(), g.cpu().numpy()
+    _kkt(gam, g, s.tol)
+    assert st["residual"] == pytest.approx(np.linalg.norm(np.minimum(gam, g)), rel=1e-6)
+    # outputs are consistent: g = M gamma + q, f_c = D gamma, u_c = Mob f_c
+    np.testing.assert_allclose(g, O.mvop(s, c, gam) + q_orc, rtol=0,
+                               atol=1e-9 * np.abs(q_orc).max())
+    F = O.D_apply(s.n, c, gam)
+    np.testing.assert_allclose(f_c.cpu().numpy(), F, rtol=0, atol=1e-11 * np.abs(F).max())
+    np.testing.assert_allclose(u_c.cpu().numpy(), O.mobility(s.axis, s.mob, F), rtol=0,
+                               atol=1e-11 * np.abs(F).max())
+    # against the oracle at the same tolerance, within the SPD bound ...
+    go, gg, sto = O.bbpgd(s, c, q_orc)
+    assert sto.status == 0
+    rel = np.linalg.norm(gam - go) / np.linalg.norm(go)
+    # ... and at a tight tolerance, where the bound is far below 1e-6
+    gt, _, stt, _, _ = sc.solve_lcp(P, con, tol=1e-9)
+    got, _, stot = O.bbpgd(s, c, q_orc, tol=1e-9)
+    assert stt["status"] == 0 and stot.status == 0
+    rel_t = np.linalg.norm(gt.cpu().numpy() - got) / np.linalg.norm(got)
+    print(f"[result] {name}: iters gpu {st['iters']} oracle {sto.iters}; rel err "
+          f"tol1e-6 {rel:.2e} tol1e-9 {rel_t:.2e}", flush=True)
+    assert rel_t <= 1e-6
+    assert rel <= 1e-4
+
+
+def test_converged_solve_semidefinite_spheres():
+    s = W.workload(1)
+    _say("solve spheres1000 (semidefinite M)")
+    sc = _sc()
+    P, box, u_nc, con = _setup_gpu(s)
+    c, u_orc, q_orc = O.setup(s)
+    gam, g, st, f_c, u_c = sc.solve_lcp(P, con, tol=1e-9, want_fc=True)
+    go, gg, sto = O.bbpgd(s, c, q_orc, tol=1e-9)
+    assert st["status"] == 0 and sto.status == 0
+    gam, g = gam.cpu().numpy(), g.cpu().numpy()
+    _kkt(gam, g, 1e-9)
+    np.testing.assert_allclose(g, gg, atol=1e-7)
+    F = O.D_apply(s.n, c, go)
+    np.testing.assert_allclose(f_c.cpu().numpy(), F, atol=1e-7 * np.abs(F).max())
+
+
+def test_bitwise_reproducible():
+    s = W.rods(4000, seed=44)
+    _say("reproducibility")
+    sc = _sc()
+    P, box, u_nc, con = _setup_gpu(s)
+    a = sc.solve_lcp(P, con, tol=s.tol)
+    b = sc.solve_lcp(P, con, tol=s.tol)
+    assert a[2]["iters"] == b[2]["iters"]
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_edge_cases():
+    sc = _sc()
+    import paper_1909_06623_amd._abi as A
+    _say("edge: empty system")
+    s = W.spheres(10, 0.3, seed=1)
+    e = s.subset(np.arange(0))
+    P = sc.Particles.from_suspension(e)
+    box = sc.Box(tuple(s.box))
+    con = sc.build_contacts(P, box, s.delta, torch.zeros((0, 6), dtype=torch.float64), s.dt)
+    assert con.count == 0
+    _say("edge: dilute, no pairs")
+    s = W.spheres(27, 0.3, seed=2)
+    g = np.stack(np.meshgrid(*[np.arange(3)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    s.pos = 4.0 * g + 1.0          # lattice spacing 4 > 2R + delta
+    s.box = np.full(3, 12.0)
+    P, box, u_nc, con = _setup_gpu(s)
+    assert con.count == 0
+    gam, g, st, f_c, u_c = sc.solve_lcp(P, con, want_fc=True)
+    assert (st["status"], st["iters"], st["mvops"]) == (0, 0, 1)
+    assert torch.all(f_c == 0)
+    _say("edge: separating pairs only")
+    s = W.workload(1)
+    P, box, u_nc, con = _setup_gpu(s)
+    con.q[: con.count] = torch.abs(con.q[: con.count]) + 1.0
+    gam, g, st, _, _ = sc.solve_lcp(P, con)
+    assert (st["iters"], st["mvops"]) == (0, 1) and torch.all(gam == 0)
+    _say("edge: max_iter 0 and warm start")
+    s = W.rods(2000, seed=3)
+    P, box, u_nc, con = _setup_gpu(s)
+    gam, g, st, _, _ = sc.solve_lcp(P, con, max_iter=0)
+    assert (st["status"], st["iters"], st["mvops"]) == (1, 0, 2)
+    gam, g, st, _, _ = sc.solve_lcp(P, con, tol=1e-8)
+    assert st["status"] == 0
+    gam2, g2, st2, _, _ = sc.solve_lcp(P, con, tol=1e-6, gamma0=gam)
+    assert (st2["iters"], st2["mvops"]) == (0, 1)
+    _say("edge: capacity too small (raw ABI)")
+    con_small = sc.Contacts(P.n, 10)
+    cc = con_small.c()
+    pc, bc = P.c(), box.c()
+    ws = sc.Workspace()
+    wsp, wsn = ws.get(P.n, 10)
+    import ctypes
+    rc = A.lib().sc_build_contacts(ctypes.byref(pc), ctypes.byref(bc), s.delta,
+                                   ctypes.c_void_p(u_nc.data_ptr()), s.dt, ctypes.byref(cc),
+                                   wsp, wsn, ctypes.c_void_p(0))
+    assert rc == A.SC_ERR_CAPACITY and cc.count == con.count
+    _say("edge: box too small")
+    s2 = W.rods(200, seed=4, min_side=1.5)
+    P2 = sc.Particles.from_suspension(s2)
+    with pytest.raises(sc.ScError) as ei:
+        sc.build_contacts(P2, sc.Box(tuple(s2.box)), s2.delta,
+                          torch.zeros((s2.n, 6), dtype=torch.float64), s2.dt)
+    assert ei.value.code == A.SC_ERR_BOX
+    _say("edge: NaN in u_nc")
+    bad = u_nc.clone()
+    bad[5, 0] = float("nan")
+    with pytest.raises(sc.ScError) as ei:
+        sc.build_contacts(P, box, s.delta, bad, s.dt)
+    assert ei.value.code == A.SC_ERR_NONFINITE
+    _say("edge: non-unit rod axis")
+    P3 = sc.Particles(P.pos, P.axis * 1.01, P.radius, P.half_len, P.mob)
+    with pytest.raises(sc.ScError) as ei:
+        sc.build_contacts(P3, box, s.delta, u_nc, s.dt)
+    assert ei.value.code == A.SC_ERR_NONFINITE
+    _say("edge: NaN in q reaches the solver")
+    con.q[3] = float("nan")
+    gam, g, st, _, _ = sc.solve_lcp(P, con)
+    assert st["status"] == A.SC_ERR_NONFINITE
