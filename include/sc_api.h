@@ -46,6 +46,7 @@ extern "C" {
 #define SC_ERR_BOX          -4  /* periodic side < 2 x interaction range */
 #define SC_ERR_HIP          -5  /* a HIP runtime call failed */
 #define SC_ERR_WORKSPACE    -6  /* workspace too small or misaligned */
+#define SC_ERR_TIMEOUT      -7  /* a grid barrier of a persistent kernel timed out */
 
 /* ---------------------------------------------------------------- data */
 
@@ -75,25 +76,34 @@ typedef struct sc_box {
     int32_t reserved;
 } sc_box;
 
-/* Contacts: one constraint per close pair i < j (section 3.1), in canonical
- * order (by i, then j). Caller-allocated; every per-contact array has
- * `capacity` rows. Column l of D (Eq. Dmatdef) places (-n_l, -tau_i,l) on
- * particle i and (+n_l, +tau_j,l) on particle j, where n_l is the unit
- * normal from i's closest point to j's and tau_k,l = (x_k,l - c_k) x n_l is
- * the moment arm of contact point x_k,l; then D_l^T U = dPhi_l/dt under
- * rigid velocities U (Eq. Dtranspose). */
+/* Contacts: one constraint per close pair i < j (section 3.1).
+ * Caller-allocated; every per-contact array has `capacity` rows. Column l of
+ * D (Eq. Dmatdef) places (-n_l, -tau_i,l) on particle ci and (+n_l, +tau_j,l)
+ * on particle cj, where n_l is the unit normal from ci's closest core point to
+ * cj's and tau_k,l = (x_k,l - c_k) x n_l is the moment arm of contact point
+ * x_k,l; then D_l^T U = dPhi_l/dt under rigid velocities U (Eq. Dtranspose).
+ *
+ * Order ("solver order"): particles are ranked by search cell (row-major over
+ * the grid reported in `grid`) and, within a cell, by index; contacts are
+ * grouped by the rank of their lower-ranked particle, partners by increasing
+ * rank. The order is a deterministic function of the inputs, keeps every
+ * gather of the solve local, and is the order of gamma and g.
+ *
+ * `plan` is a caller-allocated device buffer of at least
+ * sc_plan_bytes(n, capacity) bytes (256-byte aligned) in which
+ * sc_build_contacts stores the solver layout (ranking, incidence lists and
+ * signed column entries) read by sc_solve_lcp, sc_mvop and
+ * sc_solve_lcp_adjoint; its contents are private to the library. */
 typedef struct sc_contacts {
     int32_t capacity;       /* rows allocated (>= 0) */
     int32_t count;          /* OUT (host): number of contacts n_c */
-    int32_t *ci;            /* [capacity] particle i */
+    int32_t *ci;            /* [capacity] particle i (caller index) */
     int32_t *cj;            /* [capacity] particle j (> i) */
     double *phi;            /* [capacity] minimum separation Phi_l (<= delta) */
     double *q;              /* [capacity] LCP vector q_l = Phi_l/dt + D_l^T U_nc */
-    double *frame;          /* [9][capacity] component-major rows:
-                               n_x n_y n_z, tau_i (x y z), tau_j (x y z) */
-    int32_t *i_ptr;         /* [n+1] contacts of particle k as i: [i_ptr[k], i_ptr[k+1]) */
-    int32_t *j_ptr;         /* [n+1] offsets into j_list for particle k as j */
-    int32_t *j_list;        /* [capacity] contact indices with cj == k, ascending */
+    double *frame;          /* [capacity][9]: n (x y z), tau_i (x y z), tau_j (x y z) */
+    void *plan;             /* [plan_bytes] device, solver layout (private) */
+    size_t plan_bytes;
     int32_t n_parallel;     /* OUT (host): pairs resolved by the parallel-axes rule */
     int32_t n_zero_dist;    /* OUT (host): pairs with coincident cores (n := +x) */
     int32_t n_borderline;   /* OUT (host): pairs with |Phi - delta| < 1e-12 */
@@ -105,7 +115,12 @@ typedef struct sc_solve_opts {
     int32_t max_iter;       /* j_max of Algorithm 1 (>= 0) */
     int32_t bb;             /* step rule: 1 = BB1, 2 = BB2, 3 = BB1 odd / BB2 even */
     int32_t warm_start;     /* 1: gamma holds gamma_0 on entry; 0: gamma_0 = 0 */
-    int32_t check_every;    /* iterations between host polls of convergence (0 = auto) */
+    int32_t lanes_per_particle; /* 0 (default 4), 1, 2, 4 or 8: lanes sharing a particle's
+                                   incidence list in the gather pass */
+    int32_t grid;           /* workgroups of the persistent kernel (0 = one per CU;
+                               clamped to what is co-resident) */
+    int32_t block;          /* threads per workgroup: 0 (default 1024), 256 or 1024 */
+    int32_t reserved;
 } sc_solve_opts;
 
 typedef struct sc_stats {
@@ -116,14 +131,18 @@ typedef struct sc_stats {
     double residual;        /* ||min(gamma, g)||_2 at exit */
     double alpha;           /* last step size */
     int32_t n_degenerate;   /* step sizes kept because a BB denominator was <= 0 */
-    int32_t reserved;
-    double loop_ms;         /* GPU time of the iteration loop (HIP events on `stream`) */
+    int32_t grid;           /* workgroups of the persistent kernel used */
+    double kernel_ms;       /* GPU time of the persistent kernel (HIP events on `stream`) */
+    int32_t lanes_per_particle; /* gather lanes per particle used */
+    int32_t block;          /* threads per workgroup used */
 } sc_stats;
 
 typedef struct sc_adjoint_opts {
     double tol;             /* CG stopping tolerance, relative to ||b_A|| */
     int32_t max_iter;       /* CG iteration cap */
-    int32_t reserved;
+    int32_t lanes_per_particle; /* as in sc_solve_opts */
+    int32_t grid;           /* as in sc_solve_opts */
+    int32_t block;          /* as in sc_solve_opts */
 } sc_adjoint_opts;
 
 /* ---------------------------------------------------------------- calls */
@@ -132,6 +151,10 @@ typedef struct sc_adjoint_opts {
  * contact rows. Pure host arithmetic. */
 size_t sc_workspace_bytes(int32_t n, int32_t capacity);
 
+/* Bytes of the plan buffer of sc_contacts for n particles and `capacity`
+ * contact rows. Pure host arithmetic. */
+size_t sc_plan_bytes(int32_t n, int32_t capacity);
+
 /* u[k] = Mob_k f[k] for every particle (the dry block-diagonal mobility that
  * stands in for the paper's mobility solve, section 2). f, u: [n][6].
  * Does not synchronise. */
@@ -139,10 +162,10 @@ int sc_apply_mobility(const sc_particles *p, const double *f, double *u,
                       void *stream);
 
 /* Close-pair set A(C, delta) = {(i, j), i < j : Phi_ij <= delta} (section
- * 3.2), its contact frames (Eq. Dmatdef, Eq. Dtranspose), the particle-major
- * incidence (i_ptr, j_ptr, j_list) and q = Phi/dt + D^T u_nc (LCP LCPdef,
- * scaled by 1/dt). Phi is the minimum separation of the two cores (a point
- * for a sphere, the segment c +- h p for a spherocylinder) minus both radii.
+ * 3.2), its contact frames (Eq. Dmatdef, Eq. Dtranspose), the solver layout
+ * in c->plan and q = Phi/dt + D^T u_nc (LCP LCPdef, scaled by 1/dt). Phi is
+ * the minimum separation of the two cores (a point for a sphere, the segment
+ * c +- h p for a spherocylinder) minus both radii.
  * u_nc: [n][6] non-collisional velocities. Writes c->count; if it exceeds
  * c->capacity returns SC_ERR_CAPACITY with c->count = the required rows and
  * no contact written. SC_ERR_BOX if periodic and a side is below twice the
@@ -156,8 +179,8 @@ int sc_build_contacts(const sc_particles *p, const sc_box *box, double delta,
 int sc_mvop(const sc_particles *p, const sc_contacts *c, const double *x,
             double *y, void *ws, size_t ws_bytes, void *stream);
 
-/* BBPGD, Algorithm 1 (section 3.3.1): from gamma_0 (zero, or the contents of
- * gamma if opts->warm_start), g_0 = M gamma_0 + q, alpha_0 = g0^T g0 /
+/* BBPGD, Algorithm 1 (section 3.3.1), as one persistent cooperative launch:
+ * from gamma_0 (zero, or the contents of gamma if opts->warm_start), g_0 = M gamma_0 + q, alpha_0 = g0^T g0 /
  * g0^T M g0, then gamma_j = max(0, gamma_{j-1} - alpha_{j-1} g_{j-1}),
  * g_j = M gamma_j + q, stopping when ||min(gamma_j, g_j)||_2 < tol (Eq.
  * mmapnorm), with the BB1/BB2 step of Algorithm 1 step 15. A non-positive
@@ -166,7 +189,8 @@ int sc_mvop(const sc_particles *p, const sc_contacts *c, const double *x,
  * f_c, u_c: [n][6] or NULL; OUT: contact forces D gamma and velocities
  * Mob D gamma (section 3.2, procedure step 3). st: host pointer, OUT.
  * Returns SC_OK, SC_NOT_CONVERGED (outputs hold the last iterate) or an
- * error. Synchronises `stream`. */
+ * error. Iterates are bitwise reproducible for a given launch shape (grid,
+ * lanes_per_particle). Synchronises `stream`. */
 int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
                  const sc_solve_opts *opts, double *gamma, double *g,
                  double *f_c, double *u_c, sc_stats *st, void *ws,

@@ -17,6 +17,7 @@ SC_ERR_NONFINITE = -3
 SC_ERR_BOX = -4
 SC_ERR_HIP = -5
 SC_ERR_WORKSPACE = -6
+SC_ERR_TIMEOUT = -7
 
 c_dp = ctypes.c_void_p  # device pointers travel as plain addresses
 
@@ -35,24 +36,25 @@ class sc_box(ctypes.Structure):
 class sc_contacts(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int32), ("count", ctypes.c_int32),
                 ("ci", c_dp), ("cj", c_dp), ("phi", c_dp), ("q", c_dp),
-                ("frame", c_dp), ("i_ptr", c_dp), ("j_ptr", c_dp),
-                ("j_list", c_dp), ("n_parallel", ctypes.c_int32),
-                ("n_zero_dist", ctypes.c_int32), ("n_borderline", ctypes.c_int32),
-                ("grid", ctypes.c_int32 * 3)]
+                ("frame", c_dp), ("plan", c_dp), ("plan_bytes", ctypes.c_size_t),
+                ("n_parallel", ctypes.c_int32), ("n_zero_dist", ctypes.c_int32),
+                ("n_borderline", ctypes.c_int32), ("grid", ctypes.c_int32 * 3)]
 
 
 class sc_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("bb", ctypes.c_int32), ("warm_start", ctypes.c_int32),
-                ("check_every", ctypes.c_int32)]
+                ("lanes_per_particle", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class sc_stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("mvops", ctypes.c_int32), ("n_active", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("n_degenerate", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("loop_ms", ctypes.c_double)]
+                ("n_degenerate", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double), ("lanes_per_particle", ctypes.c_int32),
+                ("block", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -60,12 +62,14 @@ class sc_stats(ctypes.Structure):
 
 class sc_adjoint_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("lanes_per_particle", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("block", ctypes.c_int32)]
 
 
 P = ctypes.POINTER
 SIGNATURES = {
     "sc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "sc_plan_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "sc_apply_mobility": (ctypes.c_int, [P(sc_particles), c_dp, c_dp, c_dp]),
     "sc_build_contacts": (ctypes.c_int, [P(sc_particles), P(sc_box), ctypes.c_double,
                                          c_dp, ctypes.c_double, P(sc_contacts), c_dp,

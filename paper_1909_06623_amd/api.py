@@ -113,8 +113,8 @@ def default_workspace():
 
 
 class Contacts:
-    """Close pairs (i < j, canonical order) with their frames, q and the
-    particle-major incidence, in caller-allocated device arrays."""
+    """Close pairs (i < j, solver order) with their frames and q, plus the
+    library's private plan buffer, in caller-allocated device memory."""
 
     def __init__(self, n, capacity):
         self.n = int(n)
@@ -125,10 +125,12 @@ class Contacts:
         self.cj = torch.empty(cap, dtype=torch.int32, device=dev)
         self.phi = torch.empty(cap, dtype=torch.float64, device=dev)
         self.q = torch.empty(cap, dtype=torch.float64, device=dev)
-        self.frame = torch.empty((9, cap), dtype=torch.float64, device=dev)
-        self.i_ptr = torch.empty(self.n + 1, dtype=torch.int32, device=dev)
-        self.j_ptr = torch.empty(self.n + 1, dtype=torch.int32, device=dev)
-        self.j_list = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.frame = torch.empty((cap, 9), dtype=torch.float64, device=dev)
+        pb = int(A.lib().sc_plan_bytes(self.n, self.capacity))
+        self._plan = torch.empty(pb + 256, dtype=torch.uint8, device=dev)
+        addr = self._plan.data_ptr()
+        self.plan_ptr = (addr + 255) // 256 * 256
+        self.plan_bytes = pb + 256 - (self.plan_ptr - addr)
         self.count = 0
         self.n_parallel = self.n_zero_dist = self.n_borderline = 0
         self.grid = (0, 0, 0)
@@ -137,8 +139,10 @@ class Contacts:
         s = A.sc_contacts()
         s.capacity = self.capacity
         s.count = self.count
-        for name in ("ci", "cj", "phi", "q", "frame", "i_ptr", "j_ptr", "j_list"):
+        for name in ("ci", "cj", "phi", "q", "frame"):
             setattr(s, name, getattr(self, name).data_ptr())
+        s.plan = self.plan_ptr
+        s.plan_bytes = self.plan_bytes
         s.n_parallel = self.n_parallel
         s.n_zero_dist = self.n_zero_dist
         s.n_borderline = self.n_borderline
@@ -162,15 +166,21 @@ class Contacts:
 
     @property
     def nrm(self):
-        return self.frame[0:3, : self.count].T
+        return self.frame[: self.count, 0:3]
 
     @property
     def tau_i(self):
-        return self.frame[3:6, : self.count].T
+        return self.frame[: self.count, 3:6]
 
     @property
     def tau_j(self):
-        return self.frame[6:9, : self.count].T
+        return self.frame[: self.count, 6:9]
+
+    def canonical_order(self):
+        """Permutation that sorts the contacts by (ci, cj) (the order of a
+        plain enumeration of pairs i < j)."""
+        key = self.i.to(torch.int64) * (1 << 32) + self.j.to(torch.int64)
+        return torch.argsort(key)
 
 
 def apply_mobility(particles: Particles, f: torch.Tensor) -> torch.Tensor:
@@ -223,8 +233,9 @@ def mvop(particles: Particles, contacts: Contacts, x: torch.Tensor,
 
 def solve_lcp(particles: Particles, contacts: Contacts, tol: float = 1e-6,
               max_iter: int = 100000, bb: int = 1, gamma0: Optional[torch.Tensor] = None,
-              want_fc: bool = False, check_every: int = 0,
-              workspace: Optional[Workspace] = None, raise_on_nonconverged=False):
+              want_fc: bool = False, lanes_per_particle: int = 0, grid: int = 0,
+              block: int = 0, workspace: Optional[Workspace] = None,
+              raise_on_nonconverged=False):
     """BBPGD (Algorithm 1). Returns (gamma, g, stats dict, f_c, u_c); f_c and
     u_c are None unless want_fc."""
     nc = contacts.count
@@ -237,7 +248,7 @@ def solve_lcp(particles: Particles, contacts: Contacts, tol: float = 1e-6,
         f_c = torch.empty((particles.n, 6), dtype=torch.float64, device="cuda")
         u_c = torch.empty((particles.n, 6), dtype=torch.float64, device="cuda")
     opts = A.sc_solve_opts(float(tol), int(max_iter), int(bb), 1 if gamma0 is not None else 0,
-                           int(check_every))
+                           int(lanes_per_particle), int(grid), int(block), 0)
     st = A.sc_stats()
     ws = workspace or default_workspace()
     wsp, wsn = ws.get(particles.n, contacts.capacity)
@@ -246,7 +257,7 @@ def solve_lcp(particles: Particles, contacts: Contacts, tol: float = 1e-6,
                               _ptr(gamma), _ptr(g), _ptr(f_c), _ptr(u_c), ctypes.byref(st),
                               wsp, wsn, _stream())
     allow = (A.SC_OK,) if raise_on_nonconverged else (A.SC_OK, A.SC_NOT_CONVERGED,
-                                                      A.SC_ERR_NONFINITE)
+                                                      A.SC_ERR_NONFINITE, A.SC_ERR_TIMEOUT)
     _check("sc_solve_lcp", rc, allow)
     return gamma[:nc], g[:nc], st.as_dict(), f_c, u_c
 
@@ -255,7 +266,8 @@ def solve_lcp_adjoint(particles: Particles, box: Box, contacts: Contacts,
                       u_nc: torch.Tensor, dt: float, gamma: torch.Tensor,
                       dL_dgamma: Optional[torch.Tensor] = None,
                       dL_df: Optional[torch.Tensor] = None, tol: float = 1e-10,
-                      max_iter: int = 100000, workspace: Optional[Workspace] = None):
+                      max_iter: int = 100000, lanes_per_particle: int = 0, grid: int = 0,
+                      block: int = 0, workspace: Optional[Workspace] = None):
     """Implicit adjoint of a converged solve: returns (dL_dq, dL_dpos, stats)."""
     nc = contacts.count
     u_nc = _dev(u_nc)
@@ -264,7 +276,8 @@ def solve_lcp_adjoint(particles: Particles, box: Box, contacts: Contacts,
     dLf = None if dL_df is None else _dev(dL_df)
     dq = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
     dpos = torch.empty((particles.n, 3), dtype=torch.float64, device="cuda")
-    opts = A.sc_adjoint_opts(float(tol), int(max_iter), 0)
+    opts = A.sc_adjoint_opts(float(tol), int(max_iter), int(lanes_per_particle), int(grid),
+                             int(block))
     st = A.sc_stats()
     ws = workspace or default_workspace()
     wsp, wsn = ws.get(particles.n, contacts.capacity)

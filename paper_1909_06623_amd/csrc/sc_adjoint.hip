@@ -10,208 +10,164 @@
 //
 // The masked system is solved by conjugate gradients in the single-reduction
 // form of Chronopoulos and Gear (one product and one fused pair of dot
-// products per iteration), laid out exactly like the BBPGD iteration:
-// a particle-major gather pass that also applies the previous iteration's
-// vector updates on the fly, and a contact-major pass that forms A r and both
-// dot products; the last workgroup picks alpha and beta. The geometric
-// derivatives of each contact are then formed per contact and gathered per
+// products per iteration) inside one persistent kernel laid out like the
+// BBPGD iteration: pass A applies the previous iteration's vector updates on
+// the fly and forms U = Mob D r, pass B forms w = A r and both dot products.
+// The geometric derivatives are then formed per contact and gathered per
 // particle (no floating-point atomics).
+#include "sc_chain.hpp"
 #include "sc_common.hpp"
 #include "sc_geometry.hpp"
+#include "sc_plan.hpp"
+#include "sc_sync.hpp"
 
 namespace sc {
 
 namespace {
 
 struct CgCtrl {
-    double alpha, beta, gam_prev, bnorm2, tol, res;
-    int iters, done, status, max_iter;
-    unsigned ticket;
-    int n_active;
-    int pad[2];
+    double alpha, res;
+    int iters, status, n_active, pad;
 };
 
-__global__ void k_cg_init(CgCtrl *c, double tol, int max_iter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        CgCtrl z{};
-        z.tol = tol;
-        z.max_iter = max_iter;
-        *c = z;
+struct CgArgs {
+    ChainView C;
+    const double *gamma;  // active set: gamma > 0
+    double *r[2], *s[2], *p, *x, *w;
+    double *part;         // [G][2]
+    GridSync *sync;
+    CgCtrl *ctrl;
+    double tol;
+    int max_iter;
+};
+
+template <int LPP, int BS>
+__global__ void __launch_bounds__(BS) k_cg(CgArgs A) {
+    GridBarrier bar;
+    bar.init(A.sync);
+    const ChainView &C = A.C;
+    int k0, k1, l0, l1;
+    chunk(C.n, k0, k1);
+    chunk(C.nc, l0, l1);
+    bool ok;
+    double tot[2];
+
+    // first product: w = A r0 and the dot products (r0, r0), (w, r0)
+    pass_a<LPP, BS>(C, k0, k1, [&](int code, int) { return A.r[0][code >> 1]; });
+    ok = bar.sync();
+    {
+        double acc[2] = {0.0, 0.0};
+        for (int l = l0 + threadIdx.x; l < l1; l += BS) {
+            const double wl = A.gamma[l] > 0.0 ? dt_u(C, l) : 0.0;
+            A.w[l] = wl;
+            const double rl = A.r[0][l];
+            acc[0] += rl * rl;
+            acc[1] += wl * rl;
+        }
+        write_partial<2, BS>(A.part, acc);
+    }
+    ok = ok && bar.sync();
+    grid_reduce<2, BS>(A.part, tot);
+    const double bnorm2 = tot[0];
+    double gam_prev = tot[0], alpha = 0.0, beta = 0.0, res = bnorm2 > 0.0 ? 1.0 : 0.0;
+    int iters = 0, status = SC_NOT_CONVERGED;
+    if (!ok) {
+        status = SC_ERR_TIMEOUT;
+    } else if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+        status = SC_ERR_NONFINITE;
+    } else if (bnorm2 == 0.0) {
+        status = SC_OK;
+    } else if (!(tot[1] > 0.0)) {
+        status = SC_NOT_CONVERGED;  // M_AA not positive on r0
+    } else {
+        alpha = tot[0] / tot[1];
+        for (int i = 1; i <= A.max_iter; ++i) {
+            const int cur = (i - 1) & 1, nxt = i & 1;
+            const double *rc = A.r[cur], *sc_ = A.s[cur];
+            double *rn_out = A.r[nxt], *sn_out = A.s[nxt];
+            // p <- r + beta p, s <- w + beta s, x <- x + alpha p, r <- r - alpha s
+            pass_a<LPP, BS>(C, k0, k1, [&](int code, int) {
+                const int l = code >> 1;
+                const double sl = A.w[l] + beta * sc_[l];
+                const double rn = rc[l] - alpha * sl;
+                if (code & 1) {
+                    const double pl = rc[l] + beta * A.p[l];
+                    A.x[l] = A.x[l] + alpha * pl;
+                    A.p[l] = pl;
+                    sn_out[l] = sl;
+                    rn_out[l] = rn;
+                }
+                return rn;
+            });
+            ok = bar.sync();
+            double acc[2] = {0.0, 0.0};
+            for (int l = l0 + threadIdx.x; l < l1; l += BS) {
+                const double wl = A.gamma[l] > 0.0 ? dt_u(C, l) : 0.0;
+                A.w[l] = wl;
+                const double rl = rn_out[l];
+                acc[0] += rl * rl;
+                acc[1] += wl * rl;
+            }
+            write_partial<2, BS>(A.part, acc);
+            ok = ok && bar.sync();
+            grid_reduce<2, BS>(A.part, tot);
+            iters = i;
+            res = sqrt(tot[0] / bnorm2);
+            if (!ok) {
+                status = SC_ERR_TIMEOUT;
+                break;
+            }
+            if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+                status = SC_ERR_NONFINITE;
+                break;
+            }
+            if (tot[0] <= A.tol * A.tol * bnorm2) {
+                status = SC_OK;
+                break;
+            }
+            beta = tot[0] / gam_prev;
+            const double den = tot[1] - beta * tot[0] / alpha;
+            if (!(den > 0.0)) break;  // lost positive definiteness numerically
+            alpha = tot[0] / den;
+            gam_prev = tot[0];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.ctrl->alpha = alpha;
+        A.ctrl->res = res;
+        A.ctrl->iters = iters;
+        A.ctrl->status = status;
     }
 }
 
-// r0 = mask(b), b = dL/dgamma + D^T dL/dF; p = s = x = 0; count |A|.
-__global__ void k_cg_rhs(int nc, const double *gamma, const double *dLdg, const double *dtf,
-                         double *r, double *p, double *s, double *x, CgCtrl *c) {
+// r0 = mask(b) with b = dL/dgamma + D^T dL/dF (dL/dF in caller order); the
+// active set is counted on the way.
+__global__ void k_cg_rhs(int nc, const int *ci, const int *cj, const double *frame,
+                         const double *gamma, const double *dLdg, const double *dLdF, double *r,
+                         int *n_active) {
     int cnt = 0;
     for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < nc; l += gridDim.x * blockDim.x) {
         const bool act = gamma[l] > 0.0;
-        double b = 0.0;
-        if (dLdg) b += dLdg[l];
-        if (dtf) b += dtf[l];
+        double b = dLdg ? dLdg[l] : 0.0;
+        if (dLdF) {
+            const double *f = frame + 9 * static_cast<long long>(l);
+            const double *ui = dLdF + 6 * static_cast<long long>(ci[l]);
+            const double *uj = dLdF + 6 * static_cast<long long>(cj[l]);
+            b += -dot(load3(f), load3(ui)) - dot(load3(f + 3), load3(ui + 3)) +
+                 dot(load3(f), load3(uj)) + dot(load3(f + 6), load3(uj + 3));
+        }
         r[l] = act ? b : 0.0;
-        p[l] = 0.0;
-        s[l] = 0.0;
-        x[l] = 0.0;
         cnt += act;
     }
     for (int off = kWave / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
-    if (threadIdx.x % kWave == 0 && cnt) atomicAdd(&c->n_active, cnt);
-}
-
-// Particle-major pass of CG iteration i >= 1: with (alpha, beta) of step
-// i-1, per active contact
-//   p <- r + beta p,  s <- w + beta s_old,  x <- x + alpha p,  r_new = r - alpha s
-// (p, x updated in place by the i-side thread; s and r written to the next
-// buffers), then U = Mob D r_new. FIRST: U = Mob D r (no update).
-template <bool FIRST>
-__global__ void __launch_bounds__(kBlock)
-k_cg_a(int n, const double *__restrict__ axis, const double *__restrict__ mob,
-       const int *__restrict__ i_ptr, const int *__restrict__ j_ptr,
-       const int *__restrict__ j_list, const double *__restrict__ frame, long long cap,
-       const double *__restrict__ r_cur, const double *__restrict__ s_cur,
-       const double *__restrict__ wv, double *__restrict__ p, double *__restrict__ x,
-       double *__restrict__ r_nxt, double *__restrict__ s_nxt, double *__restrict__ U,
-       const CgCtrl *__restrict__ c) {
-    if (c->done) return;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const double alpha = c->alpha, beta = c->beta;
-    V3 f = v3(0.0, 0.0, 0.0), t = v3(0.0, 0.0, 0.0);
-    const int a0 = i_ptr[k], a1 = i_ptr[k + 1];
-    for (int l = a0; l < a1; ++l) {
-        double rn;
-        if (FIRST) {
-            rn = r_cur[l];
-        } else {
-            const double pl = r_cur[l] + beta * p[l];
-            const double sl = wv[l] + beta * s_cur[l];
-            x[l] = x[l] + alpha * pl;
-            p[l] = pl;
-            s_nxt[l] = sl;
-            rn = r_cur[l] - alpha * sl;
-            r_nxt[l] = rn;
-        }
-        f = f - rn * frame3(frame, cap, 0, l);
-        t = t - rn * frame3(frame, cap, 3, l);
-    }
-    const int b0 = j_ptr[k], b1 = j_ptr[k + 1];
-    for (int m = b0; m < b1; ++m) {
-        const int l = j_list[m];
-        const double rn =
-            FIRST ? r_cur[l] : r_cur[l] - alpha * (wv[l] + beta * s_cur[l]);
-        f = f + rn * frame3(frame, cap, 0, l);
-        t = t + rn * frame3(frame, cap, 6, l);
-    }
-    V3 u, om;
-    mobility_apply(load3(axis + 3 * k), mob + 4 * k, f, t, u, om);
-    double *Uk = U + 6 * static_cast<long long>(k);
-    store3(Uk, u);
-    store3(Uk + 3, om);
-}
-
-// Contact-major pass: w = mask(D^T U) = A r, and the dot products r.r, w.r.
-// The last workgroup forms beta_i = gamma_i / gamma_{i-1} and
-// alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}).
-template <bool FIRST>
-__global__ void __launch_bounds__(kBlock)
-k_cg_b(int nc, const int *__restrict__ ci, const int *__restrict__ cj,
-       const double *__restrict__ frame, long long cap, const double *__restrict__ U,
-       const double *__restrict__ gamma, const double *__restrict__ r, double *__restrict__ wv,
-       double *__restrict__ partials, CgCtrl *c) {
-    __shared__ double lds[2][kBlock / kWave];
-    __shared__ int last;
-    if (c->done) return;
-    double acc[2] = {0.0, 0.0};
-    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < nc; l += gridDim.x * blockDim.x) {
-        double w = 0.0;
-        if (gamma[l] > 0.0) {
-            const V3 n = frame3(frame, cap, 0, l), ti = frame3(frame, cap, 3, l),
-                     tj = frame3(frame, cap, 6, l);
-            const double *Ui = U + 6 * static_cast<long long>(ci[l]);
-            const double *Uj = U + 6 * static_cast<long long>(cj[l]);
-            w = -dot(n, load3(Ui)) - dot(ti, load3(Ui + 3)) + dot(n, load3(Uj)) +
-                dot(tj, load3(Uj + 3));
-        }
-        wv[l] = w;
-        const double rl = r[l];
-        acc[0] += rl * rl;
-        acc[1] += w * rl;
-    }
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-    acc[0] = wave_sum(acc[0]);
-    acc[1] = wave_sum(acc[1]);
-    if (lane == 0) {
-        lds[0][wid] = acc[0];
-        lds[1][wid] = acc[1];
-    }
+    __shared__ int ws[kBlock / kWave];
+    if (threadIdx.x % kWave == 0) ws[threadIdx.x / kWave] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s0 = 0.0, s1 = 0.0;
-        for (int w = 0; w < kBlock / kWave; ++w) {
-            s0 += lds[0][w];
-            s1 += lds[1][w];
-        }
-        __hip_atomic_store(partials + 2 * blockIdx.x, s0, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(partials + 2 * blockIdx.x + 1, s1, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned t =
-            __hip_atomic_fetch_add(&c->ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (t == gridDim.x - 1);
+        int s = 0;
+        for (int k = 0; k < kBlock / kWave; ++k) s += ws[k];
+        if (s) atomicAdd(n_active, s);
     }
-    __syncthreads();
-    if (!last) return;
-    acc[0] = acc[1] = 0.0;
-    for (int b = threadIdx.x; b < static_cast<int>(gridDim.x); b += blockDim.x) {
-        acc[0] += __hip_atomic_load(partials + 2 * b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        acc[1] +=
-            __hip_atomic_load(partials + 2 * b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    acc[0] = wave_sum(acc[0]);
-    acc[1] = wave_sum(acc[1]);
-    __syncthreads();
-    if (lane == 0) {
-        lds[0][wid] = acc[0];
-        lds[1][wid] = acc[1];
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double gam = 0.0, del = 0.0;
-    for (int w = 0; w < kBlock / kWave; ++w) {
-        gam += lds[0][w];
-        del += lds[1][w];
-    }
-    CgCtrl &C = *c;
-    C.ticket = 0;
-    if (FIRST) C.bnorm2 = gam;
-    C.res = C.bnorm2 > 0.0 ? sqrt(gam / C.bnorm2) : 0.0;
-    if (!isfinite(gam) || !isfinite(del)) {
-        C.status = SC_ERR_NONFINITE;
-        C.done = 1;
-        return;
-    }
-    if (gam <= C.tol * C.tol * C.bnorm2 || C.bnorm2 == 0.0) {
-        C.status = SC_OK;
-        C.done = 1;
-        return;
-    }
-    if (!FIRST) C.iters += 1;
-    if (C.iters >= C.max_iter) {
-        C.status = SC_NOT_CONVERGED;
-        C.done = 1;
-        return;
-    }
-    const double beta = FIRST ? 0.0 : gam / C.gam_prev;
-    const double den = FIRST ? del : del - beta * gam / C.alpha;
-    if (!(den > 0.0)) {  // M_AA lost positive definiteness numerically
-        C.status = SC_NOT_CONVERGED;
-        C.done = 1;
-        return;
-    }
-    C.beta = beta;
-    C.alpha = gam / den;
-    C.gam_prev = gam;
 }
 
 // Per-contact derivative of J_l(r) = D_l(r)^T [E_i; E_j] - (w_l/dt) Phi_l(r)
@@ -221,20 +177,23 @@ k_cg_b(int nc, const int *__restrict__ ci, const int *__restrict__ cj,
 // both free -> implicit differentiation of the 2x2 stationarity conditions;
 // one free -> its 1-D projection; both clamped (or a sphere) -> fixed.
 __global__ void k_contact_grad(int nc, const int *__restrict__ ci, const int *__restrict__ cj,
-                               const double *__restrict__ pos, const double *__restrict__ axis,
+                               const int *__restrict__ cs, const double *__restrict__ pos,
+                               const double *__restrict__ axis,
                                const double *__restrict__ half_len, PBox box,
                                const double *__restrict__ gamma, const double *__restrict__ w,
                                const double *__restrict__ dLdF, const double *__restrict__ Vw,
                                const double *__restrict__ Unc, const double *__restrict__ Uc,
-                               double inv_dt, double *__restrict__ grad, long long cap) {
+                               double inv_dt, double *__restrict__ grad) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nc) return;
     const double gl = gamma[l], wl = w[l];
+    double *gout = grad + 3 * static_cast<long long>(l);
     if (gl == 0.0 && wl == 0.0) {
-        grad[l] = grad[cap + l] = grad[2 * cap + l] = 0.0;
+        gout[0] = gout[1] = gout[2] = 0.0;
         return;
     }
     const int i = ci[l], j = cj[l];
+    const long long ri = cs[2 * l], rj = cs[2 * l + 1];
     const V3 pi = load3(axis + 3 * i), pj = load3(axis + 3 * j);
     const double hi = half_len[i], hj = half_len[j];
     const V3 r = min_image(load3(pos + 3 * i), load3(pos + 3 * j), box);
@@ -255,17 +214,15 @@ __global__ void k_contact_grad(int nc, const int *__restrict__ ci, const int *__
     const V3 d = r + t * pj - s * pi;
     const double rho = sqrt(dot(d, d));
     const V3 n = (1.0 / rho) * d;
-    // E_i, E_j (6-vectors as force and torque parts)
-    V3 EiF, EiT, EjF, EjT;
-    {
-        const long long oi = 6 * static_cast<long long>(i), oj = 6 * static_cast<long long>(j);
-        V3 fi = dLdF ? load3(dLdF + oi) : v3(0, 0, 0), ti = dLdF ? load3(dLdF + oi + 3) : v3(0, 0, 0);
-        V3 fj = dLdF ? load3(dLdF + oj) : v3(0, 0, 0), tj = dLdF ? load3(dLdF + oj + 3) : v3(0, 0, 0);
-        EiF = gl * (fi - load3(Vw + oi)) - wl * (load3(Unc + oi) + load3(Uc + oi));
-        EiT = gl * (ti - load3(Vw + oi + 3)) - wl * (load3(Unc + oi + 3) + load3(Uc + oi + 3));
-        EjF = gl * (fj - load3(Vw + oj)) - wl * (load3(Unc + oj) + load3(Uc + oj));
-        EjT = gl * (tj - load3(Vw + oj + 3)) - wl * (load3(Unc + oj + 3) + load3(Uc + oj + 3));
-    }
+    const long long oi = 6 * static_cast<long long>(i), oj = 6 * static_cast<long long>(j);
+    const V3 zero = v3(0.0, 0.0, 0.0);
+    const V3 fi = dLdF ? load3(dLdF + oi) : zero, tqi = dLdF ? load3(dLdF + oi + 3) : zero;
+    const V3 fj = dLdF ? load3(dLdF + oj) : zero, tqj = dLdF ? load3(dLdF + oj + 3) : zero;
+    const double *Vi = Vw + 8 * ri, *Vj = Vw + 8 * rj, *Ci = Uc + 8 * ri, *Cj = Uc + 8 * rj;
+    const V3 EiF = gl * (fi - load3(Vi)) - wl * (load3(Unc + oi) + load3(Ci));
+    const V3 EiT = gl * (tqi - load3(Vi + 3)) - wl * (load3(Unc + oi + 3) + load3(Ci + 3));
+    const V3 EjF = gl * (fj - load3(Vj)) - wl * (load3(Unc + oj) + load3(Cj));
+    const V3 EjT = gl * (tqj - load3(Vj + 3)) - wl * (load3(Unc + oj + 3) + load3(Cj + 3));
     // J_d = dd/dr = I + p_j dt^T - p_i ds^T, so J_d^T u = u + dt (p_j.u) - ds (p_i.u);
     // dn/dr = (I - n n^T) J_d / rho.
     auto JdT = [&](V3 u) { return u + dot(pj, u) * dt - dot(pi, u) * ds; };
@@ -273,32 +230,29 @@ __global__ void k_contact_grad(int nc, const int *__restrict__ ci, const int *__
     const V3 vn = (EjF - EiF) - s * cross(EiT, pi) + t * cross(EjT, pj);
     const V3 g = JnT(vn) - dot(cross(pi, n), EiT) * ds + dot(cross(pj, n), EjT) * dt -
                  (wl * inv_dt) * JdT(n);
-    grad[l] = g.x;
-    grad[cap + l] = g.y;
-    grad[2 * cap + l] = g.z;
+    gout[0] = g.x;
+    gout[1] = g.y;
+    gout[2] = g.z;
 }
 
-// dL/dc_k = sum over contacts with j == k of grad - sum over those with i == k.
-__global__ void k_gather_pos(int n, const int *__restrict__ i_ptr, const int *__restrict__ j_ptr,
-                             const int *__restrict__ j_list, const double *__restrict__ grad,
-                             long long cap, double *__restrict__ out) {
+// dL/dc_k = sum over k's contacts of -grad (k is ci) or +grad (k is cj),
+// gathered per rank and written at the caller index.
+__global__ void k_gather_pos(int n, Plan pl, const double *__restrict__ grad,
+                             double *__restrict__ out) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int l = i_ptr[k]; l < i_ptr[k + 1]; ++l) {
-        gx -= grad[l];
-        gy -= grad[cap + l];
-        gz -= grad[2 * cap + l];
+    for (int e = pl.inc_ptr[k]; e < pl.inc_ptr[k + 1]; ++e) {
+        const long long l = pl.inc[e] >> 1;
+        const double sg = pl.cs[2 * l] == k ? -1.0 : 1.0;
+        gx += sg * grad[3 * l + 0];
+        gy += sg * grad[3 * l + 1];
+        gz += sg * grad[3 * l + 2];
     }
-    for (int m = j_ptr[k]; m < j_ptr[k + 1]; ++m) {
-        const int l = j_list[m];
-        gx += grad[l];
-        gy += grad[cap + l];
-        gz += grad[2 * cap + l];
-    }
-    out[3 * static_cast<long long>(k) + 0] = gx;
-    out[3 * static_cast<long long>(k) + 1] = gy;
-    out[3 * static_cast<long long>(k) + 2] = gz;
+    const long long o = 3 * static_cast<long long>(pl.order[k]);
+    out[o + 0] = gx;
+    out[o + 1] = gy;
+    out[o + 2] = gz;
 }
 
 __global__ void k_neg_masked(int nc, const double *gamma, const double *x, double *out) {
@@ -306,9 +260,20 @@ __global__ void k_neg_masked(int nc, const double *gamma, const double *x, doubl
     if (l < nc) out[l] = gamma[l] > 0.0 ? -x[l] : 0.0;
 }
 
-int cg_blocks(int nc) {
-    int b = grid_for(nc);
-    return b > kMaxReduceBlocks ? kMaxReduceBlocks : b;
+using CgKernel = void (*)(CgArgs);
+
+template <int BS>
+CgKernel cg_kernel_bs(int lpp) {
+    switch (lpp) {
+    case 1: return k_cg<1, BS>;
+    case 2: return k_cg<2, BS>;
+    case 8: return k_cg<8, BS>;
+    default: return k_cg<4, BS>;
+    }
+}
+
+CgKernel cg_kernel(int lpp, int block) {
+    return block == 256 ? cg_kernel_bs<256>(lpp) : cg_kernel_bs<1024>(lpp);
 }
 
 }  // namespace
@@ -316,12 +281,13 @@ int cg_blocks(int nc) {
 size_t adjoint_ws_bytes(int32_t n, int32_t cap) {
     const size_t nn = static_cast<size_t>(n), cc = static_cast<size_t>(cap);
     size_t b = 0;
-    b += 8 * align_up(cc * sizeof(double), 256);        // r[2], s[2], p, x, w, dtf
+    b += 7 * align_up(cc * sizeof(double), 256);        // r[2], s[2], p, x, w
     b += align_up(3 * cc * sizeof(double), 256);        // grad
-    b += 3 * align_up(6 * nn * sizeof(double), 256);    // U, Vw, Uc
-    b += align_up(2 * kMaxReduceBlocks * sizeof(double), 256);
+    b += 3 * align_up(8 * nn * sizeof(double), 256);    // U, Vw, Uc (rank order)
+    b += align_up(4 * kMaxReduceBlocks * sizeof(double), 256);
+    b += align_up(sizeof(GridSync), 256);
     b += align_up(sizeof(CgCtrl), 256);
-    return b + 1024;
+    return b + 2048;
 }
 
 }  // namespace sc
@@ -337,15 +303,18 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     if (!p || !box || !c || !opts || !st || p->n < 0 || c->count < 0 ||
         c->count > c->capacity)
         return SC_ERR_INVALID;
-    if (!(dt > 0.0) || !(opts->tol > 0.0) || opts->max_iter < 0) return SC_ERR_INVALID;
+    if (!(dt > 0.0) || !(opts->tol > 0.0) || opts->max_iter < 0 ||
+        opts->lanes_per_particle < 0 || opts->lanes_per_particle > 8 || opts->grid < 0 ||
+        (opts->block != 0 && opts->block != 256 && opts->block != 1024))
+        return SC_ERR_INVALID;
     *st = sc_stats{};
     const int n = p->n, nc = c->count;
+    Plan pl;
+    if (!carve_plan(c->plan, c->plan_bytes, n, c->capacity, pl)) return SC_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream_);
     if (n > 0 && (!dL_dpos || !p->pos || !p->axis || !p->half_len || !p->mob || !u_nc))
         return SC_ERR_INVALID;
-    if (nc > 0 && (!gamma || !dL_dq || !c->ci || !c->cj || !c->frame || !c->i_ptr ||
-                   !c->j_ptr || !c->j_list))
-        return SC_ERR_INVALID;
+    if (nc > 0 && (!gamma || !dL_dq || !c->ci || !c->cj || !c->frame)) return SC_ERR_INVALID;
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 ||
         ws_bytes < adjoint_ws_bytes(n, c->capacity))
         return SC_ERR_WORKSPACE;
@@ -357,66 +326,64 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     }
     const long long cap = c->capacity;
     Carver cv{static_cast<char *>(ws), ws_bytes};
-    double *r[2] = {cv.take<double>(cap), cv.take<double>(cap)};
-    double *sv[2] = {cv.take<double>(cap), cv.take<double>(cap)};
-    double *pv = cv.take<double>(cap);
-    double *x = cv.take<double>(cap);
-    double *wv = cv.take<double>(cap);
-    double *dtf = cv.take<double>(cap);
+    double *r0 = cv.take<double>(cap), *r1 = cv.take<double>(cap);
+    double *s0 = cv.take<double>(cap), *s1 = cv.take<double>(cap);
+    double *pv = cv.take<double>(cap), *x = cv.take<double>(cap), *wv = cv.take<double>(cap);
     double *grad = cv.take<double>(3 * cap);
-    double *U = cv.take<double>(6 * static_cast<size_t>(n));
-    double *Vw = cv.take<double>(6 * static_cast<size_t>(n));
-    double *Uc = cv.take<double>(6 * static_cast<size_t>(n));
-    double *partials = cv.take<double>(2 * kMaxReduceBlocks);
+    double *U = cv.take<double>(8 * static_cast<size_t>(n));
+    double *Vw = cv.take<double>(8 * static_cast<size_t>(n));
+    double *Uc = cv.take<double>(8 * static_cast<size_t>(n));
+    double *part = cv.take<double>(4 * kMaxReduceBlocks);
+    GridSync *sync = cv.take<GridSync>(1);
     CgCtrl *ctrl = cv.take<CgCtrl>(1);
     if (!cv.ok) return SC_ERR_WORKSPACE;
 
-    const int nb = cg_blocks(nc);
-    k_cg_init<<<1, 1, 0, s>>>(ctrl, opts->tol, opts->max_iter);
-    if (dL_df) launch_DT(nc, c->ci, c->cj, c->frame, cap, dL_df, dtf, s);
-    k_cg_rhs<<<nb, kBlock, 0, s>>>(nc, gamma, dL_dgamma, dL_df ? dtf : nullptr, r[0], pv,
-                                   sv[0], x, ctrl);
-    k_cg_a<true><<<grid_for(n), kBlock, 0, s>>>(n, p->axis, p->mob, c->i_ptr, c->j_ptr,
-                                                c->j_list, c->frame, cap, r[0], sv[0], wv, pv,
-                                                x, r[1], sv[1], U, ctrl);
-    k_cg_b<true><<<nb, kBlock, 0, s>>>(nc, c->ci, c->cj, c->frame, cap, U, gamma, r[0], wv,
-                                       partials, ctrl);
-    // CG iterations in chunks, polled one chunk behind through a host copy
-    const int chunk = 16;
-    int it = 0;
-    int done_host = 0;
-    while (it < opts->max_iter && !done_host) {
-        const int upto = it + chunk < opts->max_iter ? it + chunk : opts->max_iter;
-        for (int i = it + 1; i <= upto; ++i) {
-            const int cur = (i - 1) & 1, nxt = i & 1;
-            k_cg_a<false><<<grid_for(n), kBlock, 0, s>>>(n, p->axis, p->mob, c->i_ptr,
-                                                         c->j_ptr, c->j_list, c->frame, cap,
-                                                         r[cur], sv[cur], wv, pv, x, r[nxt],
-                                                         sv[nxt], U, ctrl);
-            k_cg_b<false><<<nb, kBlock, 0, s>>>(nc, c->ci, c->cj, c->frame, cap, U, gamma,
-                                                r[nxt], wv, partials, ctrl);
-        }
-        it = upto;
-        SC_HIP_TRY(hipMemcpyAsync(&done_host, &ctrl->done, sizeof(int), hipMemcpyDeviceToHost, s));
-        SC_HIP_TRY(hipStreamSynchronize(s));
-    }
-    CgCtrl hc;
-    SC_HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(CgCtrl), hipMemcpyDeviceToHost, s));
-    SC_HIP_TRY(hipStreamSynchronize(s));
-    if (!hc.done) hc.status = SC_NOT_CONVERGED;
+    int lpp = opts->lanes_per_particle ? opts->lanes_per_particle : 4;
+    if (lpp != 1 && lpp != 2 && lpp != 4 && lpp != 8) return SC_ERR_INVALID;
+    const int block = opts->block ? opts->block : 1024;
+    CgKernel kern = cg_kernel(lpp, block);
+    const int G = persistent_grid(reinterpret_cast<const void *>(kern), block, opts->grid);
+    if (G < 1) return SC_ERR_HIP;
 
+    SC_HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(CgCtrl), s));
+    SC_HIP_TRY(hipMemsetAsync(sync, 0, sizeof(GridSync), s));
+    SC_HIP_TRY(hipMemsetAsync(s0, 0, sizeof(double) * nc, s));
+    SC_HIP_TRY(hipMemsetAsync(pv, 0, sizeof(double) * nc, s));
+    SC_HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * nc, s));
+    int nb = grid_for(nc);
+    if (nb > kMaxReduceBlocks) nb = kMaxReduceBlocks;
+    k_cg_rhs<<<nb, kBlock, 0, s>>>(nc, c->ci, c->cj, c->frame, gamma, dL_dgamma, dL_df, r0,
+                                   &ctrl->n_active);
+    CgArgs A;
+    A.C = chain_view(p, c, pl, U);
+    A.gamma = gamma;
+    A.r[0] = r0;
+    A.r[1] = r1;
+    A.s[0] = s0;
+    A.s[1] = s1;
+    A.p = pv;
+    A.x = x;
+    A.w = wv;
+    A.part = part;
+    A.sync = sync;
+    A.ctrl = ctrl;
+    A.tol = opts->tol;
+    A.max_iter = opts->max_iter;
+    void *args[] = {&A};
+    SC_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G),
+                                          dim3(block), args, 0, s));
     // dL/dq = -w on A; V_w = Mob D w; U_c = Mob D gamma; geometric terms
     k_neg_masked<<<grid_for(nc), kBlock, 0, s>>>(nc, gamma, x, dL_dq);
-    launch_mob_D(n, p->axis, p->mob, c->i_ptr, c->j_ptr, c->j_list, c->frame, cap, x, Vw,
-                 nullptr, s);
-    launch_mob_D(n, p->axis, p->mob, c->i_ptr, c->j_ptr, c->j_list, c->frame, cap, gamma, Uc,
-                 nullptr, s);
+    ChainView Cv = chain_view(p, c, pl, Vw), Cc = chain_view(p, c, pl, Uc);
+    launch_mob_d(Cv, x, pl.order, nullptr, nullptr, s);
+    launch_mob_d(Cc, gamma, pl.order, nullptr, nullptr, s);
     PBox pb{{box->len[0], box->len[1], box->len[2]}, box->periodic ? 1 : 0};
-    k_contact_grad<<<grid_for(nc), kBlock, 0, s>>>(nc, c->ci, c->cj, p->pos, p->axis,
+    k_contact_grad<<<grid_for(nc), kBlock, 0, s>>>(nc, c->ci, c->cj, pl.cs, p->pos, p->axis,
                                                    p->half_len, pb, gamma, x, dL_df, Vw, u_nc,
-                                                   Uc, 1.0 / dt, grad, cap);
-    k_gather_pos<<<grid_for(n), kBlock, 0, s>>>(n, c->i_ptr, c->j_ptr, c->j_list, grad, cap,
-                                                dL_dpos);
+                                                   Uc, 1.0 / dt, grad);
+    k_gather_pos<<<grid_for(n), kBlock, 0, s>>>(n, pl, grad, dL_dpos);
+    CgCtrl hc;
+    SC_HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(CgCtrl), hipMemcpyDeviceToHost, s));
     SC_HIP_TRY(hipStreamSynchronize(s));
     SC_HIP_TRY(hipGetLastError());
     st->status = hc.status;
@@ -425,5 +392,8 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     st->n_active = hc.n_active;
     st->residual = hc.res;
     st->alpha = hc.alpha;
+    st->grid = G;
+    st->block = block;
+    st->lanes_per_particle = lpp;
     return hc.status;
 }

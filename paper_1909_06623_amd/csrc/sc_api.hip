@@ -21,8 +21,9 @@ extern "C" const char *sc_strerror(int code) {
     case SC_ERR_BOX: return "periodic box side below twice the interaction range";
     case SC_ERR_HIP: return "HIP runtime error";
     case SC_ERR_WORKSPACE: return "workspace too small or not 256-byte aligned";
+    case SC_ERR_TIMEOUT: return "a grid barrier of a persistent kernel timed out";
     default: return "unknown status code";
     }
 }
 
-extern "C" int sc_version(void) { return 100; }
+extern "C" int sc_version(void) { return 200; }

@@ -61,14 +61,6 @@ int scan_tmp_ints(int n);
 void scan_exclusive(const int *in, int *out, int n, int *tmp,
                     hipStream_t stream);
 
-// Plain products shared by the solve and the adjoint (sc_solve.hip):
-// U = Mob D x (and F = D x if F != nullptr), and y = D^T U.
-void launch_mob_D(int n, const double *axis, const double *mob, const int *i_ptr,
-                  const int *j_ptr, const int *j_list, const double *frame, long long cap,
-                  const double *x, double *U, double *F, hipStream_t s);
-void launch_DT(int nc, const int *ci, const int *cj, const double *frame, long long cap,
-               const double *U, double *y, hipStream_t s);
-
 // ------------------------------------------------------------------ device
 
 struct V3 {

@@ -3,22 +3,23 @@
 // Builds the set A(C, delta) = {(i, j), i < j : Phi_ij <= delta} of section
 // 3.2 with a uniform cell list (section 5.2 names cell lists as the standard
 // near-neighbour method), the contact frames that define the columns of D
-// (Eq. Dmatdef; their entries follow from Eq. Dtranspose), the particle-major
-// incidence used by the gather form of D gamma, and q = Phi/dt + D^T U_nc
-// (LCP LCPdef).
+// (Eq. Dmatdef; their entries follow from Eq. Dtranspose) and
+// q = Phi/dt + D^T U_nc (LCP LCPdef), plus the solver layout (sc_plan.hpp).
 //
-// Pipeline (all stream-ordered, two host synchronisations: the interaction
-// range sizes the grid, and the pair count is checked against capacity):
-//   validate + max extent -> bin -> scan -> scatter -> count pairs -> scan
-//   -> write pairs (sorted by j per i) -> j-side incidence -> q.
-// Every per-pair decision is a pure function of the pair, so the contact
-// list is independent of thread scheduling; within-cell member order does
-// not matter because each i sorts its partners.
+// Pipeline (stream-ordered; two host synchronisations: the interaction range
+// sizes the grid, and the pair count is checked against capacity):
+//   validate + max extent -> bin -> scan -> scatter -> rank particles in
+//   cell order (ties by caller index) -> count partners of higher rank ->
+//   scan -> write contacts (partners sorted by rank) -> incidence lists and
+//   signed column entries -> q.
+// Every decision is a pure function of the inputs, so the contact list and
+// its order are independent of thread scheduling.
 #include <cmath>
 #include <cstring>
 
 #include "sc_common.hpp"
 #include "sc_geometry.hpp"
+#include "sc_plan.hpp"
 
 namespace sc {
 
@@ -46,7 +47,14 @@ struct Parts {
     const double *pos, *axis, *radius, *half_len, *mob;
 };
 
-// ----------------------------------------------------------- cell list
+// Ranked (cell-ordered) copies used by the pair search: centre and radius in
+// one 32-byte record, the half length, and the cell of each rank; the axis
+// comes from the plan record.
+struct Ranked {
+    const double *prec;   // [n][4] x y z, R
+    const double *hl;     // [n]
+    const int *cell;      // [n]
+};
 
 __device__ __forceinline__ int cell_axis(double x, int a, const Grid &g) {
     double u = x - g.lo[a];
@@ -112,141 +120,219 @@ __global__ void k_scatter(int n, const int *cell_of, const int *cell_start, int 
     members[cell_start[c] + atomicAdd(cell_fill + c, 1)] = k;
 }
 
-// Visit every partner j > i of particle i (threads walk particles in cell
-// order, so neighbouring lanes scan the same cells) whose pair has
-// Phi <= delta, calling fn(j, geo).
+// Rank of particle k: its cell's start plus the number of cell members with
+// a smaller caller index (a deterministic order within each cell). Writes the
+// permutation and the ranked particle records.
+__global__ void k_rank(Parts P, const int *cell_of, const int *cell_start, const int *members,
+                       Plan pl, double *prec, double *hl, int *cell_r) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P.n) return;
+    const int c = cell_of[k];
+    const int b0 = cell_start[c], b1 = cell_start[c + 1];
+    int r = 0;
+    for (int m = b0; m < b1; ++m) r += members[m] < k;
+    const int rk = b0 + r;
+    pl.rank[k] = rk;
+    pl.order[rk] = k;
+    cell_r[rk] = c;
+    double *rec = pl.pdat + 8 * static_cast<long long>(rk);
+    rec[0] = P.axis[3 * k + 0];
+    rec[1] = P.axis[3 * k + 1];
+    rec[2] = P.axis[3 * k + 2];
+    rec[3] = 0.0;
+    for (int a = 0; a < 4; ++a) rec[4 + a] = P.mob[4 * k + a];
+    double *pr = prec + 4 * static_cast<long long>(rk);
+    pr[0] = P.pos[3 * k + 0];
+    pr[1] = P.pos[3 * k + 1];
+    pr[2] = P.pos[3 * k + 2];
+    pr[3] = P.radius[k];
+    hl[rk] = P.half_len[k];
+}
+
+// Geometry of ranks (ri, rj) evaluated as the pair (lower caller index, higher
+// caller index), so a contact's normal and moment arms do not depend on the
+// ranking.
+__device__ __forceinline__ PairGeo ranked_geo(int a, int b, const Ranked &R, const Plan &pl,
+                                              const PBox &box, bool &a_is_i) {
+    a_is_i = pl.order[a] < pl.order[b];
+    const int ri = a_is_i ? a : b, rj = a_is_i ? b : a;
+    const double *pi_ = R.prec + 4 * static_cast<long long>(ri);
+    const double *pj_ = R.prec + 4 * static_cast<long long>(rj);
+    const double *ai = pl.pdat + 8 * static_cast<long long>(ri);
+    const double *aj = pl.pdat + 8 * static_cast<long long>(rj);
+    return pair_geo(min_image(v3(pi_[0], pi_[1], pi_[2]), v3(pj_[0], pj_[1], pj_[2]), box),
+                    v3(ai[0], ai[1], ai[2]), pi_[3], R.hl[ri], v3(aj[0], aj[1], aj[2]),
+                    pj_[3], R.hl[rj]);
+}
+
+// Visit every partner u > t (by rank) of rank t whose pair has Phi <= delta,
+// calling fn(u, geo).
 template <class Fn>
-__device__ __forceinline__ void for_close_partners(int i, const Parts &P, const Grid &g,
-                                                   const int *cell_of, const int *cell_start,
-                                                   const int *members, Fn fn) {
-    const V3 ci = load3(P.pos + 3 * i), pi = load3(P.axis + 3 * i);
-    const double Ri = P.radius[i], hi = P.half_len[i];
-    const int c = cell_of[i];
+__device__ __forceinline__ void for_close_partners(int t, const Ranked &R, const Plan &pl,
+                                                   const Grid &g, const int *cell_start,
+                                                   Fn fn) {
+    const double *pt = R.prec + 4 * static_cast<long long>(t);
+    const V3 ct = v3(pt[0], pt[1], pt[2]);
+    const double Rt = pt[3], ht = R.hl[t];
+    const int c = R.cell[t];
     const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
     int nx[3], ny[3], nz[3];
     const int kx = neighbours(cx, 0, g, nx), ky = neighbours(cy, 1, g, ny),
               kz = neighbours(cz, 2, g, nz);
+    const PBox box = g.box();
     for (int az = 0; az < kz; ++az)
         for (int ay = 0; ay < ky; ++ay)
             for (int ax = 0; ax < kx; ++ax) {
                 const int cc = (nz[az] * g.nc[1] + ny[ay]) * g.nc[0] + nx[ax];
+                int u = cell_start[cc];
                 const int end = cell_start[cc + 1];
-                for (int m = cell_start[cc]; m < end; ++m) {
-                    const int j = members[m];
-                    if (j <= i) continue;
-                    const V3 r = min_image(ci, load3(P.pos + 3 * j), g.box());
-                    const double Rj = P.radius[j], hj = P.half_len[j];
-                    // the core distance is at least |r| - hi - hj
-                    const double reach = hi + hj + Ri + Rj + g.delta;
+                if (u <= t) u = t + 1;
+                for (; u < end; ++u) {
+                    const double *pu = R.prec + 4 * static_cast<long long>(u);
+                    const V3 r = min_image(ct, v3(pu[0], pu[1], pu[2]), box);
+                    // the core distance is at least |r| - ht - hu
+                    const double reach = ht + R.hl[u] + Rt + pu[3] + g.delta;
                     if (dot(r, r) > reach * reach * (1.0 + 1e-9)) continue;
-                    const PairGeo G = pair_geo(r, pi, Ri, hi, load3(P.axis + 3 * j), Rj, hj);
-                    if (G.phi <= g.delta) fn(j, G);
+                    bool t_is_i;
+                    const PairGeo G = ranked_geo(t, u, R, pl, box, t_is_i);
+                    if (G.phi <= g.delta) fn(u, G);
                 }
             }
 }
 
-__global__ void k_count_pairs(Parts P, Grid g, const int *cell_of, const int *cell_start,
-                              const int *members, int *count, int *flags) {
+__global__ void k_count_pairs(int n, Ranked R, Plan pl, Grid g, const int *cell_start,
+                              int *flags) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= P.n) return;
-    const int i = members[t];
+    if (t >= n) return;
     int cnt = 0, npar = 0, nzero = 0, nborder = 0;
-    for_close_partners(i, P, g, cell_of, cell_start, members, [&](int, const PairGeo &G) {
+    for_close_partners(t, R, pl, g, cell_start, [&](int, const PairGeo &G) {
         ++cnt;
         npar += G.flags & 1;
         nzero += (G.flags >> 1) & 1;
         nborder += fabs(G.phi - g.delta) < 1e-12;
     });
-    count[i] = cnt;
+    pl.cptr[t] = cnt;
     if (npar) atomicAdd(flags + kFlagParallel, npar);
     if (nzero) atomicAdd(flags + kFlagZero, nzero);
     if (nborder) atomicAdd(flags + kFlagBorder, nborder);
 }
 
-__global__ void k_write_pairs(Parts P, Grid g, const int *cell_of, const int *cell_start,
-                              const int *members, const int *i_ptr, int *ci, int *cj,
-                              double *phi, double *frame, long long cap) {
+// Contacts of rank t (partners of higher rank, ascending): caller indices,
+// Phi, frame [l][9] = n, tau_i, tau_j oriented from ci (lower caller index)
+// to cj, and cs[l] = the ranks of (ci, cj).
+__global__ void k_write_pairs(int n, Ranked R, Plan pl, Grid g, const int *cell_start,
+                              int *ci, int *cj, double *phi, double *frame) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= P.n) return;
-    const int i = members[t];
-    const int base = i_ptr[i], lim = i_ptr[i + 1] - base;
+    if (t >= n) return;
+    const int base = pl.cptr[t], lim = pl.cptr[t + 1] - base;
+    int *part = pl.cs + 2 * static_cast<long long>(base);  // even slots: partner ranks
     int k = 0;
     // the count pass used the same pure predicate, so k ends at lim; the
     // bound only guards the segment
-    for_close_partners(i, P, g, cell_of, cell_start, members, [&](int j, const PairGeo &) {
-        if (k < lim) cj[base + k] = j;
+    for_close_partners(t, R, pl, g, cell_start, [&](int u, const PairGeo &) {
+        if (k < lim) part[2 * k] = u;
         ++k;
     });
     if (k > lim) k = lim;
-    // canonical order: partners of i by increasing j (segments are short)
     for (int a = 1; a < k; ++a) {
-        const int v = cj[base + a];
+        const int v = part[2 * a];
         int b = a - 1;
-        while (b >= 0 && cj[base + b] > v) {
-            cj[base + b + 1] = cj[base + b];
+        while (b >= 0 && part[2 * b] > v) {
+            part[2 * (b + 1)] = part[2 * b];
             --b;
         }
-        cj[base + b + 1] = v;
+        part[2 * (b + 1)] = v;
     }
-    const V3 c_i = load3(P.pos + 3 * i), pi = load3(P.axis + 3 * i);
-    const double Ri = P.radius[i], hi = P.half_len[i];
+    const PBox box = g.box();
+    const int ot = pl.order[t];
     for (int a = 0; a < k; ++a) {
         const long long l = base + a;
-        const int j = cj[l];
-        const V3 pj = load3(P.axis + 3 * j);
-        const PairGeo G = pair_geo(min_image(c_i, load3(P.pos + 3 * j), g.box()), pi, Ri, hi, pj,
-                                   P.radius[j], P.half_len[j]);
-        ci[l] = i;
+        const int u = part[2 * a];
+        bool t_is_i;
+        const PairGeo G = ranked_geo(t, u, R, pl, box, t_is_i);
+        const int ri = t_is_i ? t : u, rj = t_is_i ? u : t;
+        const double *ai = pl.pdat + 8 * static_cast<long long>(ri);
+        const double *aj = pl.pdat + 8 * static_cast<long long>(rj);
+        const int ou = pl.order[u];
+        ci[l] = t_is_i ? ot : ou;
+        cj[l] = t_is_i ? ou : ot;
         phi[l] = G.phi;
         // moment arms of the contact points: tau_i = (s p_i) x n, tau_j = (t p_j) x n
-        const V3 ti = cross(G.s * pi, G.n), tj = cross(G.t * pj, G.n);
-        frame[0 * cap + l] = G.n.x;
-        frame[1 * cap + l] = G.n.y;
-        frame[2 * cap + l] = G.n.z;
-        frame[3 * cap + l] = ti.x;
-        frame[4 * cap + l] = ti.y;
-        frame[5 * cap + l] = ti.z;
-        frame[6 * cap + l] = tj.x;
-        frame[7 * cap + l] = tj.y;
-        frame[8 * cap + l] = tj.z;
+        const V3 ti = cross(G.s * v3(ai[0], ai[1], ai[2]), G.n);
+        const V3 tj = cross(G.t * v3(aj[0], aj[1], aj[2]), G.n);
+        double *f = frame + 9 * l;
+        f[0] = G.n.x; f[1] = G.n.y; f[2] = G.n.z;
+        f[3] = ti.x;  f[4] = ti.y;  f[5] = ti.z;
+        f[6] = tj.x;  f[7] = tj.y;  f[8] = tj.z;
+        part[2 * a] = ri;
+        part[2 * a + 1] = rj;
     }
 }
 
-__global__ void k_j_degree(int nc, const int *cj, int *deg) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l < nc) atomicAdd(deg + cj[l], 1);
-}
-
-__global__ void k_j_fill(int nc, const int *cj, const int *j_ptr, int *fill, int *j_list) {
+// Incidences of each rank: its contacts as the lower rank first, in contact
+// order (these incidences own gamma_l), then its contacts as the higher rank,
+// placed by an atomic cursor and sorted by contact index afterwards.
+__global__ void k_second_degree(int nc, Plan pl, int *deg) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nc) return;
-    const int j = cj[l];
-    j_list[j_ptr[j] + atomicAdd(fill + j, 1)] = l;
+    const int a = pl.cs[2 * l], b = pl.cs[2 * l + 1];
+    atomicAdd(deg + (a > b ? a : b), 1);
 }
 
-__global__ void k_j_sort(int n, const int *j_ptr, int *j_list) {
+__global__ void k_inc_counts(int n, Plan pl, const int *deg) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const int b0 = j_ptr[k], b1 = j_ptr[k + 1];
-    for (int a = b0 + 1; a < b1; ++a) {
-        const int v = j_list[a];
+    pl.inc_ptr[k] = (pl.cptr[k + 1] - pl.cptr[k]) + deg[k];
+}
+
+__global__ void k_inc_fill(int nc, Plan pl, int *fill) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nc) return;
+    const int a = pl.cs[2 * l], b = pl.cs[2 * l + 1];
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    pl.inc[pl.inc_ptr[lo] + (l - pl.cptr[lo])] = 2 * l + 1;
+    const int first_hi = pl.cptr[hi + 1] - pl.cptr[hi];
+    pl.inc[pl.inc_ptr[hi] + first_hi + atomicAdd(fill + hi, 1)] = 2 * l;
+}
+
+// Sort the higher-rank part of each incidence list, then write the signed
+// column entries: -(n, tau_i) on ci's rank, +(n, tau_j) on cj's rank.
+__global__ void k_inc_finish(int n, Plan pl, const double *frame) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int e0 = pl.inc_ptr[k] + (pl.cptr[k + 1] - pl.cptr[k]), e1 = pl.inc_ptr[k + 1];
+    for (int a = e0 + 1; a < e1; ++a) {
+        const int v = pl.inc[a];
         int b = a - 1;
-        while (b >= b0 && j_list[b] > v) {
-            j_list[b + 1] = j_list[b];
+        while (b >= e0 && pl.inc[b] > v) {
+            pl.inc[b + 1] = pl.inc[b];
             --b;
         }
-        j_list[b + 1] = v;
+        pl.inc[b + 1] = v;
+    }
+    for (int e = pl.inc_ptr[k]; e < e1; ++e) {
+        const long long l = pl.inc[e] >> 1;
+        const double *f = frame + 9 * l;
+        const bool is_i = pl.cs[2 * l] == k;
+        const double sg = is_i ? -1.0 : 1.0;
+        const double *tau = is_i ? f + 3 : f + 6;
+        double *d = pl.dpm + 6 * static_cast<long long>(e);
+        d[0] = sg * f[0];
+        d[1] = sg * f[1];
+        d[2] = sg * f[2];
+        d[3] = sg * tau[0];
+        d[4] = sg * tau[1];
+        d[5] = sg * tau[2];
     }
 }
 
 // q_l = Phi_l / dt + D_l^T U_nc (LCP LCPdef, scaled by 1/dt).
 __global__ void k_q(int nc, const int *ci, const int *cj, const double *phi,
-                    const double *frame, long long cap, const double *u_nc, double dt,
-                    double *q, int *flags) {
+                    const double *frame, const double *u_nc, double dt, double *q, int *flags) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nc) return;
-    const V3 n = frame3(frame, cap, 0, l), ti = frame3(frame, cap, 3, l),
-             tj = frame3(frame, cap, 6, l);
+    const double *f = frame + 9 * static_cast<long long>(l);
+    const V3 n = load3(f), ti = load3(f + 3), tj = load3(f + 6);
     const double *ui = u_nc + 6 * static_cast<long long>(ci[l]);
     const double *uj = u_nc + 6 * static_cast<long long>(cj[l]);
     const double v = -dot(n, load3(ui)) - dot(ti, load3(ui + 3)) + dot(n, load3(uj)) +
@@ -264,19 +350,25 @@ size_t contacts_ws_bytes(int32_t n, int32_t cap) {
     (void)cap;
     const size_t nn = static_cast<size_t>(n), nb = cell_budget(n);
     size_t b = 0;
-    b += align_up(kFlagCount * sizeof(int), 256) + 256;     // flags
-    b += 256;                                                // max extent
-    b += 3 * align_up(nn * sizeof(int), 256);                // cell_of, members, j fill
+    b += align_up(kFlagCount * sizeof(int), 256) + 256;     // flags, max extent
+    b += 5 * align_up(nn * sizeof(int), 256);                // cell_of, members, cell_r, deg, fill
+    b += align_up(4 * nn * sizeof(double), 256);             // ranked centre + radius
+    b += align_up(nn * sizeof(double), 256);                 // ranked half length
     b += 2 * align_up((nb + 1) * sizeof(int), 256);          // cell_start, cell_fill
     const size_t sn = (nn + 1 > nb + 1 ? nn + 1 : nb + 1);
     b += align_up(static_cast<size_t>(scan_tmp_ints(static_cast<int>(sn))) * sizeof(int), 256);
     b += 256;                                                // host-read staging
-    return b + 1024;
+    return b + 2048;
 }
 
 }  // namespace sc
 
 using namespace sc;
+
+extern "C" size_t sc_plan_bytes(int32_t n, int32_t capacity) {
+    if (n < 0 || capacity < 0) return 0;
+    return plan_bytes(n, capacity);
+}
 
 extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, double delta,
                                  const double *u_nc, double dt, sc_contacts *c, void *ws,
@@ -291,16 +383,17 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     c->n_parallel = c->n_zero_dist = c->n_borderline = 0;
     c->grid[0] = c->grid[1] = c->grid[2] = 0;
     const int n = p->n;
-    if (!c->i_ptr || !c->j_ptr) return SC_ERR_INVALID;
+    Plan pl;
+    if (!carve_plan(c->plan, c->plan_bytes, n, c->capacity, pl)) return SC_ERR_INVALID;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     if (n == 0) {
-        SC_HIP_TRY(hipMemsetAsync(c->i_ptr, 0, sizeof(int), stream));
-        SC_HIP_TRY(hipMemsetAsync(c->j_ptr, 0, sizeof(int), stream));
+        SC_HIP_TRY(hipMemsetAsync(pl.cptr, 0, sizeof(int), stream));
+        SC_HIP_TRY(hipMemsetAsync(pl.inc_ptr, 0, sizeof(int), stream));
         SC_HIP_TRY(hipStreamSynchronize(stream));
         return SC_OK;
     }
     if (!p->pos || !p->axis || !p->radius || !p->half_len || !p->mob || !u_nc) return SC_ERR_INVALID;
-    if (c->capacity > 0 && (!c->ci || !c->cj || !c->phi || !c->q || !c->frame || !c->j_list))
+    if (c->capacity > 0 && (!c->ci || !c->cj || !c->phi || !c->q || !c->frame))
         return SC_ERR_INVALID;
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return SC_ERR_WORKSPACE;
     if (ws_bytes < contacts_ws_bytes(n, c->capacity)) return SC_ERR_WORKSPACE;
@@ -311,7 +404,11 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     unsigned long long *max_ext = cv.take<unsigned long long>(1);
     int *cell_of = cv.take<int>(n);
     int *members = cv.take<int>(n);
-    int *jfill = cv.take<int>(n);
+    int *cell_r = cv.take<int>(n);
+    int *deg = cv.take<int>(n);
+    int *fill = cv.take<int>(n);
+    double *prec = cv.take<double>(4 * static_cast<size_t>(n));
+    double *hl = cv.take<double>(n);
     int *cell_start = cv.take<int>(nb + 1);
     int *cell_fill = cv.take<int>(nb + 1);
     const int sn = static_cast<int>((static_cast<size_t>(n) + 1 > nb + 1) ? n + 1 : nb + 1);
@@ -337,7 +434,6 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     }
     const double rmax = 2.0 * ext + delta;
     Grid g{};
-    size_t ncell = 1;
     for (int a = 0; a < 3; ++a) {
         g.lo[a] = box->lo[a];
         g.len[a] = box->len[a];
@@ -350,7 +446,7 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
         int a = (g.nc[0] >= g.nc[1] && g.nc[0] >= g.nc[2]) ? 0 : (g.nc[1] >= g.nc[2] ? 1 : 2);
         g.nc[a] = g.nc[a] > 1 ? (g.nc[a] + 1) / 2 : 1;
     }
-    ncell = static_cast<size_t>(g.nc[0]) * g.nc[1] * g.nc[2];
+    const size_t ncell = static_cast<size_t>(g.nc[0]) * g.nc[1] * g.nc[2];
     for (int a = 0; a < 3; ++a) {
         g.side[a] = box->len[a] / g.nc[a];
         c->grid[a] = g.nc[a];
@@ -358,18 +454,20 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     g.periodic = box->periodic ? 1 : 0;
     g.delta = delta;
 
-    // bin particles, then sort them by cell (order within a cell is free)
+    // bin particles and rank them in cell order
     SC_HIP_TRY(hipMemsetAsync(cell_start, 0, (ncell + 1) * sizeof(int), stream));
     SC_HIP_TRY(hipMemsetAsync(cell_fill, 0, ncell * sizeof(int), stream));
     k_bin<<<grid_for(n), kBlock, 0, stream>>>(P, g, cell_of, cell_start);
     scan_exclusive(cell_start, cell_start, static_cast<int>(ncell), scan_tmp, stream);
     k_scatter<<<grid_for(n), kBlock, 0, stream>>>(n, cell_of, cell_start, cell_fill, members);
+    k_rank<<<grid_for(n), kBlock, 0, stream>>>(P, cell_of, cell_start, members, pl, prec, hl,
+                                               cell_r);
+    Ranked R{prec, hl, cell_r};
 
-    // count close partners per i, then offsets
-    k_count_pairs<<<grid_for(n), kBlock, 0, stream>>>(P, g, cell_of, cell_start, members,
-                                                      c->i_ptr, flags);
-    scan_exclusive(c->i_ptr, c->i_ptr, n, scan_tmp, stream);
-    SC_HIP_TRY(hipMemcpyAsync(stage, c->i_ptr + n, sizeof(int), hipMemcpyDeviceToDevice, stream));
+    // partners of higher rank, then offsets
+    k_count_pairs<<<grid_for(n), kBlock, 0, stream>>>(n, R, pl, g, cell_start, flags);
+    scan_exclusive(pl.cptr, pl.cptr, n, scan_tmp, stream);
+    SC_HIP_TRY(hipMemcpyAsync(stage, pl.cptr + n, sizeof(int), hipMemcpyDeviceToDevice, stream));
     SC_HIP_TRY(hipMemcpyAsync(stage + 1, flags, kFlagCount * sizeof(int), hipMemcpyDeviceToDevice,
                               stream));
     int hstage[1 + kFlagCount];
@@ -382,22 +480,19 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     c->n_borderline = hstage[1 + kFlagBorder];
     if (nc > c->capacity) return SC_ERR_CAPACITY;
 
-    const long long cap = c->capacity;
-    k_write_pairs<<<grid_for(n), kBlock, 0, stream>>>(P, g, cell_of, cell_start, members,
-                                                      c->i_ptr, c->ci, c->cj, c->phi, c->frame,
-                                                      cap);
-    // j-side incidence: contacts l with cj[l] == k, ascending
-    SC_HIP_TRY(hipMemsetAsync(c->j_ptr, 0, (n + 1) * sizeof(int), stream));
-    SC_HIP_TRY(hipMemsetAsync(jfill, 0, n * sizeof(int), stream));
+    k_write_pairs<<<grid_for(n), kBlock, 0, stream>>>(n, R, pl, g, cell_start, c->ci, c->cj,
+                                                      c->phi, c->frame);
+    // incidence lists and signed column entries
+    SC_HIP_TRY(hipMemsetAsync(deg, 0, n * sizeof(int), stream));
+    SC_HIP_TRY(hipMemsetAsync(fill, 0, n * sizeof(int), stream));
+    if (nc > 0) k_second_degree<<<grid_for(nc), kBlock, 0, stream>>>(nc, pl, deg);
+    k_inc_counts<<<grid_for(n), kBlock, 0, stream>>>(n, pl, deg);
+    scan_exclusive(pl.inc_ptr, pl.inc_ptr, n, scan_tmp, stream);
     if (nc > 0) {
-        k_j_degree<<<grid_for(nc), kBlock, 0, stream>>>(nc, c->cj, c->j_ptr);
-    }
-    scan_exclusive(c->j_ptr, c->j_ptr, n, scan_tmp, stream);
-    if (nc > 0) {
-        k_j_fill<<<grid_for(nc), kBlock, 0, stream>>>(nc, c->cj, c->j_ptr, jfill, c->j_list);
-        k_j_sort<<<grid_for(n), kBlock, 0, stream>>>(n, c->j_ptr, c->j_list);
-        k_q<<<grid_for(nc), kBlock, 0, stream>>>(nc, c->ci, c->cj, c->phi, c->frame, cap, u_nc,
-                                                 dt, c->q, flags);
+        k_inc_fill<<<grid_for(nc), kBlock, 0, stream>>>(nc, pl, fill);
+        k_inc_finish<<<grid_for(n), kBlock, 0, stream>>>(n, pl, c->frame);
+        k_q<<<grid_for(nc), kBlock, 0, stream>>>(nc, c->ci, c->cj, c->phi, c->frame, u_nc, dt,
+                                                 c->q, flags);
     }
     SC_HIP_TRY(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, stream));
     SC_HIP_TRY(hipStreamSynchronize(stream));
