@@ -36,6 +36,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="particle-count scale (tests)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -49,6 +51,16 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8,
+                          "launches": 5}), flush=True)
+        return
     s = W.workload(2, scale=args.scale)
     print(f"[bench] workload {s.name}: N={s.n}, box {s.box[0]:.4f}", file=sys.stderr, flush=True)
     P = sc.Particles.from_suspension(s)
