@@ -21,11 +21,19 @@ HBM_PEAK_GBS = 8000.0
 
 
 def rod_iteration_bytes(nc, n):
-    """Algorithmic bytes of one BBPGD iteration on a rod system: per contact
-    the 80-byte frame record read in both passes, 8 bytes of incidence and
-    48 bytes of gamma/g/q traffic; per particle U written and read (96) and
-    the axis (24)."""
+    """Algorithmic bytes of one matrix-free BBPGD iteration on a rod system:
+    per contact the 80-byte frame record read in both passes, 8 bytes of
+    incidence and 48 bytes of gamma/g/q traffic; per particle U written and
+    read (96) and the axis (24)."""
     return 216 * nc + 120 * n
+
+
+def matrix_iteration_bytes(nc, nnz):
+    """Algorithmic bytes of one BBPGD iteration on the assembled M: each
+    nonzero's column index and value (12), and per row its offset (4), q (8)
+    and gamma, g read and written (32). Column gathers of gamma and g are
+    reuse of rows already counted."""
+    return 12 * nnz + 44 * nc
 
 
 def main():
@@ -101,10 +109,14 @@ def main():
         g_out = sc.solve_lcp(P, con, tol=s.tol, workspace=ws)
     torch.cuda.synchronize()
     solve_ms = 1e3 * (time.perf_counter() - t1) / args.steps
+    # the matrix-free two-pass product on the same contacts, for comparison
+    chain = sc.solve_lcp(P, con, tol=s.tol, workspace=ws, op=1)[2]
 
     st = stats[-1]
     iters = st["iters"]
-    bytes_iter = rod_iteration_bytes(con.count, s.n)
+    used_matrix = st["op"] == 2
+    bytes_iter = (matrix_iteration_bytes(con.count, con.nnz) if used_matrix
+                  else rod_iteration_bytes(con.count, s.n))
     kernel_ms = float(np.median([x["kernel_ms"] for x in stats]))
     per_iter_s = kernel_ms * 1e-3 / max(1, iters + 2)
     achieved = bytes_iter / per_iter_s / 1e9
@@ -156,12 +168,19 @@ def main():
                    "mvops": st["mvops"], "n_active": st["n_active"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_bbpgd (persistent BBPGD solve; per launch = "
-                               "iterations + 2 products)",
+                     "kernel": ("k_bbpgd_mat" if used_matrix else "k_bbpgd")
+                               + " (persistent BBPGD solve; per launch = iterations + 2 "
+                               "products)",
+                     "bytes_model": ("12 nnz + 44 n_c" if used_matrix
+                                     else "216 n_c + 120 N"),
                      "bytes_per_iter": bytes_iter, "us_per_iter": per_iter_s * 1e6,
                      "kernel_ms": kernel_ms, "grid": st["grid"], "block": st["block"],
                      "lanes_per_particle": st["lanes_per_particle"]},
         "cpu_baseline": cpu,
+        "chain_solve": {"iters": chain["iters"], "kernel_ms": chain["kernel_ms"],
+                        "us_per_iter": 1e3 * chain["kernel_ms"] / (chain["iters"] + 2)},
+        "operator": "assembled M" if st["op"] == 2 else "matrix-free chain",
+        "nnz_M": con.nnz,
         "build_ms": build_ms,
         "solve_ms": solve_ms,
         "solve_only_rods_per_s": s.n / (solve_ms * 1e-3),

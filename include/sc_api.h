@@ -108,18 +108,36 @@ typedef struct sc_contacts {
     int32_t n_zero_dist;    /* OUT (host): pairs with coincident cores (n := +x) */
     int32_t n_borderline;   /* OUT (host): pairs with |Phi - delta| < 1e-12 */
     int32_t grid[3];        /* OUT (host): search cells per axis used */
+    int64_t nnz;            /* OUT (host): nonzeros of M = D^T Mob D (set by build) */
+    void *mat;              /* optional device buffer of sc_matrix_bytes(count, nnz)
+                               bytes (256-byte aligned) for the assembled M */
+    size_t mat_bytes;
+    int32_t mat_ready;      /* OUT (host): 1 once sc_assemble_matrix filled mat */
+    int32_t reserved;
 } sc_contacts;
+
+#define SC_OP_AUTO   0      /* assembled M if c->mat_ready, else the matrix-free chain */
+#define SC_OP_CHAIN  1      /* matrix-free: gather D x, apply Mob, gather D^T U */
+#define SC_OP_MATRIX 2      /* assembled sparse M (requires c->mat_ready) */
 
 typedef struct sc_solve_opts {
     double tol;             /* absolute tolerance on ||min(gamma, g)||_2 (> 0) */
     int32_t max_iter;       /* j_max of Algorithm 1 (>= 0) */
     int32_t bb;             /* step rule: 1 = BB1, 2 = BB2, 3 = BB1 odd / BB2 even */
     int32_t warm_start;     /* 1: gamma holds gamma_0 on entry; 0: gamma_0 = 0 */
-    int32_t lanes_per_particle; /* 0 (default 4), 1, 2, 4 or 8: lanes sharing a particle's
-                                   incidence list in the gather pass */
+    int32_t lanes_per_particle; /* chain product: 0 (default 4), 1, 2, 4 or 8 lanes sharing
+                                   a particle's incidence list */
     int32_t grid;           /* workgroups of the persistent kernel (0 = one per CU;
-                               clamped to what is co-resident) */
-    int32_t block;          /* threads per workgroup: 0 (default 1024), 256 or 1024 */
+                               clamped to at most one per CU and to what is
+                               co-resident) */
+    int32_t block;          /* threads per workgroup: 0 (default 1024), 256, 512 or 1024 */
+    int32_t op;             /* product M x: SC_OP_AUTO (assembled M when ready, else the
+                               matrix-free chain), SC_OP_CHAIN or SC_OP_MATRIX */
+    int32_t slices_per_wave; /* assembled-M product: 0 (default 1), 1, 2 or 4 slices of 64
+                                rows that one wave works on at once */
+    int32_t lds_entries_per_wave; /* assembled-M product: entries of M each wave keeps in
+                                LDS for the whole solve; 0 = as many as fit, -1 = none,
+                                > 0 = at most that many */
     int32_t reserved;
 } sc_solve_opts;
 
@@ -133,8 +151,12 @@ typedef struct sc_stats {
     int32_t n_degenerate;   /* step sizes kept because a BB denominator was <= 0 */
     int32_t grid;           /* workgroups of the persistent kernel used */
     double kernel_ms;       /* GPU time of the persistent kernel (HIP events on `stream`) */
-    int32_t lanes_per_particle; /* gather lanes per particle used */
+    int32_t lanes_per_particle; /* gather lanes per particle (chain; 0 for the matrix) */
     int32_t block;          /* threads per workgroup used */
+    int32_t op;             /* SC_OP_CHAIN or SC_OP_MATRIX: the product used */
+    int32_t slices_per_wave; /* slices per wave (matrix; 0 for the chain) */
+    int32_t lds_entries_per_wave; /* entries of M per wave held in LDS (matrix) */
+    int32_t reserved;
 } sc_stats;
 
 typedef struct sc_adjoint_opts {
@@ -143,6 +165,9 @@ typedef struct sc_adjoint_opts {
     int32_t lanes_per_particle; /* as in sc_solve_opts */
     int32_t grid;           /* as in sc_solve_opts */
     int32_t block;          /* as in sc_solve_opts */
+    int32_t op;             /* as in sc_solve_opts */
+    int32_t slices_per_wave; /* as in sc_solve_opts */
+    int32_t lds_entries_per_wave; /* as in sc_solve_opts */
 } sc_adjoint_opts;
 
 /* ---------------------------------------------------------------- calls */
@@ -154,6 +179,11 @@ size_t sc_workspace_bytes(int32_t n, int32_t capacity);
 /* Bytes of the plan buffer of sc_contacts for n particles and `capacity`
  * contact rows. Pure host arithmetic. */
 size_t sc_plan_bytes(int32_t n, int32_t capacity);
+
+/* Bytes of the assembled-matrix buffer for `count` contact rows and `nnz`
+ * nonzeros (both as reported in sc_contacts after sc_build_contacts). Pure
+ * host arithmetic; 0 if nnz does not fit 32-bit column offsets. */
+size_t sc_matrix_bytes(int32_t count, int64_t nnz);
 
 /* u[k] = Mob_k f[k] for every particle (the dry block-diagonal mobility that
  * stands in for the paper's mobility solve, section 2). f, u: [n][6].
@@ -173,6 +203,17 @@ int sc_apply_mobility(const sc_particles *p, const double *f, double *u,
 int sc_build_contacts(const sc_particles *p, const sc_box *box, double delta,
                       const double *u_nc, double dt, sc_contacts *c,
                       void *ws, size_t ws_bytes, void *stream);
+
+/* Assemble M = D^T Mob D (LCP LCPdef) into c->mat as a sparse matrix with
+ * one row per contact: row l holds M_lm for every contact m sharing a
+ * particle with l (deg(ci) + deg(cj) - 1 entries, the diagonal first; rows
+ * are stored in slices of 64, each slice depth by depth, layout private),
+ * M_lm = a_lk^T Mob_k a_mk with a_lk the signed column entries of contact l
+ * on the shared particle k. For a block-diagonal mobility this is exact and
+ * replaces the two-pass product inside the solve. Requires a prior
+ * sc_build_contacts and c->mat_bytes >= sc_matrix_bytes(count, nnz); sets
+ * c->mat_ready. Synchronises `stream`. */
+int sc_assemble_matrix(const sc_particles *p, sc_contacts *c, void *stream);
 
 /* y = M x = D^T Mob D x for x, y of c->count entries: one matrix-free
  * product ("MVOP", LCP LCPdef and section 6.2). Does not synchronise. */

@@ -19,6 +19,10 @@ SC_ERR_HIP = -5
 SC_ERR_WORKSPACE = -6
 SC_ERR_TIMEOUT = -7
 
+SC_OP_AUTO = 0
+SC_OP_CHAIN = 1
+SC_OP_MATRIX = 2
+
 c_dp = ctypes.c_void_p  # device pointers travel as plain addresses
 
 
@@ -38,14 +42,18 @@ class sc_contacts(ctypes.Structure):
                 ("ci", c_dp), ("cj", c_dp), ("phi", c_dp), ("q", c_dp),
                 ("frame", c_dp), ("plan", c_dp), ("plan_bytes", ctypes.c_size_t),
                 ("n_parallel", ctypes.c_int32), ("n_zero_dist", ctypes.c_int32),
-                ("n_borderline", ctypes.c_int32), ("grid", ctypes.c_int32 * 3)]
+                ("n_borderline", ctypes.c_int32), ("grid", ctypes.c_int32 * 3),
+                ("nnz", ctypes.c_int64), ("mat", c_dp), ("mat_bytes", ctypes.c_size_t),
+                ("mat_ready", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class sc_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("bb", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("lanes_per_particle", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("block", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("slices_per_wave", ctypes.c_int32), ("lds_entries_per_wave", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class sc_stats(ctypes.Structure):
@@ -54,22 +62,27 @@ class sc_stats(ctypes.Structure):
                 ("residual", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("n_degenerate", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double), ("lanes_per_particle", ctypes.c_int32),
-                ("block", ctypes.c_int32)]
+                ("block", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("slices_per_wave", ctypes.c_int32), ("lds_entries_per_wave", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
 
 
 class sc_adjoint_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("lanes_per_particle", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("block", ctypes.c_int32)]
+                ("block", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("slices_per_wave", ctypes.c_int32), ("lds_entries_per_wave", ctypes.c_int32)]
 
 
 P = ctypes.POINTER
 SIGNATURES = {
     "sc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "sc_plan_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "sc_matrix_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64]),
+    "sc_assemble_matrix": (ctypes.c_int, [P(sc_particles), P(sc_contacts), c_dp]),
     "sc_apply_mobility": (ctypes.c_int, [P(sc_particles), c_dp, c_dp, c_dp]),
     "sc_build_contacts": (ctypes.c_int, [P(sc_particles), P(sc_box), ctypes.c_double,
                                          c_dp, ctypes.c_double, P(sc_contacts), c_dp,

@@ -134,6 +134,11 @@ class Contacts:
         self.count = 0
         self.n_parallel = self.n_zero_dist = self.n_borderline = 0
         self.grid = (0, 0, 0)
+        self.nnz = 0
+        self._mat = None
+        self.mat_ptr = 0
+        self.mat_bytes = 0
+        self.mat_ready = 0
 
     def c(self):
         s = A.sc_contacts()
@@ -146,6 +151,10 @@ class Contacts:
         s.n_parallel = self.n_parallel
         s.n_zero_dist = self.n_zero_dist
         s.n_borderline = self.n_borderline
+        s.nnz = self.nnz
+        s.mat = self.mat_ptr
+        s.mat_bytes = self.mat_bytes
+        s.mat_ready = self.mat_ready
         return s
 
     def _take(self, s):
@@ -154,6 +163,24 @@ class Contacts:
         self.n_zero_dist = int(s.n_zero_dist)
         self.n_borderline = int(s.n_borderline)
         self.grid = tuple(int(g) for g in s.grid)
+        self.nnz = int(s.nnz)
+        self.mat_ready = int(s.mat_ready)
+
+    def assemble(self, particles):
+        """Assemble M = D^T Mob D into a device buffer owned by this object."""
+        mb = int(A.lib().sc_matrix_bytes(self.count, self.nnz))
+        if mb == 0:
+            raise RuntimeError(f"M with {self.nnz} nonzeros cannot be assembled")
+        if self._mat is None or self.mat_bytes < mb:
+            self._mat = torch.empty(mb + 256, dtype=torch.uint8, device="cuda")
+            addr = self._mat.data_ptr()
+            self.mat_ptr = (addr + 255) // 256 * 256
+            self.mat_bytes = mb + 256 - (self.mat_ptr - addr)
+        pc, cc = particles.c(), self.c()
+        _check("sc_assemble_matrix",
+               A.lib().sc_assemble_matrix(ctypes.byref(pc), ctypes.byref(cc), _stream()))
+        self._take(cc)
+        return self
 
     # views of the first `count` rows
     @property
@@ -195,9 +222,10 @@ def apply_mobility(particles: Particles, f: torch.Tensor) -> torch.Tensor:
 
 def build_contacts(particles: Particles, box: Box, delta: float, u_nc: torch.Tensor,
                    dt: float, capacity: Optional[int] = None,
-                   workspace: Optional[Workspace] = None) -> Contacts:
-    """Close-pair set, contact frames, incidence and q (grows the contact
-    arrays and retries when the capacity is too small)."""
+                   workspace: Optional[Workspace] = None, assemble: bool = True) -> Contacts:
+    """Close-pair set, contact frames, solver layout and q (grows the contact
+    arrays and retries when the capacity is too small); with ``assemble``
+    also forms the sparse M = D^T Mob D used by the one-pass solve."""
     u_nc = _dev(u_nc)
     ws = workspace or default_workspace()
     n = particles.n
@@ -215,6 +243,8 @@ def build_contacts(particles: Particles, box: Box, delta: float, u_nc: torch.Ten
             cap = int(cc.count)
             continue
         _check("sc_build_contacts", rc)
+        if assemble:
+            con.assemble(particles)
         return con
 
 
@@ -234,8 +264,9 @@ def mvop(particles: Particles, contacts: Contacts, x: torch.Tensor,
 def solve_lcp(particles: Particles, contacts: Contacts, tol: float = 1e-6,
               max_iter: int = 100000, bb: int = 1, gamma0: Optional[torch.Tensor] = None,
               want_fc: bool = False, lanes_per_particle: int = 0, grid: int = 0,
-              block: int = 0, workspace: Optional[Workspace] = None,
-              raise_on_nonconverged=False):
+              block: int = 0, op: int = 0, workspace: Optional[Workspace] = None,
+              raise_on_nonconverged=False, slices_per_wave: int = 0,
+              lds_entries_per_wave: int = 0):
     """BBPGD (Algorithm 1). Returns (gamma, g, stats dict, f_c, u_c); f_c and
     u_c are None unless want_fc."""
     nc = contacts.count
@@ -248,7 +279,8 @@ def solve_lcp(particles: Particles, contacts: Contacts, tol: float = 1e-6,
         f_c = torch.empty((particles.n, 6), dtype=torch.float64, device="cuda")
         u_c = torch.empty((particles.n, 6), dtype=torch.float64, device="cuda")
     opts = A.sc_solve_opts(float(tol), int(max_iter), int(bb), 1 if gamma0 is not None else 0,
-                           int(lanes_per_particle), int(grid), int(block), 0)
+                           int(lanes_per_particle), int(grid), int(block), int(op),
+                           int(slices_per_wave), int(lds_entries_per_wave), 0)
     st = A.sc_stats()
     ws = workspace or default_workspace()
     wsp, wsn = ws.get(particles.n, contacts.capacity)
@@ -267,7 +299,8 @@ def solve_lcp_adjoint(particles: Particles, box: Box, contacts: Contacts,
                       dL_dgamma: Optional[torch.Tensor] = None,
                       dL_df: Optional[torch.Tensor] = None, tol: float = 1e-10,
                       max_iter: int = 100000, lanes_per_particle: int = 0, grid: int = 0,
-                      block: int = 0, workspace: Optional[Workspace] = None):
+                      block: int = 0, op: int = 0, workspace: Optional[Workspace] = None,
+                      slices_per_wave: int = 0, lds_entries_per_wave: int = 0):
     """Implicit adjoint of a converged solve: returns (dL_dq, dL_dpos, stats)."""
     nc = contacts.count
     u_nc = _dev(u_nc)
@@ -277,7 +310,8 @@ def solve_lcp_adjoint(particles: Particles, box: Box, contacts: Contacts,
     dq = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
     dpos = torch.empty((particles.n, 3), dtype=torch.float64, device="cuda")
     opts = A.sc_adjoint_opts(float(tol), int(max_iter), int(lanes_per_particle), int(grid),
-                             int(block))
+                             int(block), int(op), int(slices_per_wave),
+                             int(lds_entries_per_wave))
     st = A.sc_stats()
     ws = workspace or default_workspace()
     wsp, wsn = ws.get(particles.n, contacts.capacity)

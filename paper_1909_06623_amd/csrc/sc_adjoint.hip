@@ -18,17 +18,13 @@
 #include "sc_chain.hpp"
 #include "sc_common.hpp"
 #include "sc_geometry.hpp"
+#include "sc_matrix.hpp"
 #include "sc_plan.hpp"
 #include "sc_sync.hpp"
 
 namespace sc {
 
 namespace {
-
-struct CgCtrl {
-    double alpha, res;
-    int iters, status, n_active, pad;
-};
 
 struct CgArgs {
     ChainView C;
@@ -140,11 +136,12 @@ __global__ void __launch_bounds__(BS) k_cg(CgArgs A) {
     }
 }
 
-// r0 = mask(b) with b = dL/dgamma + D^T dL/dF (dL/dF in caller order); the
-// active set is counted on the way.
+// r0 = mask(b) with b = dL/dgamma + D^T dL/dF (dL/dF in caller order),
+// written with a stride (1 for a plain vector, 4 into (r, w, s, pad)
+// records); the active set is counted on the way.
 __global__ void k_cg_rhs(int nc, const int *ci, const int *cj, const double *frame,
                          const double *gamma, const double *dLdg, const double *dLdF, double *r,
-                         int *n_active) {
+                         int stride, int *n_active) {
     int cnt = 0;
     for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < nc; l += gridDim.x * blockDim.x) {
         const bool act = gamma[l] > 0.0;
@@ -156,7 +153,7 @@ __global__ void k_cg_rhs(int nc, const int *ci, const int *cj, const double *fra
             b += -dot(load3(f), load3(ui)) - dot(load3(f + 3), load3(ui + 3)) +
                  dot(load3(f), load3(uj)) + dot(load3(f + 6), load3(uj + 3));
         }
-        r[l] = act ? b : 0.0;
+        r[static_cast<long long>(l) * stride] = act ? b : 0.0;
         cnt += act;
     }
     for (int off = kWave / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
@@ -273,7 +270,8 @@ CgKernel cg_kernel_bs(int lpp) {
 }
 
 CgKernel cg_kernel(int lpp, int block) {
-    return block == 256 ? cg_kernel_bs<256>(lpp) : cg_kernel_bs<1024>(lpp);
+    return block == 256 ? cg_kernel_bs<256>(lpp)
+                        : block == 512 ? cg_kernel_bs<512>(lpp) : cg_kernel_bs<1024>(lpp);
 }
 
 }  // namespace
@@ -281,7 +279,8 @@ CgKernel cg_kernel(int lpp, int block) {
 size_t adjoint_ws_bytes(int32_t n, int32_t cap) {
     const size_t nn = static_cast<size_t>(n), cc = static_cast<size_t>(cap);
     size_t b = 0;
-    b += 7 * align_up(cc * sizeof(double), 256);        // r[2], s[2], p, x, w
+    b += align_up(8 * cc * sizeof(double), 256);        // CG vectors or (r, w, s) records
+    b += 2 * align_up(cc * sizeof(double), 256);        // p, x
     b += align_up(3 * cc * sizeof(double), 256);        // grad
     b += 3 * align_up(8 * nn * sizeof(double), 256);    // U, Vw, Uc (rank order)
     b += align_up(4 * kMaxReduceBlocks * sizeof(double), 256);
@@ -304,11 +303,14 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
         c->count > c->capacity)
         return SC_ERR_INVALID;
     if (!(dt > 0.0) || !(opts->tol > 0.0) || opts->max_iter < 0 ||
-        opts->lanes_per_particle < 0 || opts->lanes_per_particle > 8 || opts->grid < 0 ||
-        (opts->block != 0 && opts->block != 256 && opts->block != 1024))
+        !lanes_ok(opts->lanes_per_particle) || !spw_ok(opts->slices_per_wave) ||
+        opts->lds_entries_per_wave < -1 || opts->grid < 0 ||
+        !block_ok(opts->block) || opts->op < 0 ||
+        opts->op > SC_OP_MATRIX || (opts->op == SC_OP_MATRIX && !c->mat_ready))
         return SC_ERR_INVALID;
     *st = sc_stats{};
     const int n = p->n, nc = c->count;
+    const bool use_mat = opts->op == SC_OP_MATRIX || (opts->op == SC_OP_AUTO && c->mat_ready);
     Plan pl;
     if (!carve_plan(c->plan, c->plan_bytes, n, c->capacity, pl)) return SC_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream_);
@@ -326,9 +328,12 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     }
     const long long cap = c->capacity;
     Carver cv{static_cast<char *>(ws), ws_bytes};
-    double *r0 = cv.take<double>(cap), *r1 = cv.take<double>(cap);
-    double *s0 = cv.take<double>(cap), *s1 = cv.take<double>(cap);
-    double *pv = cv.take<double>(cap), *x = cv.take<double>(cap), *wv = cv.take<double>(cap);
+    // one contiguous block: the chain CG's vectors r0 r1 s0 s1 w, or the
+    // matrix CG's two arrays of (r, w, s, pad) records
+    double *zrec = cv.take<double>(8 * cap);
+    double *r0 = zrec, *r1 = zrec + cap, *s0 = zrec + 2 * cap, *s1 = zrec + 3 * cap;
+    double *wv = zrec + 4 * cap;
+    double *pv = cv.take<double>(cap), *x = cv.take<double>(cap);
     double *grad = cv.take<double>(3 * cap);
     double *U = cv.take<double>(8 * static_cast<size_t>(n));
     double *Vw = cv.take<double>(8 * static_cast<size_t>(n));
@@ -338,11 +343,14 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     CgCtrl *ctrl = cv.take<CgCtrl>(1);
     if (!cv.ok) return SC_ERR_WORKSPACE;
 
-    int lpp = opts->lanes_per_particle ? opts->lanes_per_particle : 4;
-    if (lpp != 1 && lpp != 2 && lpp != 4 && lpp != 8) return SC_ERR_INVALID;
+    const int lpp = opts->lanes_per_particle ? opts->lanes_per_particle : 4;
+    const int spw = opts->slices_per_wave ? opts->slices_per_wave : 1;
+    int cache_used = 0;
     const int block = opts->block ? opts->block : 1024;
+    MatBufs mb{};
+    if (use_mat && !carve_matrix(c->mat, c->mat_bytes, nc, c->nnz, mb)) return SC_ERR_INVALID;
     CgKernel kern = cg_kernel(lpp, block);
-    const int G = persistent_grid(reinterpret_cast<const void *>(kern), block, opts->grid);
+    int G = use_mat ? 1 : persistent_grid(reinterpret_cast<const void *>(kern), block, opts->grid);
     if (G < 1) return SC_ERR_HIP;
 
     SC_HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(CgCtrl), s));
@@ -352,8 +360,9 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     SC_HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * nc, s));
     int nb = grid_for(nc);
     if (nb > kMaxReduceBlocks) nb = kMaxReduceBlocks;
+    if (use_mat) SC_HIP_TRY(hipMemsetAsync(zrec, 0, sizeof(double) * 4 * nc, s));
     k_cg_rhs<<<nb, kBlock, 0, s>>>(nc, c->ci, c->cj, c->frame, gamma, dL_dgamma, dL_df, r0,
-                                   &ctrl->n_active);
+                                   use_mat ? 4 : 1, &ctrl->n_active);
     CgArgs A;
     A.C = chain_view(p, c, pl, U);
     A.gamma = gamma;
@@ -370,8 +379,14 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     A.tol = opts->tol;
     A.max_iter = opts->max_iter;
     void *args[] = {&A};
-    SC_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G),
-                                          dim3(block), args, 0, s));
+    if (use_mat) {
+        SC_HIP_TRY(launch_cg_mat(mat_view(nc, mb), gamma, zrec, pv, x, part, sync, ctrl,
+                                 opts->tol, opts->max_iter, spw, opts->lds_entries_per_wave,
+                                 block, opts->grid, s, &G, &cache_used));
+    } else {
+        SC_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G),
+                                              dim3(block), args, 0, s));
+    }
     // dL/dq = -w on A; V_w = Mob D w; U_c = Mob D gamma; geometric terms
     k_neg_masked<<<grid_for(nc), kBlock, 0, s>>>(nc, gamma, x, dL_dq);
     ChainView Cv = chain_view(p, c, pl, Vw), Cc = chain_view(p, c, pl, Uc);
@@ -394,6 +409,9 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     st->alpha = hc.alpha;
     st->grid = G;
     st->block = block;
-    st->lanes_per_particle = lpp;
+    st->lanes_per_particle = use_mat ? 0 : lpp;
+    st->slices_per_wave = use_mat ? spw : 0;
+    st->lds_entries_per_wave = cache_used;
+    st->op = use_mat ? SC_OP_MATRIX : SC_OP_CHAIN;
     return hc.status;
 }

@@ -18,6 +18,18 @@
 
 namespace sc {
 
+// Results of a persistent solve, written by workgroup 0.
+struct SolveCtrl {
+    double alpha, res;
+    int iters, mvops, status, ndegen;
+    int n_active, pad[3];
+};
+
+struct CgCtrl {
+    double alpha, res;
+    int iters, status, n_active, pad;
+};
+
 struct ChainView {
     int n, nc;
     const double *pdat;    // [n][8]
@@ -94,54 +106,57 @@ __device__ __forceinline__ double dt_u(const ChainView &C, int l) {
            (f[6] * Uj[3] + f[7] * Uj[4] + f[8] * Uj[5]);
 }
 
-// Workgroup sum of NV values (slot MAXSLOT, if >= 0, is a max), returned to
-// every thread through LDS. Fixed order.
-template <int NV, int BS, int MAXSLOT = -1>
-__device__ __forceinline__ void block_reduce_all(double (&v)[NV]) {
-    __shared__ double red[NV][BS / kWave];
-    __shared__ double out[NV];
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = (k == MAXSLOT) ? wave_max(v[k]) : wave_sum(v[k]);
-    if (lane == 0)
-        for (int k = 0; k < NV; ++k) red[k][wid] = v[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < NV; ++k) {
-            double s = red[k][0];
-            for (int w = 1; w < BS / kWave; ++w)
-                s = (k == MAXSLOT) ? fmax(s, red[k][w]) : s + red[k][w];
-            out[k] = s;
-        }
-    }
-    __syncthreads();
-    for (int k = 0; k < NV; ++k) v[k] = out[k];
-    __syncthreads();
-}
+// Grid-wide reductions, in two halves around a grid barrier. Slot MAXSLOT
+// (if >= 0) is a maximum, the others are sums; every order is fixed, so all
+// workgroups compute bitwise identical totals and take identical decisions.
 
-// Grid-wide reduction of the per-workgroup partials written before the last
-// barrier: part[L * NV + k] for logical workgroups L = 0..G-1, summed in the
-// same fixed order by every workgroup, so all of them take identical
-// control decisions.
-template <int NV, int BS, int MAXSLOT = -1>
-__device__ __forceinline__ void grid_reduce(const double *part, double (&tot)[NV]) {
-    const int G = gridDim.x;
-    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
-    for (int L = threadIdx.x; L < G; L += BS)
-        for (int k = 0; k < NV; ++k) {
-            const double x = part[L * NV + k];
-            tot[k] = (k == MAXSLOT) ? fmax(tot[k], x) : tot[k] + x;
-        }
-    block_reduce_all<NV, BS, MAXSLOT>(tot);
-}
-
+// Before the barrier: the workgroup's NV partials (wave butterflies, then
+// one wave over the per-wave results) go to part[L * NV + k] for logical
+// workgroup L.
 template <int NV, int BS, int MAXSLOT = -1>
 __device__ __forceinline__ void write_partial(double *part, double (&acc)[NV]) {
-    block_reduce_all<NV, BS, MAXSLOT>(acc);
-    if (threadIdx.x == 0) {
-        const int L = logical_block();
-        for (int k = 0; k < NV; ++k) part[L * NV + k] = acc[k];
+    constexpr int NW = BS / kWave;
+    __shared__ double red[NV][NW];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = (k == MAXSLOT) ? wave_max(acc[k]) : wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[k][wid] = acc[k];
     }
+    __syncthreads();
+    if (wid == 0) {
+        const int L = logical_block();
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double x = lane < NW ? red[k][lane] : (k == MAXSLOT ? -HUGE_VAL : 0.0);
+            x = (k == MAXSLOT) ? wave_max(x) : wave_sum(x);
+            if (lane == 0) part[L * NV + k] = x;
+        }
+    }
+}
+
+// After the barrier: wave k folds slot k of all G partials (lane-strided,
+// then a butterfly) and the totals reach every thread through LDS.
+template <int NV, int BS, int MAXSLOT = -1>
+__device__ __forceinline__ void grid_reduce(const double *part, double (&tot)[NV]) {
+    static_assert(BS / kWave >= NV, "one wave per reduced value");
+    __shared__ double out[NV];
+    const int lane = threadIdx.x % kWave, k = threadIdx.x / kWave;
+    const int G = gridDim.x;
+    if (k < NV) {
+        const bool mx = k == MAXSLOT;
+        double x = mx ? -HUGE_VAL : 0.0;
+        for (int L = lane; L < G; L += kWave) {
+            const double y = part[L * NV + k];
+            x = mx ? fmax(x, y) : x + y;
+        }
+        x = mx ? wave_max(x) : wave_sum(x);
+        if (lane == 0) out[k] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) tot[j] = out[j];
 }
 
 // Host helpers defined in sc_solve.hip.
@@ -152,9 +167,13 @@ void launch_mob_d(const ChainView &C, const double *x, const int *order, double 
                   double *u_out, hipStream_t s);
 // y = D^T C.U
 void launch_dt(const ChainView &C, double *y, hipStream_t s);
-// Grid size for a persistent kernel of `block` threads: the request (0 =
-// one workgroup per CU) clamped to what is co-resident, a multiple of 8 when
-// possible.
-int persistent_grid(const void *fn, int block, int requested);
+// Grid size for a persistent kernel of `block` threads and `dyn` bytes of
+// dynamic LDS: the request (0 = one workgroup per CU) clamped to one
+// workgroup per CU and to what is co-resident, a multiple of 8 when possible.
+int persistent_grid(const void *fn, int block, int requested, size_t dyn = 0);
+// Valid tuning options (0 = default).
+inline bool lanes_ok(int v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8; }
+inline bool spw_ok(int v) { return v == 0 || v == 1 || v == 2 || v == 4; }
+inline bool block_ok(int v) { return v == 0 || v == 256 || v == 512 || v == 1024; }
 
 }  // namespace sc

@@ -326,6 +326,27 @@ __global__ void k_inc_finish(int n, Plan pl, const double *frame) {
     }
 }
 
+// Nonzeros of M = D^T Mob D: contact rows l have deg(ci) + deg(cj) - 1
+// entries, so the total is sum_k deg(k)^2 - n_c.
+__global__ void k_deg_squares(int n, Plan pl, unsigned long long *sum) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long d2 = 0;
+    if (k < n) {
+        const unsigned long long d = pl.inc_ptr[k + 1] - pl.inc_ptr[k];
+        d2 = d * d;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        d2 += __shfl_xor(d2, off, kWave);
+    __shared__ unsigned long long ws[kBlock / kWave];
+    if (threadIdx.x % kWave == 0) ws[threadIdx.x / kWave] = d2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += ws[w];
+        if (t) atomicAdd(sum, t);
+    }
+}
+
 // q_l = Phi_l / dt + D_l^T U_nc (LCP LCPdef, scaled by 1/dt).
 __global__ void k_q(int nc, const int *ci, const int *cj, const double *phi,
                     const double *frame, const double *u_nc, double dt, double *q, int *flags) {
@@ -382,6 +403,8 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     c->count = 0;
     c->n_parallel = c->n_zero_dist = c->n_borderline = 0;
     c->grid[0] = c->grid[1] = c->grid[2] = 0;
+    c->nnz = 0;
+    c->mat_ready = 0;
     const int n = p->n;
     Plan pl;
     if (!carve_plan(c->plan, c->plan_bytes, n, c->capacity, pl)) return SC_ERR_INVALID;
@@ -488,15 +511,21 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     if (nc > 0) k_second_degree<<<grid_for(nc), kBlock, 0, stream>>>(nc, pl, deg);
     k_inc_counts<<<grid_for(n), kBlock, 0, stream>>>(n, pl, deg);
     scan_exclusive(pl.inc_ptr, pl.inc_ptr, n, scan_tmp, stream);
+    unsigned long long *dsq = max_ext;  // the extent word is free again
+    SC_HIP_TRY(hipMemsetAsync(dsq, 0, sizeof(unsigned long long), stream));
     if (nc > 0) {
         k_inc_fill<<<grid_for(nc), kBlock, 0, stream>>>(nc, pl, fill);
         k_inc_finish<<<grid_for(n), kBlock, 0, stream>>>(n, pl, c->frame);
         k_q<<<grid_for(nc), kBlock, 0, stream>>>(nc, c->ci, c->cj, c->phi, c->frame, u_nc, dt,
                                                  c->q, flags);
+        k_deg_squares<<<grid_for(n), kBlock, 0, stream>>>(n, pl, dsq);
     }
+    unsigned long long hdsq = 0;
     SC_HIP_TRY(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, stream));
+    SC_HIP_TRY(hipMemcpyAsync(&hdsq, dsq, sizeof(hdsq), hipMemcpyDeviceToHost, stream));
     SC_HIP_TRY(hipStreamSynchronize(stream));
     SC_HIP_TRY(hipGetLastError());
+    c->nnz = nc > 0 ? static_cast<int64_t>(hdsq) - nc : 0;
     if (hflags[kFlagNonfiniteQ]) return SC_ERR_NONFINITE;
     return SC_OK;
 }

@@ -16,6 +16,7 @@
 
 #include "sc_chain.hpp"
 #include "sc_common.hpp"
+#include "sc_matrix.hpp"
 #include "sc_plan.hpp"
 #include "sc_sync.hpp"
 
@@ -23,11 +24,7 @@ namespace sc {
 
 namespace {
 
-struct Ctrl {
-    double alpha, res;
-    int iters, mvops, status, ndegen;
-    int n_active, pad[3];
-};
+using Ctrl = SolveCtrl;
 
 struct SolveArgs {
     ChainView C;
@@ -269,22 +266,25 @@ BbKernel bb_kernel_bs(int lpp) {
 }
 
 BbKernel bb_kernel(int lpp, int block) {
-    return block == 256 ? bb_kernel_bs<256>(lpp) : bb_kernel_bs<1024>(lpp);
+    return block == 256 ? bb_kernel_bs<256>(lpp)
+                        : block == 512 ? bb_kernel_bs<512>(lpp) : bb_kernel_bs<1024>(lpp);
 }
 
-// Largest co-resident grid for a persistent kernel (cached per kernel) and
-// the number of CUs.
-int max_coresident(const void *fn, int block, int *cus) {
+// Largest co-resident grid for a persistent kernel (cached per kernel and
+// dynamic LDS size) and the number of CUs.
+int max_coresident(const void *fn, int block, size_t dyn, int *cus) {
     static thread_local const void *last_fn = nullptr;
+    static thread_local size_t last_dyn = 0;
     static thread_local int last = 0, last_cus = 0;
-    if (fn != last_fn) {
+    if (fn != last_fn || dyn != last_dyn) {
         int per_cu = 0, dev = 0;
         hipDeviceProp_t prop;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipGetDeviceProperties(&prop, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, dyn) != hipSuccess)
             return 0;
         last_fn = fn;
+        last_dyn = dyn;
         last = per_cu * prop.multiProcessorCount;
         last_cus = prop.multiProcessorCount;
     }
@@ -294,11 +294,16 @@ int max_coresident(const void *fn, int block, int *cus) {
 
 }  // namespace
 
-int persistent_grid(const void *fn, int block, int requested) {
+// At most one workgroup per CU: with two 1024-thread workgroups per CU the
+// occupancy query allowed the launch, yet the start-up barrier of one
+// kernel variant timed out waiting for workgroups that never became
+// resident, so larger grids are not used.
+int persistent_grid(const void *fn, int block, int requested, size_t dyn) {
     int cus = 0;
-    const int cap = max_coresident(fn, block, &cus);
+    const int cap = max_coresident(fn, block, dyn, &cus);
     int g = requested > 0 ? requested : cus;
     if (g > cap) g = cap;
+    if (g > cus) g = cus;
     if (g > kMaxReduceBlocks) g = kMaxReduceBlocks;
     if (g >= 8) g -= g % 8;
     return g < 1 ? 1 : g;
@@ -325,7 +330,7 @@ void launch_dt(const ChainView &C, double *y, hipStream_t s) {
 size_t solve_ws_bytes(int32_t n, int32_t cap) {
     const size_t nn = static_cast<size_t>(n), cc = static_cast<size_t>(cap);
     size_t b = 0;
-    b += 2 * align_up(cc * sizeof(double), 256);          // second gamma, g buffers
+    b += align_up(4 * cc * sizeof(double), 256);          // second gamma/g buffers or (gamma, g) records
     b += align_up(8 * nn * sizeof(double), 256);          // U (rank order)
     b += align_up(4 * kMaxReduceBlocks * sizeof(double), 256);
     b += align_up(sizeof(GridSync), 256);
@@ -372,8 +377,7 @@ extern "C" int sc_mvop(const sc_particles *p, const sc_contacts *c, const double
     if (!x || !y) return SC_ERR_INVALID;
     if (!ws_ok(ws, ws_bytes, solve_ws_bytes(p->n, c->capacity))) return SC_ERR_WORKSPACE;
     Carver cv{static_cast<char *>(ws), ws_bytes};
-    cv.take<double>(c->capacity);
-    cv.take<double>(c->capacity);
+    cv.take<double>(4 * static_cast<size_t>(c->capacity));
     double *U = cv.take<double>(8 * static_cast<size_t>(p->n));
     if (!cv.ok) return SC_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -393,17 +397,22 @@ extern "C" int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
     if (rc) return rc;
     if (!opts || !st) return SC_ERR_INVALID;
     if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->bb < 1 || opts->bb > 3 ||
-        opts->lanes_per_particle < 0 || opts->lanes_per_particle > 8 || opts->grid < 0 ||
-        (opts->block != 0 && opts->block != 256 && opts->block != 1024))
+        !lanes_ok(opts->lanes_per_particle) || !spw_ok(opts->slices_per_wave) ||
+        opts->lds_entries_per_wave < -1 || opts->grid < 0 ||
+        !block_ok(opts->block) || opts->op < 0 ||
+        opts->op > SC_OP_MATRIX || (opts->op == SC_OP_MATRIX && !c->mat_ready))
         return SC_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream_);
     const int n = p->n, nc = c->count;
     *st = sc_stats{};
+    const bool use_mat = opts->op == SC_OP_MATRIX || (opts->op == SC_OP_AUTO && c->mat_ready);
+    MatBufs mb{};
+    if (use_mat && !carve_matrix(c->mat, c->mat_bytes, nc, c->nnz, mb)) return SC_ERR_INVALID;
     if (nc > 0 && (!gamma || !g)) return SC_ERR_INVALID;
     if (!ws_ok(ws, ws_bytes, solve_ws_bytes(n, c->capacity))) return SC_ERR_WORKSPACE;
     Carver cv{static_cast<char *>(ws), ws_bytes};
-    double *gam1 = cv.take<double>(c->capacity);
-    double *g1 = cv.take<double>(c->capacity);
+    double *zbuf = cv.take<double>(4 * static_cast<size_t>(c->capacity));
+    double *gam1 = zbuf, *g1 = zbuf + c->capacity;
     double *U = cv.take<double>(8 * static_cast<size_t>(n));
     double *part = cv.take<double>(4 * kMaxReduceBlocks);
     GridSync *sync = cv.take<GridSync>(1);
@@ -422,11 +431,12 @@ extern "C" int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
     Timing &tm = timing();
     if (!tm.ok) return SC_ERR_HIP;
 
-    int lpp = opts->lanes_per_particle ? opts->lanes_per_particle : 4;
-    if (lpp != 1 && lpp != 2 && lpp != 4 && lpp != 8) return SC_ERR_INVALID;
+    const int lpp = opts->lanes_per_particle ? opts->lanes_per_particle : 4;
+    const int spw = opts->slices_per_wave ? opts->slices_per_wave : 1;
+    int cache_used = 0;
     const int block = opts->block ? opts->block : 1024;
     BbKernel kern = bb_kernel(lpp, block);
-    const int G = persistent_grid(reinterpret_cast<const void *>(kern), block, opts->grid);
+    int G = use_mat ? 1 : persistent_grid(reinterpret_cast<const void *>(kern), block, opts->grid);
     if (G < 1) return SC_ERR_HIP;
 
     SolveArgs A;
@@ -448,16 +458,24 @@ extern "C" int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
     SC_HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), s));
     void *args[] = {&A};
     SC_HIP_TRY(hipEventRecord(tm.t0, s));
-    SC_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G),
-                                          dim3(block), args, 0, s));
+    if (use_mat) {
+        SC_HIP_TRY(launch_bbpgd_mat(mat_view(nc, mb), c->q, gamma, g, zbuf, part, sync, ctrl,
+                                    opts->tol, opts->max_iter, opts->bb, spw,
+                                    opts->lds_entries_per_wave, block, opts->grid, s, &G,
+                                    &cache_used));
+    } else {
+        SC_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G),
+                                              dim3(block), args, 0, s));
+    }
     SC_HIP_TRY(hipEventRecord(tm.t1, s));
     Ctrl hc;
     SC_HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     SC_HIP_TRY(hipStreamSynchronize(s));
     float kernel_ms = 0.0f;
     SC_HIP_TRY(hipEventElapsedTime(&kernel_ms, tm.t0, tm.t1));
-    // the last iterate lives in buffer (iters & 1)
-    if (hc.iters & 1) {
+    // the chain solve leaves the last iterate in buffer (iters & 1); the
+    // matrix solve writes gamma and g itself
+    if (!use_mat && (hc.iters & 1)) {
         SC_HIP_TRY(hipMemcpyAsync(gamma, gam1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
         SC_HIP_TRY(hipMemcpyAsync(g, g1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
     }
@@ -481,6 +499,9 @@ extern "C" int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
     st->kernel_ms = kernel_ms;
     st->grid = G;
     st->block = block;
-    st->lanes_per_particle = lpp;
+    st->lanes_per_particle = use_mat ? 0 : lpp;
+    st->slices_per_wave = use_mat ? spw : 0;
+    st->lds_entries_per_wave = cache_used;
+    st->op = use_mat ? SC_OP_MATRIX : SC_OP_CHAIN;
     return hc.status;
 }

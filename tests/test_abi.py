@@ -71,6 +71,12 @@ def test_invalid_arguments_rejected_without_device_work():
     bad = A.sc_solve_opts(1e-6, 100, 7, 0, 0)
     assert L.sc_solve_lcp(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(bad), None, None,
                           None, None, ctypes.byref(st), None, 0, None) == A.SC_ERR_INVALID
+    for field, value in (("slices_per_wave", 3), ("lds_entries_per_wave", -2),
+                         ("lanes_per_particle", 16), ("block", 768), ("op", 3)):
+        bad = A.sc_solve_opts(1e-6, 100, 1, 0, 0)
+        setattr(bad, field, value)
+        assert L.sc_solve_lcp(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(bad), None, None,
+                              None, None, ctypes.byref(st), None, 0, None) == A.SC_ERR_INVALID
     box = A.sc_box()
     assert L.sc_build_contacts(ctypes.byref(p0), ctypes.byref(box), 0.1, None, 1e-3,
                                ctypes.byref(c), None, 0, None) == A.SC_ERR_INVALID

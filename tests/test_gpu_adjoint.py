@@ -42,8 +42,9 @@ def test_two_sphere_closed_form():
     np.testing.assert_allclose(dpos.cpu().numpy()[0], d / (M * dt), rtol=1e-9, atol=1e-9)
 
 
+@pytest.mark.parametrize("op", [1, 2])
 @pytest.mark.parametrize("kind", ["rods", "mixed"])
-def test_against_oracle_adjoint(kind):
+def test_against_oracle_adjoint(kind, op):
     import paper_1909_06623_amd as sc
     s = (W.rods(1500, seed=81) if kind == "rods"
          else W.rods_and_spheres(1000, 200, seed=82))
@@ -67,14 +68,17 @@ def test_against_oracle_adjoint(kind):
     wg[pm] = wts                              # library order
     # loss 1: linear in gamma
     dq, dpos, sta = sc.solve_lcp_adjoint(P, box, con, u_nc, s.dt, gam,
-                                         dL_dgamma=torch.from_numpy(wg).cuda(), tol=1e-12)
+                                         dL_dgamma=torch.from_numpy(wg).cuda(), tol=1e-12,
+                                         op=op)
+    assert sta["op"] == op
     rq, rpos, _ = O.adjoint(s, c, q, u_orc, gp, dL_dgamma=wts)
     print(f"[result] CG iters {sta['iters']} rel res {sta['residual']:.1e}", flush=True)
     np.testing.assert_allclose(dq.cpu().numpy()[pm], rq, rtol=0, atol=1e-6 * np.abs(rq).max())
     np.testing.assert_allclose(dpos.cpu().numpy(), rpos, rtol=0,
                                atol=1e-6 * np.abs(rpos).max())
     # loss 2: 1/2 ||D gamma||^2
-    dq, dpos, sta = sc.solve_lcp_adjoint(P, box, con, u_nc, s.dt, gam, dL_df=f_c, tol=1e-12)
+    dq, dpos, sta = sc.solve_lcp_adjoint(P, box, con, u_nc, s.dt, gam, dL_df=f_c, tol=1e-12,
+                                         op=op)
     F = O.D_apply(s.n, c, gp)
     rq, rpos, _ = O.adjoint(s, c, q, u_orc, gp, dL_dF=F)
     np.testing.assert_allclose(dq.cpu().numpy()[pm], rq, rtol=0, atol=1e-6 * np.abs(rq).max())

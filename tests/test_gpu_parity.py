@@ -117,15 +117,20 @@ def test_mvop(name):
     np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
+OPS = {"chain": 1, "matrix": 2}
+
+
+@pytest.mark.parametrize("op", list(OPS))
 @pytest.mark.parametrize("bb", [1, 2, 3])
-def test_fixed_steps_match(bb):
+def test_fixed_steps_match(bb, op):
     s = W.rods(3000, seed=31)
-    _say(f"fixed steps bb={bb}")
+    _say(f"fixed steps bb={bb} op={op}")
     sc = _sc()
     P, box, u_nc, con = _setup_gpu(s)
     c, u_orc, q_orc = O.setup(s)
     pm = _perm(con)
-    gam, g, st, _, _ = sc.solve_lcp(P, con, tol=s.tol, max_iter=6, bb=bb)
+    gam, g, st, _, _ = sc.solve_lcp(P, con, tol=s.tol, max_iter=6, bb=bb, op=OPS[op])
+    assert st["op"] == OPS[op]
     go, gg, sto = O.bbpgd(s, c, q_orc, max_iter=6, bb=bb)
     assert st["status"] == 1 and sto.status == 1
     assert (st["iters"], st["mvops"]) == (6, 8)
@@ -142,15 +147,16 @@ def _kkt(gam, g, tol):
     assert np.all(np.abs(gam * g) <= tol * np.maximum(1.0, np.maximum(gam, np.abs(g))))
 
 
+@pytest.mark.parametrize("op", list(OPS))
 @pytest.mark.parametrize("name", ["rods5000", "mixed", "rods_small_box"])
-def test_converged_solve_spd(name):
+def test_converged_solve_spd(name, op):
     s = CASES[name]()
-    _say(f"solve {name}")
+    _say(f"solve {name} op={op}")
     sc = _sc()
     P, box, u_nc, con = _setup_gpu(s)
     c, u_orc, q_orc = O.setup(s)
     pm = _perm(con)
-    gam, g, st, f_c, u_c = sc.solve_lcp(P, con, tol=s.tol, want_fc=True)
+    gam, g, st, f_c, u_c = sc.solve_lcp(P, con, tol=s.tol, want_fc=True, op=OPS[op])
     assert st["status"] == 0
     gam, g = gam.cpu().numpy()[pm], g.cpu().numpy()[pm]
     _kkt(gam, g, s.tol)
@@ -167,7 +173,7 @@ def test_converged_solve_spd(name):
     assert sto.status == 0
     rel = np.linalg.norm(gam - go) / np.linalg.norm(go)
     # ... and at a tight tolerance, where the bound is far below 1e-6
-    gt, _, stt, _, _ = sc.solve_lcp(P, con, tol=1e-9)
+    gt, _, stt, _, _ = sc.solve_lcp(P, con, tol=1e-9, op=OPS[op])
     got, _, stot = O.bbpgd(s, c, q_orc, tol=1e-9)
     assert stt["status"] == 0 and stot.status == 0
     rel_t = np.linalg.norm(gt.cpu().numpy()[pm] - got) / np.linalg.norm(got)
@@ -177,14 +183,15 @@ def test_converged_solve_spd(name):
     assert rel <= 1e-4
 
 
-def test_converged_solve_semidefinite_spheres():
+@pytest.mark.parametrize("op", list(OPS))
+def test_converged_solve_semidefinite_spheres(op):
     s = W.workload(1)
-    _say("solve spheres1000 (semidefinite M)")
+    _say(f"solve spheres1000 (semidefinite M) op={op}")
     sc = _sc()
     P, box, u_nc, con = _setup_gpu(s)
     c, u_orc, q_orc = O.setup(s)
     pm = _perm(con)
-    gam, g, st, f_c, u_c = sc.solve_lcp(P, con, tol=1e-9, want_fc=True)
+    gam, g, st, f_c, u_c = sc.solve_lcp(P, con, tol=1e-9, want_fc=True, op=OPS[op])
     go, gg, sto = O.bbpgd(s, c, q_orc, tol=1e-9)
     assert st["status"] == 0 and sto.status == 0
     gam, g = gam.cpu().numpy()[pm], g.cpu().numpy()[pm]
@@ -194,15 +201,86 @@ def test_converged_solve_semidefinite_spheres():
     np.testing.assert_allclose(f_c.cpu().numpy(), F, atol=1e-7 * np.abs(F).max())
 
 
-def test_bitwise_reproducible():
+@pytest.mark.parametrize("op", list(OPS))
+def test_bitwise_reproducible(op):
     s = W.rods(4000, seed=44)
-    _say("reproducibility")
+    _say(f"reproducibility op={op}")
     sc = _sc()
     P, box, u_nc, con = _setup_gpu(s)
-    a = sc.solve_lcp(P, con, tol=s.tol)
-    b = sc.solve_lcp(P, con, tol=s.tol)
+    a = sc.solve_lcp(P, con, tol=s.tol, op=OPS[op])
+    b = sc.solve_lcp(P, con, tol=s.tol, op=OPS[op])
     assert a[2]["iters"] == b[2]["iters"]
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("spw", [1, 2, 4])
+def test_matrix_launch_shapes_agree(spw):
+    """Every launch shape of the one-pass solve runs the same algorithm: a
+    few fixed steps agree with the oracle, M's nonzero count is
+    sum_k deg(k)^2 - n_c, and the product M gamma_0 + q (a solve with no
+    descent step) is bitwise the same for every shape, since each row is
+    summed in storage order by one lane."""
+    s = W.rods_and_spheres(2500, 500, seed=45)
+    _say(f"matrix slices_per_wave={spw}")
+    sc = _sc()
+    P, box, u_nc, con = _setup_gpu(s)
+    c, u_orc, q_orc = O.setup(s)
+    deg = np.bincount(c.i, minlength=s.n) + np.bincount(c.j, minlength=s.n)
+    assert con.nnz == int(np.sum(deg.astype(np.int64) ** 2)) - c.nc
+    assert con.count % 64 != 0  # a ragged last slice
+    pm = _perm(con)
+    go, gg, sto = O.bbpgd(s, c, q_orc, max_iter=5)
+    for block, grid, cache in ((256, 0, 0), (1024, 0, 0), (1024, 24, 0), (256, 3, 0),
+                               (1024, 8, 96)):
+        gam, g, st, _, _ = sc.solve_lcp(P, con, max_iter=5, op=2, slices_per_wave=spw,
+                                        block=block, grid=grid, lds_entries_per_wave=cache)
+        assert (st["slices_per_wave"], st["block"], st["op"]) == (spw, block, 2)
+        np.testing.assert_allclose(gam.cpu().numpy()[pm], go, rtol=1e-9,
+                                   atol=1e-9 * np.abs(go).max())
+    rng = np.random.default_rng(4545)
+    x_o = rng.uniform(0.0, 1.0, c.nc) * (rng.uniform(size=c.nc) < 0.6)
+    x_lib = np.empty_like(x_o)
+    x_lib[pm] = x_o
+    ref = None
+    # entries held in LDS (all, a prefix per wave, none) change nothing either
+    for block, grid, cache in ((1024, 0, 0), (256, 0, 0), (1024, 8, 0), (256, 40, 0),
+                               (1024, 8, 96), (256, 3, 250), (1024, 0, -1)):
+        _, g, st, _, _ = sc.solve_lcp(P, con, max_iter=0, op=2, slices_per_wave=spw,
+                                      block=block, grid=grid, lds_entries_per_wave=cache,
+                                      gamma0=torch.from_numpy(x_lib))
+        if cache > 0:
+            assert st["lds_entries_per_wave"] == cache
+        elif cache < 0:
+            assert st["lds_entries_per_wave"] == 0
+        if ref is None:
+            ref = g.clone()
+        else:
+            assert torch.equal(g, ref), (block, grid, cache)
+    want = O.mvop(s, c, x_o) + q_orc
+    np.testing.assert_allclose(ref.cpu().numpy()[pm], want, rtol=1e-12,
+                               atol=1e-12 * np.abs(want).max())
+
+
+def test_matrix_tiny_systems():
+    """Fewer rows than one slice (most workgroups own no slice)."""
+    sc = _sc()
+    big = W.rods(1200, seed=46)
+    cb = O.find_contacts(big)
+    for k in (1, 4, 12):
+        idx = np.unique(np.concatenate([cb.i[:k], cb.j[:k]]))
+        s = big.subset(idx)
+        _say(f"matrix tiny: {len(idx)} rods")
+        P, box, u_nc, con = _setup_gpu(s)
+        c, u_orc, q_orc = O.setup(s)
+        assert 1 <= c.nc < 64 and con.count == c.nc
+        pm = _perm(con)
+        gam, g, st, _, _ = sc.solve_lcp(P, con, tol=1e-10, op=2)
+        go, gg, sto = O.bbpgd(s, c, q_orc, tol=1e-10)
+        assert st["status"] == 0 and st["op"] == 2
+        np.testing.assert_allclose(g.cpu().numpy()[pm], gg, rtol=1e-6,
+                                   atol=1e-6 * np.abs(gg).max())
+        np.testing.assert_allclose(gam.cpu().numpy()[pm], go, rtol=1e-6,
+                                   atol=1e-6 * np.abs(go).max())
 
 
 def test_edge_cases():
