@@ -2,13 +2,15 @@
 100,000 spherocylinders (length 1, diameter 0.05, ~6 close pairs per rod,
 isotropic, periodic box), FP64, one MI355X.
 
-One step = build_contacts + solve_lcp on the resident synthetic inputs.
-Prints one JSON line: whole-job throughput in rods/s, the HBM roofline of the
-BBPGD iteration (algorithmic bytes per iteration over the measured GPU time of
-the iteration loop), the adjoint/forward time ratio (loss 1/2 ||D gamma||^2),
-and the FP64 oracle timed on the host for comparison.
+One step = build_contacts (cell binning, pairs, D, q, assembled M) +
+solve_lcp on the resident synthetic inputs. Prints one JSON line: whole-job
+throughput in rods/s, the HBM roofline of the persistent BBPGD kernel
+(algorithmic bytes of the method's iterations over the kernel's HIP-event
+time), the adjoint/forward time ratio (loss 1/2 ||D gamma||^2), and the FP64
+oracle timed on the host for comparison.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -18,22 +20,48 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Counter summary of the solve kernel on this workload (rocprofv3 FETCH_SIZE
+# and WRITE_SIZE passes, scaled by a plain-copy calibration).
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bbpgd_mat_rods100k_traffic.json")
+# Sources that define the persistent matrix solve kernel.
+KERNEL_SOURCES = ["sc_matrix.hip", "sc_matrix.hpp", "sc_chain.hpp", "sc_sync.hpp", "sc_common.hpp"]
 
 
-def rod_iteration_bytes(nc, n):
-    """Algorithmic bytes of one matrix-free BBPGD iteration on a rod system:
-    per contact the 80-byte frame record read in both passes, 8 bytes of
+def iteration_bytes(nc, n, rods=True):
+    """Algorithmic bytes of one BBPGD iteration (one product M gamma = D^T Mob
+    D gamma with the BB step and reductions), with D kept compact and read
+    twice. Rods: per contact an 80-byte D record read twice, 8 bytes of
     incidence and 48 bytes of gamma/g/q traffic; per particle U written and
-    read (96) and the axis (24)."""
-    return 216 * nc + 120 * n
+    read (96) and the axis (24). Spheres: 32-byte records, U of 3 entries."""
+    return 216 * nc + 120 * n if rods else 120 * nc + 56 * n
 
 
-def matrix_iteration_bytes(nc, nnz):
-    """Algorithmic bytes of one BBPGD iteration on the assembled M: each
-    nonzero's column index and value (12), and per row its offset (4), q (8)
-    and gamma, g read and written (32). Column gathers of gamma and g are
-    reuse of rows already counted."""
+def operator_bytes(nc, nnz):
+    """Bytes the assembled-M product itself streams per iteration: each
+    nonzero's column and value (12), and per row its length (4), q (8) and
+    gamma, g read and written (32)."""
     return 12 * nnz + 44 * nc
+
+
+def kernel_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1909_06623_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(iters):
+    """HBM bytes per launch from the stored counter summary, or None if the
+    kernel sources or the launch (iteration count) changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256") != kernel_digest() or t.get("iters") != iters:
+        return None
+    return t.get("bytes_per_launch")
 
 
 def main():
@@ -115,11 +143,14 @@ def main():
     st = stats[-1]
     iters = st["iters"]
     used_matrix = st["op"] == 2
-    bytes_iter = (matrix_iteration_bytes(con.count, con.nnz) if used_matrix
-                  else rod_iteration_bytes(con.count, s.n))
-    kernel_ms = float(np.median([x["kernel_ms"] for x in stats]))
-    per_iter_s = kernel_ms * 1e-3 / max(1, iters + 2)
-    achieved = bytes_iter / per_iter_s / 1e9
+    rods = bool(np.all(s.half_len > 0))
+    bytes_iter = iteration_bytes(con.count, s.n, rods)
+    products = iters + 2  # Algorithm 1: g_0, g_0^T M g_0, then one per step
+    bytes_launch = bytes_iter * products
+    # mean HIP-event time of the persistent kernel over the timed steps
+    kernel_ms = float(np.mean([x["kernel_ms"] for x in stats]))
+    achieved = bytes_launch / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(iters) if used_matrix else None
 
     adj = None
     if not args.no_adjoint:
@@ -167,14 +198,20 @@ def main():
                    "n": s.n, "n_contacts": con.count, "iters": iters,
                    "mvops": st["mvops"], "n_active": st["n_active"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": ("k_bbpgd_mat" if used_matrix else "k_bbpgd")
-                               + " (persistent BBPGD solve; per launch = iterations + 2 "
-                               "products)",
-                     "bytes_model": ("12 nnz + 44 n_c" if used_matrix
-                                     else "216 n_c + 120 N"),
-                     "bytes_per_iter": bytes_iter, "us_per_iter": per_iter_s * 1e6,
-                     "kernel_ms": kernel_ms, "grid": st["grid"], "block": st["block"],
+                               + " (persistent BBPGD solve, one launch per solve)",
+                     "bytes_model": ("216 n_c + 120 N" if rods else "120 n_c + 56 N")
+                                    + " bytes per product, (iterations + 2) products "
+                                      "per launch",
+                     "bytes_per_product": bytes_iter, "products_per_launch": products,
+                     "bytes_per_launch": bytes_launch, "launch_ms": kernel_ms,
+                     "us_per_product": 1e3 * kernel_ms / products,
+                     "operator_bytes_per_product": (operator_bytes(con.count, con.nnz)
+                                                    if used_matrix else None),
+                     "grid": st["grid"], "block": st["block"],
+                     "slices_per_wave": st["slices_per_wave"],
+                     "lds_entries_per_wave": st["lds_entries_per_wave"],
                      "lanes_per_particle": st["lanes_per_particle"]},
         "cpu_baseline": cpu,
         "chain_solve": {"iters": chain["iters"], "kernel_ms": chain["kernel_ms"],
