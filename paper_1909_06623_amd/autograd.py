@@ -1,0 +1,112 @@
+"""torch.autograd bindings of the collision solve.
+
+Two functions, both thin wrappers of the C ABI (every step runs in the HIP
+library):
+
+* ``collision_solve(pos, ...)``: close pairs, D, q and the BBPGD solve of
+  the collision LCP (section 3.2, Algorithm 1) as a function of the particle
+  centres. Returns (gamma, F_c = D gamma). Its backward is the implicit
+  adjoint through the converged solution on its active set (not in the
+  paper; the derivation is in ``sc_solve_lcp_adjoint``'s header comment):
+  it returns dL/d(centres) and stores dL/dq in the ``SolveInfo``.
+* ``lcp_solve(q, ...)``: the solve on a fixed contact set as a function of q,
+  returning gamma; its backward returns dL/dq = -w with M_AA w_A = dL/dgamma_A.
+
+Orientations, radii, mobility coefficients and U_nc receive no gradient. The
+contact set is piecewise constant in the centres; the gradient is that of the
+active branch.
+"""
+from __future__ import annotations
+
+import copy
+import dataclasses
+from typing import Optional
+
+import torch
+from torch.autograd.function import once_differentiable
+
+from .api import Box, Contacts, Particles, build_contacts, solve_lcp, solve_lcp_adjoint
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    """Side results of a differentiable solve."""
+    contacts: Optional[Contacts] = None
+    stats: Optional[dict] = None
+    dL_dq: Optional[torch.Tensor] = None          # filled by backward
+    adjoint_stats: Optional[dict] = None          # filled by backward
+
+
+class _CollisionSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, pos, particles, box, u_nc, dt, delta, tol, adjoint_tol, info, kw):
+        P = dataclasses.replace(particles, pos=pos.detach().to(torch.float64).contiguous())
+        con = build_contacts(P, box, delta, u_nc, dt)
+        gamma, g, st, f_c, u_c = solve_lcp(P, con, tol=tol, want_fc=True, **kw)
+        info.contacts, info.stats = con, st
+        ctx.state = (P, box, con, u_nc, dt, adjoint_tol, info, kw)
+        ctx.save_for_backward(gamma)
+        return gamma, f_c
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, dL_dgamma, dL_df):
+        (gamma,) = ctx.saved_tensors
+        P, box, con, u_nc, dt, adjoint_tol, info, kw = ctx.state
+        dq, dpos, sta = solve_lcp_adjoint(P, box, con, u_nc, dt, gamma, dL_dgamma=dL_dgamma,
+                                          dL_df=dL_df, tol=adjoint_tol,
+                                          **_adjoint_kw(kw))
+        info.dL_dq, info.adjoint_stats = dq, sta
+        return dpos, None, None, None, None, None, None, None, None, None
+
+
+class _LcpSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, q, particles, box, contacts, u_nc, dt, tol, adjoint_tol, info, kw):
+        con = copy.copy(contacts)
+        con.q = contacts.q.clone()
+        con.q[: con.count] = q.detach().to(torch.float64)
+        gamma, g, st, _, _ = solve_lcp(particles, con, tol=tol, **kw)
+        info.contacts, info.stats = con, st
+        ctx.state = (particles, box, con, u_nc, dt, adjoint_tol, info, kw)
+        ctx.save_for_backward(gamma)
+        return gamma
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, dL_dgamma):
+        (gamma,) = ctx.saved_tensors
+        P, box, con, u_nc, dt, adjoint_tol, info, kw = ctx.state
+        dq, dpos, sta = solve_lcp_adjoint(P, box, con, u_nc, dt, gamma, dL_dgamma=dL_dgamma,
+                                          tol=adjoint_tol, **_adjoint_kw(kw))
+        info.dL_dq, info.adjoint_stats = dq, sta
+        return dq, None, None, None, None, None, None, None, None, None
+
+
+def _adjoint_kw(kw):
+    keep = ("lanes_per_particle", "grid", "block", "op", "slices_per_wave",
+            "lds_entries_per_wave", "workspace")
+    return {k: v for k, v in kw.items() if k in keep}
+
+
+def collision_solve(pos: torch.Tensor, particles: Particles, box: Box, u_nc: torch.Tensor,
+                    dt: float, delta: float, tol: float = 1e-6, adjoint_tol: float = 1e-10,
+                    info: Optional[SolveInfo] = None, **solve_kw):
+    """(gamma, F_c, info) for centres ``pos`` [n, 3] (float64, CUDA). The
+    other particle properties come from ``particles``; gamma is in the
+    library's contact order (``info.contacts``)."""
+    info = SolveInfo() if info is None else info
+    gamma, f_c = _CollisionSolve.apply(pos, particles, box, u_nc, float(dt), float(delta),
+                                       float(tol), float(adjoint_tol), info, solve_kw)
+    return gamma, f_c, info
+
+
+def lcp_solve(q: torch.Tensor, particles: Particles, box: Box, contacts: Contacts,
+              u_nc: torch.Tensor, dt: float, tol: float = 1e-6, adjoint_tol: float = 1e-10,
+              info: Optional[SolveInfo] = None, **solve_kw):
+    """(gamma, info) of the LCP on ``contacts`` with the given q (library
+    contact order); differentiable in q."""
+    info = SolveInfo() if info is None else info
+    gamma = _LcpSolve.apply(q, particles, box, contacts, u_nc, float(dt), float(tol),
+                            float(adjoint_tol), info, solve_kw)
+    return gamma, info
