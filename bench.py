@@ -64,6 +64,60 @@ def measured_traffic(iters):
     return t.get("bytes_per_launch")
 
 
+def batched(sc, W, torch, np, count):
+    """512 independent suspensions (N log-uniform in [200, 20000], spheres or
+    rods): one persistent launch replayed from a HIP graph, against the same
+    instances solved one at a time with solve_lcp on the same GPU."""
+    sus, _ = W.batched_instances(count=count)
+    items = []
+    t0 = time.perf_counter()
+    for s in sus:
+        P = sc.Particles.from_suspension(s)
+        box = sc.Box(tuple(s.box))
+        u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
+        items.append((P, sc.build_contacts(P, box, s.delta, u_nc, s.dt)))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    tol = 1e-6
+    t0 = time.perf_counter()
+    b = sc.Batch(items, tol=tol, team=0)
+    tune_s = time.perf_counter() - t0
+    b.graph_solve()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.graph_solve()
+    torch.cuda.synchronize()
+    batch_ms = 1e3 * (time.perf_counter() - t0) / reps
+    st, info = b.stats()
+    ws = sc.Workspace()
+    for P, con in items[:4]:  # warm the single-instance path
+        sc.solve_lcp(P, con, tol=tol, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single_iters = []
+    for P, con in items:
+        single_iters.append(sc.solve_lcp(P, con, tol=tol, workspace=ws)[2]["iters"])
+    torch.cuda.synchronize()
+    single_ms = 1e3 * (time.perf_counter() - t0)
+    b.close()
+    n_tot = sum(s.n for s in sus)
+    return {"instances": count, "particles": n_tot,
+            "contacts": sum(con.count for _, con in items),
+            "nnz_M": sum(con.nnz for _, con in items),
+            "batch_ms": batch_ms, "one_at_a_time_ms": single_ms,
+            "speedup": single_ms / batch_ms,
+            "batch_particles_per_s": n_tot / (batch_ms * 1e-3),
+            "team": info["team"], "tune_ms": info["tune_ms"], "tune_s": tune_s,
+            "all_converged": all(x["status"] == 0 for x in st),
+            "iters_max": max(x["iters"] for x in st),
+            "iters_sum": sum(x["iters"] for x in st),
+            "single_iters_sum": int(sum(single_iters)),
+            "build_s": build_s, "tol": tol,
+            "launch": "reset kernel + one cooperative persistent kernel, HIP graph replay"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +126,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="particle-count scale (tests)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
     args = ap.parse_args()
@@ -165,6 +221,8 @@ def main():
                "ratio": adj_ms / solve_ms, "cg_iters": sta["iters"],
                "cg_rel_residual": sta["residual"], "n_active": sta["n_active"]}
 
+    batch = None if args.no_batch else batched(sc, W, torch, np, args.batch_count)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -223,6 +281,7 @@ def main():
         "solve_only_rods_per_s": s.n / (solve_ms * 1e-3),
         "adjoint": adj,
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],
+        "batched": batch,
     }
     print(json.dumps(line), flush=True)
 

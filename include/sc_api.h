@@ -253,6 +253,66 @@ int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
                          const sc_adjoint_opts *opts, sc_stats *st, void *ws,
                          size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------- batched */
+
+/* One LCP of a batch (an independent suspension): its particles, its
+ * contacts from sc_build_contacts with the assembled M (c.mat_ready == 1),
+ * and device buffers for gamma (IN: gamma_0 when warm-starting) and g,
+ * [c.count] each. The batch keeps the pointers, not the structs' owners:
+ * every buffer must outlive the batch. */
+typedef struct sc_batch_item {
+    sc_particles p;
+    sc_contacts c;
+    double *gamma;
+    double *g;
+} sc_batch_item;
+
+typedef struct sc_batch_opts {
+    double tol;             /* epsilon_tol of Algorithm 1 for every instance */
+    int32_t max_iter;       /* j_max */
+    int32_t bb;             /* 1 = BB1, 2 = BB2, 3 = alternating */
+    int32_t warm_start;     /* 1: gamma holds gamma_0 on entry */
+    int32_t team;           /* workgroups per instance, all on one XCD: 1, 2, 4, 8,
+                               16 or 32; 0 = autotune (solves the batch once per size
+                               and keeps the fastest; overwrites gamma and g) */
+    int32_t block;          /* threads per workgroup: 0 (1024), 256, 512 or 1024 */
+    int32_t reserved;
+} sc_batch_opts;
+
+typedef struct sc_batch_info {
+    int32_t team, block, grid;      /* launch used */
+    int32_t lds_entries_per_wave;   /* entries of M per wave kept in LDS */
+    float tune_ms[6];               /* autotuner: batch time for team 1, 2, ..., 32 */
+} sc_batch_info;
+
+typedef struct sc_batch sc_batch;   /* opaque plan (host memory) */
+
+/* Workspace bytes of a batch (device memory, 256-byte aligned). */
+size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *items);
+
+/* Plans a batch of `count` LCPs (Algorithm 1 per instance, section 4): checks
+ * every item, writes the instance table and the work order (by nonzeros,
+ * largest first) into ws, and picks the team size (autotuning if
+ * opts->team == 0). *out receives a plan to free with sc_batch_destroy.
+ * Synchronises `stream`. */
+int sc_batch_create(int32_t count, const sc_batch_item *items, const sc_batch_opts *opts,
+                    void *ws, size_t ws_bytes, void *stream, sc_batch **out);
+
+/* Solves every instance of the batch in one persistent launch (preceded by a
+ * small reset kernel). Enqueues only: no synchronisation, no allocation. */
+int sc_batch_solve(sc_batch *b, void *stream);
+
+/* As sc_batch_solve, through a HIP graph captured on the first call (the
+ * persistent kernel's node is marked cooperative) and replayed after. */
+int sc_batch_graph_launch(sc_batch *b, void *stream);
+
+/* Per-instance results of the last solve (st: host array of count; grid
+ * holds the team size) and the launch used (info may be NULL).
+ * Synchronises `stream`. */
+int sc_batch_stats(const sc_batch *b, sc_stats *st, sc_batch_info *info, void *stream);
+
+void sc_batch_destroy(sc_batch *b);
+
 /* Static string describing a return code. */
 const char *sc_strerror(int code);
 

@@ -6,10 +6,10 @@ kernels for gfx950 behind a C ABI (include/sc_api.h). This package is the thin
 Python binding: PyTorch provides device memory and streams only.
 """
 from ._abi import ScError, LIB_PATH  # noqa: F401
-from .api import (Box, Contacts, Particles, Workspace, apply_mobility,  # noqa: F401
+from .api import (Batch, Box, Contacts, Particles, Workspace, apply_mobility,  # noqa: F401
                   build_contacts, mvop, solve_lcp, solve_lcp_adjoint)
 from .autograd import SolveInfo, collision_solve, lcp_solve  # noqa: F401
 
-__all__ = ["Box", "Contacts", "Particles", "Workspace", "apply_mobility",
+__all__ = ["Batch", "Box", "Contacts", "Particles", "Workspace", "apply_mobility",
            "build_contacts", "mvop", "solve_lcp", "solve_lcp_adjoint", "ScError",
            "SolveInfo", "collision_solve", "lcp_solve"]

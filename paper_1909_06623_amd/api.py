@@ -322,3 +322,73 @@ def solve_lcp_adjoint(particles: Particles, box: Box, contacts: Contacts,
                                       ctypes.byref(st), wsp, wsn, _stream())
     _check("sc_solve_lcp_adjoint", rc, (A.SC_OK, A.SC_NOT_CONVERGED))
     return dq[:nc], dpos, st.as_dict()
+
+
+class Batch:
+    """Many independent LCPs solved in one persistent launch (one team of
+    workgroups per instance at a time, instances taken largest first).
+
+    ``items``: list of (Particles, Contacts) with assembled M. ``team``: 0
+    autotunes the number of workgroups per instance. ``gamma[k]``, ``g[k]``
+    hold each instance's solution after ``solve()`` / ``graph_solve()``."""
+
+    def __init__(self, items, tol=1e-6, max_iter=100000, bb=1, team=0, block=0,
+                 gamma0=None):
+        self._keep = []
+        self.gamma, self.g = [], []
+        arr = (A.sc_batch_item * max(1, len(items)))()
+        for k, (P, con) in enumerate(items):
+            if not con.mat_ready:
+                con.assemble(P)
+            nc = con.count
+            gm = torch.zeros(max(1, nc), dtype=torch.float64, device="cuda")
+            if gamma0 is not None and nc:
+                gm[:nc] = _dev(gamma0[k])
+            g = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
+            self.gamma.append(gm[:nc])
+            self.g.append(g[:nc])
+            arr[k].p = P.c()
+            arr[k].c = con.c()
+            arr[k].gamma = gm.data_ptr()
+            arr[k].g = g.data_ptr()
+            self._keep += [P, con, gm, g]
+        self.count = len(items)
+        need = int(A.lib().sc_batch_workspace_bytes(self.count, arr))
+        self._ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        base = (self._ws.data_ptr() + 255) // 256 * 256
+        size = need + 256 - (base - self._ws.data_ptr())
+        opts = A.sc_batch_opts(float(tol), int(max_iter), int(bb),
+                               1 if gamma0 is not None else 0, int(team), int(block), 0)
+        h = ctypes.c_void_p()
+        _check("sc_batch_create",
+               A.lib().sc_batch_create(self.count, arr, ctypes.byref(opts), ctypes.c_void_p(base),
+                                       ctypes.c_size_t(size), _stream(), ctypes.byref(h)))
+        self._items = arr
+        self._h = h
+
+    def solve(self):
+        _check("sc_batch_solve", A.lib().sc_batch_solve(self._h, _stream()))
+
+    def graph_solve(self):
+        _check("sc_batch_graph_launch", A.lib().sc_batch_graph_launch(self._h, _stream()))
+
+    def stats(self):
+        st = (A.sc_stats * max(1, self.count))()
+        info = A.sc_batch_info()
+        _check("sc_batch_stats", A.lib().sc_batch_stats(self._h, st, ctypes.byref(info),
+                                                        _stream()))
+        inf = {"team": info.team, "block": info.block, "grid": info.grid,
+               "lds_entries_per_wave": info.lds_entries_per_wave,
+               "tune_ms": list(info.tune_ms)}
+        return [st[k].as_dict() for k in range(self.count)], inf
+
+    def close(self):
+        if self._h:
+            A.lib().sc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

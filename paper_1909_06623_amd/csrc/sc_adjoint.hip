@@ -283,7 +283,7 @@ size_t adjoint_ws_bytes(int32_t n, int32_t cap) {
     b += 2 * align_up(cc * sizeof(double), 256);        // p, x
     b += align_up(3 * cc * sizeof(double), 256);        // grad
     b += 3 * align_up(8 * nn * sizeof(double), 256);    // U, Vw, Uc (rank order)
-    b += align_up(4 * kMaxReduceBlocks * sizeof(double), 256);
+    b += align_up(2 * kPartHalf * sizeof(double), 256);
     b += align_up(sizeof(GridSync), 256);
     b += align_up(sizeof(CgCtrl), 256);
     return b + 2048;
@@ -338,7 +338,7 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     double *U = cv.take<double>(8 * static_cast<size_t>(n));
     double *Vw = cv.take<double>(8 * static_cast<size_t>(n));
     double *Uc = cv.take<double>(8 * static_cast<size_t>(n));
-    double *part = cv.take<double>(4 * kMaxReduceBlocks);
+    double *part = cv.take<double>(2 * kPartHalf);
     GridSync *sync = cv.take<GridSync>(1);
     CgCtrl *ctrl = cv.take<CgCtrl>(1);
     if (!cv.ok) return SC_ERR_WORKSPACE;

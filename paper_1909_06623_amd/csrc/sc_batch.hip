@@ -1,0 +1,450 @@
+// sc_batch.hip -- many independent collision LCPs (each with its own
+// assembled M) solved by Algorithm 1 in one persistent launch (gfx950).
+//
+// The grid (one workgroup per CU) splits into teams of `team` workgroups
+// that share one XCD, so a team barrier stays inside one L2 and needs no
+// write-back. Team leaders take instances from a work queue ordered by
+// nonzeros, largest first (greedy list scheduling); every member then runs
+// Algorithm 1 on its nnz-balanced share of the instance's slices, with the
+// instance's M partly resident in LDS, exactly as the single-instance
+// solver does over the whole grid. An instance's arithmetic depends only on
+// the team size, not on which team takes it, so results are reproducible.
+// A reset kernel (no memset) precedes the persistent kernel, so the pair
+// can be captured in a HIP graph and replayed.
+#include <algorithm>
+#include <climits>
+#include <numeric>
+#include <vector>
+
+#include "sc_chain.hpp"
+#include "sc_common.hpp"
+#include "sc_matrix.hpp"
+#include "sc_matrix_pass.hpp"
+#include "sc_sync.hpp"
+
+namespace sc {
+
+namespace {
+
+constexpr int kMaxTeam = 32;            // workgroups of one XCD (256 CUs / 8)
+constexpr int kTeamPartHalf = 4 * kMaxTeam;
+
+struct BatchDesc {
+    MatView M;
+    const double *q;
+    double *gamma, *g;
+    GG *z0, *z1;
+};
+
+struct alignas(256) BatchCtl {
+    unsigned next[32];              // work queue head
+    unsigned err[32];               // timeout flag
+    unsigned init[32];              // start-up arrivals
+    unsigned xslot[kMaxXcc][32];    // workgroups per XCD (slot counters)
+};
+
+struct BatchArgs {
+    const BatchDesc *items;
+    const int *order;       // queue position -> instance, by nonzeros, descending
+    SolveCtrl *ctrl;        // [count], per instance
+    BatchCtl *ctl;
+    TeamSync *tsync;        // [teams]
+    double *part;           // [teams][2 * kTeamPartHalf]
+    int count, team, warm, cache;
+    double tol;
+    int max_iter, bb;
+};
+
+// Clears the queue, barrier counters and per-instance results (an instance
+// no team reached keeps SC_ERR_TIMEOUT).
+__global__ void k_batch_reset(BatchCtl *ctl, TeamSync *ts, int nteams, SolveCtrl *ctrl, int count) {
+    unsigned *c = reinterpret_cast<unsigned *>(ctl);
+    for (int k = threadIdx.x; k < static_cast<int>(sizeof(BatchCtl) / 4); k += blockDim.x) c[k] = 0u;
+    unsigned *t = reinterpret_cast<unsigned *>(ts);
+    const long long nt = static_cast<long long>(nteams) * (sizeof(TeamSync) / 4);
+    for (long long k = threadIdx.x; k < nt; k += blockDim.x) t[k] = 0u;
+    for (int k = threadIdx.x; k < count; k += blockDim.x) {
+        ctrl[k] = SolveCtrl{};
+        ctrl[k].status = SC_ERR_TIMEOUT;
+    }
+}
+
+template <int R, int BS>
+__global__ void __launch_bounds__(BS) k_bbpgd_batch(BatchArgs A) {
+    __shared__ int sh[4];
+    BatchCtl *ctl = A.ctl;
+    const int t = A.team;
+    // team formation: slot of this workgroup within its XCD, then teams of t
+    // consecutive slots in each XCD (workgroups left over sit out)
+    if (threadIdx.x == 0) {
+        const unsigned x = xcc_id();
+        const unsigned slot = __hip_atomic_fetch_add(&ctl->xslot[x][0], 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&ctl->init[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const bool good = spin_reach(&ctl->init[0], gridDim.x, &ctl->err[0]);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        int base = 0;
+        for (unsigned k = 0; k < x; ++k) base += static_cast<int>(ld_relaxed(&ctl->xslot[k][0])) / t;
+        const int mine = static_cast<int>(ld_relaxed(&ctl->xslot[x][0])) / t;
+        const int s = static_cast<int>(slot);
+        sh[0] = good && s < mine * t ? base + s / t : -1;  // team
+        sh[1] = s % t;                                     // member
+    }
+    __syncthreads();
+    const int team = sh[0], member = sh[1];
+    __syncthreads();
+    if (team < 0) return;
+    TeamBarrier tb{A.tsync + team, &ctl->err[0], static_cast<unsigned>(t), 0u};
+    double *part = A.part + static_cast<long long>(team) * 2 * kTeamPartHalf;
+    for (;;) {
+        if (member == 0 && threadIdx.x == 0) {
+            const unsigned k =
+                __hip_atomic_fetch_add(&ctl->next[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sh[2] = static_cast<int>(k);
+            if (t > 1)
+                __hip_atomic_store(&A.tsync[team].item[0], k, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const bool ok = tb.sync();
+        if (threadIdx.x == 0 && t > 1) sh[2] = static_cast<int>(ld_relaxed(&A.tsync[team].item[0]));
+        __syncthreads();
+        const int k = sh[2];
+        __syncthreads();
+        if (!ok || k >= A.count) break;
+        const int item = A.order[k];
+        const BatchDesc D = A.items[item];
+        const SliceChunk ch = slice_chunk(D.M, member, t);
+        const WaveCache W = wave_cache<R, BS>(D.M, ch, A.cache);
+        fill_cache<R, BS>(D.M, ch, W);
+        bbpgd_rows<R, BS>(D.M, ch, W, D.q, A.warm ? D.gamma : nullptr, D.gamma, D.g, D.z0, D.z1,
+                          part, kTeamPartHalf, member, t, tb, A.tol, A.max_iter, A.bb,
+                          A.ctrl + item);
+    }
+}
+
+using BatchKernel = void (*)(BatchArgs);
+
+BatchKernel batch_kernel(int block) {
+    switch (block) {
+    case 256: return k_bbpgd_batch<1, 256>;
+    case 512: return k_bbpgd_batch<1, 512>;
+    default: return k_bbpgd_batch<1, 1024>;
+    }
+}
+
+// Dynamic LDS for the matrix cache (as for the single-instance solver).
+hipError_t batch_cache(const void *fn, int block, int *per_block, size_t *dyn) {
+    int dev = 0, max_lds = 0;
+    hipFuncAttributes fa;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e == hipSuccess) e = hipFuncGetAttributes(&fa, fn);
+    if (e != hipSuccess) return e;
+    const int nw = block / kWave;
+    long long per = (static_cast<long long>(max_lds) - static_cast<long long>(fa.sharedSizeBytes) - 256) /
+                    (12LL * nw);
+    per -= per % 2;
+    if (per < 2) per = 0;
+    *per_block = static_cast<int>(per) * nw;
+    *dyn = per > 0 ? static_cast<size_t>(per) * 12 * nw : 16;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(*dyn));
+}
+
+size_t z_doubles(const sc_contacts &c) { return 4 * static_cast<size_t>(c.count > 0 ? c.count : 1); }
+
+}  // namespace
+
+}  // namespace sc
+
+using namespace sc;
+
+struct sc_batch {
+    int count = 0;
+    std::vector<int32_t> counts;       // rows per instance
+    BatchArgs args{};
+    int nteams_max = 0;
+    int team = 1, block = 1024, grid = 0;
+    size_t dyn = 0;
+    const void *fn = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    float tune_ms[6] = {0, 0, 0, 0, 0, 0};
+};
+
+namespace {
+
+size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nteams) {
+    const size_t nd = static_cast<size_t>(std::max(count, 1));
+    size_t b = 0;
+    b += align_up(sizeof(BatchCtl), 256);
+    b += align_up(sizeof(TeamSync) * static_cast<size_t>(nteams), 256);
+    b += align_up(sizeof(double) * 2 * kTeamPartHalf * static_cast<size_t>(nteams), 256);
+    b += align_up(sizeof(BatchDesc) * nd, 256);
+    b += align_up(sizeof(int) * nd, 256);
+    b += align_up(sizeof(SolveCtrl) * nd, 256);
+    for (int32_t k = 0; k < count; ++k) b += align_up(sizeof(double) * z_doubles(items[k].c), 256);
+    return b + 256;
+}
+
+int enqueue(sc_batch *b, hipStream_t s) {
+    const int nteams = b->nteams_max;
+    k_batch_reset<<<1, 256, 0, s>>>(b->args.ctl, b->args.tsync, nteams, b->args.ctrl, b->count);
+    BatchArgs a = b->args;
+    a.team = b->team;
+    void *args[] = {&a};
+    SC_HIP_TRY(hipLaunchCooperativeKernel(b->fn, dim3(b->grid), dim3(b->block), args, b->dyn, s));
+    return SC_OK;
+}
+
+}  // namespace
+
+extern "C" size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *items) {
+    if (count < 0 || (count > 0 && !items)) return 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 1024;
+    return batch_ws_bytes(count, items, std::max(cus, 1));
+}
+
+extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const sc_batch_opts *opts,
+                               void *ws, size_t ws_bytes, void *stream, sc_batch **out) {
+    if (!out || !opts || count < 0 || (count > 0 && !items)) return SC_ERR_INVALID;
+    *out = nullptr;
+    if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->bb < 1 || opts->bb > 3 ||
+        !(opts->team == 0 || opts->team == 1 || opts->team == 2 || opts->team == 4 ||
+          opts->team == 8 || opts->team == 16 || opts->team == 32) ||
+        !block_ok(opts->block))
+        return SC_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<BatchDesc> descs(static_cast<size_t>(count));
+    std::vector<long long> nnz(static_cast<size_t>(count));
+    for (int32_t k = 0; k < count; ++k) {
+        const sc_contacts &c = items[k].c;
+        if (c.count < 0 || c.count > c.capacity || !c.mat_ready || !c.q ||
+            (c.count > 0 && (!items[k].gamma || !items[k].g)))
+            return SC_ERR_INVALID;
+        MatBufs mb{};
+        if (!carve_matrix(c.mat, c.mat_bytes, c.count, c.nnz, mb)) return SC_ERR_INVALID;
+        descs[k].M = mat_view(c.count, mb);
+        descs[k].q = c.q;
+        descs[k].gamma = items[k].gamma;
+        descs[k].g = items[k].g;
+        nnz[k] = c.nnz;
+    }
+    auto *b = new sc_batch;
+    b->count = count;
+    b->block = opts->block ? opts->block : 1024;
+    b->fn = reinterpret_cast<const void *>(batch_kernel(b->block));
+    int per_block = 0;
+    if (batch_cache(b->fn, b->block, &per_block, &b->dyn) != hipSuccess) {
+        delete b;
+        return SC_ERR_HIP;
+    }
+    b->grid = persistent_grid(b->fn, b->block, 0, b->dyn);
+    b->nteams_max = b->grid;
+    if (b->grid < 1) {
+        delete b;
+        return SC_ERR_HIP;
+    }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 ||
+        ws_bytes < batch_ws_bytes(count, items, b->nteams_max)) {
+        delete b;
+        return SC_ERR_WORKSPACE;
+    }
+    Carver cv{static_cast<char *>(ws), ws_bytes};
+    BatchArgs &a = b->args;
+    a.ctl = cv.take<BatchCtl>(1);
+    a.tsync = cv.take<TeamSync>(static_cast<size_t>(b->nteams_max));
+    a.part = cv.take<double>(2 * kTeamPartHalf * static_cast<size_t>(b->nteams_max));
+    BatchDesc *d_descs = cv.take<BatchDesc>(static_cast<size_t>(std::max(count, 1)));
+    int *d_order = cv.take<int>(static_cast<size_t>(std::max(count, 1)));
+    a.ctrl = cv.take<SolveCtrl>(static_cast<size_t>(std::max(count, 1)));
+    for (int32_t k = 0; k < count; ++k) {
+        GG *z = reinterpret_cast<GG *>(cv.take<double>(z_doubles(items[k].c)));
+        descs[k].z0 = z;
+        descs[k].z1 = z + std::max(items[k].c.count, 1);
+        b->counts.push_back(items[k].c.count);
+    }
+    if (!cv.ok) {
+        delete b;
+        return SC_ERR_WORKSPACE;
+    }
+    std::vector<int> order(static_cast<size_t>(count));
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nnz[x] > nnz[y]; });
+    a.items = d_descs;
+    a.order = d_order;
+    a.count = count;
+    a.warm = opts->warm_start ? 1 : 0;
+    a.cache = per_block;
+    a.tol = opts->tol;
+    a.max_iter = opts->max_iter;
+    a.bb = opts->bb;
+    if (count > 0) {
+        if (hipMemcpyAsync(d_descs, descs.data(), sizeof(BatchDesc) * count, hipMemcpyHostToDevice,
+                           s) != hipSuccess ||
+            hipMemcpyAsync(d_order, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            delete b;
+            return SC_ERR_HIP;
+        }
+    }
+    if (opts->team > 0) {
+        b->team = opts->team;
+    } else {
+        // autotuner: solve the batch once per team size, keep the fastest
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            delete b;
+            return SC_ERR_HIP;
+        }
+        const int sizes[6] = {1, 2, 4, 8, 16, 32};
+        float best = -1.0f;
+        int rc = SC_OK;
+        for (int i = 0; i < 6 && rc == SC_OK; ++i) {
+            b->team = sizes[i];
+            rc = hipEventRecord(e0, s) == hipSuccess ? enqueue(b, s) : SC_ERR_HIP;
+            if (rc == SC_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                                hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&b->tune_ms[i], e0, e1) != hipSuccess))
+                rc = SC_ERR_HIP;
+            if (rc == SC_OK && (best < 0.0f || b->tune_ms[i] < best)) best = b->tune_ms[i];
+        }
+        int pick = 1;
+        for (int i = 0; i < 6; ++i)
+            if (b->tune_ms[i] == best) {
+                pick = sizes[i];
+                break;
+            }
+        b->team = pick;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != SC_OK) {
+            delete b;
+            return rc;
+        }
+    }
+    *out = b;
+    return SC_OK;
+}
+
+extern "C" int sc_batch_solve(sc_batch *b, void *stream) {
+    if (!b) return SC_ERR_INVALID;
+    if (b->count == 0) return SC_OK;
+    return enqueue(b, static_cast<hipStream_t>(stream));
+}
+
+namespace {
+
+// Captures reset + persistent kernel on a private stream (the caller's may be
+// the legacy default stream, which cannot be captured), marks the persistent
+// kernel's node cooperative and instantiates the graph.
+int build_graph(sc_batch *b) {
+    hipStream_t cs = nullptr;
+    SC_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    int rc = SC_OK;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = SC_ERR_HIP;
+    } else {
+        rc = enqueue(b, cs);
+        if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) rc = SC_ERR_HIP;
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != SC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    size_t nn = 0;
+    std::vector<hipGraphNode_t> nodes;
+    int marked = 0;
+    if (hipGraphGetNodes(g, nullptr, &nn) == hipSuccess) {
+        nodes.resize(nn);
+        if (hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) nn = 0;
+    }
+    for (size_t i = 0; i < nn && rc == SC_OK; ++i) {
+        hipGraphNodeType ty;
+        hipKernelNodeParams kp{};
+        if (hipGraphNodeGetType(nodes[i], &ty) != hipSuccess) rc = SC_ERR_HIP;
+        if (rc != SC_OK || ty != hipGraphNodeTypeKernel) continue;
+        if (hipGraphKernelNodeGetParams(nodes[i], &kp) != hipSuccess) rc = SC_ERR_HIP;
+        if (rc != SC_OK || kp.func != b->fn) continue;
+        hipKernelNodeAttrValue v{}, chk{};
+        v.cooperative = 1;
+        if (hipGraphKernelNodeSetAttribute(nodes[i], hipKernelNodeAttributeCooperative, &v) !=
+                hipSuccess ||
+            hipGraphKernelNodeGetAttribute(nodes[i], hipKernelNodeAttributeCooperative, &chk) !=
+                hipSuccess ||
+            chk.cooperative != 1)
+            rc = SC_ERR_HIP;
+        ++marked;
+    }
+    if (rc == SC_OK && marked != 1) rc = SC_ERR_HIP;
+    if (rc == SC_OK && hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        b->exec = nullptr;
+        rc = SC_ERR_HIP;
+    }
+    if (rc != SC_OK) {
+        (void)hipGraphDestroy(g);
+        return rc;
+    }
+    b->graph = g;
+    return SC_OK;
+}
+
+}  // namespace
+
+extern "C" int sc_batch_graph_launch(sc_batch *b, void *stream) {
+    if (!b) return SC_ERR_INVALID;
+    if (b->count == 0) return SC_OK;
+    if (!b->exec) {
+        const int rc = build_graph(b);
+        if (rc != SC_OK) return rc;
+    }
+    SC_HIP_TRY(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+    return SC_OK;
+}
+
+extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_batch_info *info,
+                              void *stream) {
+    if (!b || (b->count > 0 && !stats)) return SC_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (info) {
+        info->team = b->team;
+        info->block = b->block;
+        info->grid = b->grid;
+        info->lds_entries_per_wave = b->args.cache / (b->block / kWave);
+        for (int i = 0; i < 6; ++i) info->tune_ms[i] = b->tune_ms[i];
+    }
+    if (b->count == 0) return SC_OK;
+    std::vector<SolveCtrl> h(static_cast<size_t>(b->count));
+    SC_HIP_TRY(hipMemcpyAsync(h.data(), b->args.ctrl, sizeof(SolveCtrl) * b->count,
+                              hipMemcpyDeviceToHost, s));
+    SC_HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < b->count; ++k) {
+        sc_stats &st = stats[k];
+        st = sc_stats{};
+        st.status = h[k].status;
+        st.iters = h[k].iters;
+        st.mvops = h[k].mvops;
+        st.residual = h[k].res;
+        st.alpha = h[k].alpha;
+        st.n_degenerate = h[k].ndegen;
+        st.grid = b->team;
+        st.block = b->block;
+        st.op = SC_OP_MATRIX;
+        st.slices_per_wave = 1;
+        st.lds_entries_per_wave = b->args.cache / (b->block / kWave);
+        st.n_active = -1;
+    }
+    return SC_OK;
+}
+
+extern "C" void sc_batch_destroy(sc_batch *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    delete b;
+}

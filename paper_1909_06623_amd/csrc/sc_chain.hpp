@@ -111,10 +111,10 @@ __device__ __forceinline__ double dt_u(const ChainView &C, int l) {
 // workgroups compute bitwise identical totals and take identical decisions.
 
 // Before the barrier: the workgroup's NV partials (wave butterflies, then
-// one wave over the per-wave results) go to part[L * NV + k] for logical
-// workgroup L.
+// one wave over the per-wave results) go to part[slot * NV + k]; the slot is
+// the logical workgroup unless given.
 template <int NV, int BS, int MAXSLOT = -1>
-__device__ __forceinline__ void write_partial(double *part, double (&acc)[NV]) {
+__device__ __forceinline__ void write_partial(double *part, double (&acc)[NV], int slot = -1) {
     constexpr int NW = BS / kWave;
     __shared__ double red[NV][NW];
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
@@ -126,7 +126,7 @@ __device__ __forceinline__ void write_partial(double *part, double (&acc)[NV]) {
     }
     __syncthreads();
     if (wid == 0) {
-        const int L = logical_block();
+        const int L = slot >= 0 ? slot : logical_block();
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             double x = lane < NW ? red[k][lane] : (k == MAXSLOT ? -HUGE_VAL : 0.0);
@@ -136,14 +136,15 @@ __device__ __forceinline__ void write_partial(double *part, double (&acc)[NV]) {
     }
 }
 
-// After the barrier: wave k folds slot k of all G partials (lane-strided,
-// then a butterfly) and the totals reach every thread through LDS.
+// After the barrier: wave k folds value k of all G partials (lane-strided,
+// then a butterfly) and the totals reach every thread through LDS. G is the
+// grid size unless given.
 template <int NV, int BS, int MAXSLOT = -1>
-__device__ __forceinline__ void grid_reduce(const double *part, double (&tot)[NV]) {
+__device__ __forceinline__ void grid_reduce(const double *part, double (&tot)[NV], int nparts = -1) {
     static_assert(BS / kWave >= NV, "one wave per reduced value");
     __shared__ double out[NV];
     const int lane = threadIdx.x % kWave, k = threadIdx.x / kWave;
-    const int G = gridDim.x;
+    const int G = nparts >= 0 ? nparts : static_cast<int>(gridDim.x);
     if (k < NV) {
         const bool mx = k == MAXSLOT;
         double x = mx ? -HUGE_VAL : 0.0;

@@ -14,6 +14,7 @@ namespace sc {
 constexpr int kBlock = 256;            // threads per workgroup (4 waves)
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kMaxReduceBlocks = 1024; // partial-sum slots of grid reductions
+constexpr int kPartHalf = 4 * kMaxReduceBlocks;  // doubles per half of the partials buffer
 
 // ------------------------------------------------------------------ host
 

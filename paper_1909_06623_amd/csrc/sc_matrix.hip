@@ -26,6 +26,7 @@
 #include "sc_chain.hpp"
 #include "sc_common.hpp"
 #include "sc_matrix.hpp"
+#include "sc_matrix_pass.hpp"
 #include "sc_plan.hpp"
 #include "sc_sync.hpp"
 
@@ -145,228 +146,6 @@ __global__ void k_assemble(ChainView C, int ns, const int32_t *len, const int32_
     }
 }
 
-// Slices of the workgroup, balanced by nonzeros: logical workgroup L owns
-// slices [s0, s1) with s0 the first slice whose offset reaches L * nnz / G.
-struct SliceChunk {
-    int s0, s1, l0, l1;  // slices and the rows they cover
-};
-
-__device__ __forceinline__ int first_slice_at(const MatView &M, long long target) {
-    int lo = 0, hi = M.ns;  // smallest s with soff[s] >= target
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (M.soff[mid] < target) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ SliceChunk slice_chunk(const MatView &M) {
-    __shared__ int bounds[2];
-    const long long L = logical_block(), G = gridDim.x;
-    const long long nnz = M.soff[M.ns];
-    if (threadIdx.x == 0) bounds[0] = L == 0 ? 0 : first_slice_at(M, L * nnz / G);
-    if (threadIdx.x == 1) bounds[1] = L == G - 1 ? M.ns : first_slice_at(M, (L + 1) * nnz / G);
-    __syncthreads();
-    SliceChunk c;
-    c.s0 = bounds[0];
-    c.s1 = bounds[1];
-    c.l0 = min(c.s0 * kWave, M.nc);
-    c.l1 = min(c.s1 * kWave, M.nc);
-    __syncthreads();
-    return c;
-}
-
-// Diagonal of row l (depth 0 holds every row of the slice in lane order).
-__device__ __forceinline__ double mat_diag(const MatView &M, int l) {
-    return M.val[M.soff[l / kWave] + l % kWave];
-}
-
-// Part of M kept in LDS for the whole persistent solve. The workgroup's
-// dynamic LDS is split evenly over its waves; each wave walks its slices in
-// its fixed processing order and keeps a prefix of each slice's entries
-// until its region is full, so the fill and every pass agree on which
-// entries live in LDS without any table. The rest is read from global
-// memory.
-extern __shared__ double sc_lds_dyn[];
-
-struct WaveCache {
-    double *val;
-    int32_t *col;
-    int cap;  // entries in this wave's region
-};
-
-// Entries of the wave's slices, in the order the pass visits them.
-template <int R, int BS>
-__device__ __forceinline__ int wave_entries(const MatView &M, const SliceChunk &ch) {
-    constexpr int NW = BS / kWave;
-    int e = 0;
-    for (int s = ch.s0 + threadIdx.x / kWave; s < ch.s1; s += NW * R)
-        for (int r = 0; r < R; ++r) {
-            const int sr = s + r * NW;
-            if (sr < ch.s1) e += M.soff[sr + 1] - M.soff[sr];
-        }
-    return __builtin_amdgcn_readfirstlane(e);
-}
-
-// Splits the workgroup's `cap` entries of LDS over its waves in proportion
-// to their entries, so that all waves leave about the same share in global
-// memory.
-template <int R, int BS>
-__device__ WaveCache wave_cache(const MatView &M, const SliceChunk &ch, int cap) {
-    constexpr int NW = BS / kWave;
-    __shared__ int need[NW];
-    const int wv = threadIdx.x / kWave;
-    const int e = wave_entries<R, BS>(M, ch);
-    if (threadIdx.x % kWave == 0) need[wv] = e;
-    __syncthreads();
-    long long tot = 0, before = 0;
-    for (int w = 0; w < NW; ++w) {
-        if (w == wv) before = tot;
-        tot += need[w];
-    }
-    __syncthreads();
-    auto share = [&](long long x) {
-        return tot <= cap ? x : x * cap / (tot > 0 ? tot : 1);
-    };
-    const long long b0 = share(before), b1 = share(before + e);
-    WaveCache w;
-    w.val = sc_lds_dyn + b0;
-    w.col = reinterpret_cast<int32_t *>(sc_lds_dyn + cap) + b0;
-    w.cap = static_cast<int>(b1 - b0);
-    return w;
-}
-
-// Calls f(r, first entry, entries, LDS offset, entries in LDS) for every
-// slice of the wave in processing order (R slices per step, as the pass).
-template <int R, int BS, class F>
-__device__ __forceinline__ void walk_wave_slices(const MatView &M, const SliceChunk &ch,
-                                                 int cap, int s, int &used, F f) {
-    constexpr int NW = BS / kWave;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int sr = s + r * NW;
-        int e0 = 0, ne = 0;
-        if (sr < ch.s1) {
-            e0 = __builtin_amdgcn_readfirstlane(M.soff[sr]);
-            ne = __builtin_amdgcn_readfirstlane(M.soff[sr + 1]) - e0;
-        }
-        const int k = min(ne, cap - used);
-        f(r, e0, ne, used, k);
-        used += k;
-    }
-}
-
-template <int R, int BS>
-__device__ void fill_cache(const MatView &M, const SliceChunk &ch, const WaveCache &W) {
-    constexpr int NW = BS / kWave;
-    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    int used = 0;
-    for (int s = ch.s0 + wv; s < ch.s1 && used < W.cap; s += NW * R)
-        walk_wave_slices<R, BS>(M, ch, W.cap, s, used, [&](int, int e0, int, int at, int k) {
-            for (int x = lane; x < k; x += kWave) {
-                W.val[at + x] = M.val[e0 + x];
-                W.col[at + x] = M.col[e0 + x];
-            }
-        });
-    __syncthreads();
-}
-
-// One pass over the chunk's rows: acc_l = sum_k val_k x(col_k), summed in
-// storage order (so a row's value does not depend on the launch shape).
-// Each wave takes R slices at a time (one lane per row). Per batch of B
-// depths it reads the columns, issues every gather, then reads the values
-// and accumulates. The batch has no per-entry branch, so its gathers are in
-// flight together: a lane without an entry at a depth gathers its own row
-// and adds nothing. pre(l) loads the row's own inputs up front; epi(l, acc,
-// pre) finishes the row.
-template <int R, int BS, class P, class X, class E>
-__device__ __forceinline__ void spmv_pass(const MatView &M, const SliceChunk &ch,
-                                          const WaveCache &W, P pre, X xf, E epi) {
-    constexpr int NW = BS / kWave;
-    constexpr int B = 8 / R;  // depths per batch (measured best with 1024 threads)
-    using Pre = decltype(pre(0));
-    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    int used = 0;
-    for (int s = ch.s0 + wv; s < ch.s1; s += NW * R) {
-        int n[R], pos[R], e0[R], lds0[R], nlds[R], row[R];
-        Pre pv[R];
-        double acc[R];
-        int wid = 0;
-        walk_wave_slices<R, BS>(M, ch, W.cap, s, used, [&](int r, int f, int, int at, int k) {
-            e0[r] = f;
-            lds0[r] = at;
-            nlds[r] = k;
-        });
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int sr = s + r * NW;
-            const bool have = sr < ch.s1;
-            const int l = sr * kWave + lane;
-            row[r] = min(l, M.nc - 1);  // a valid row for lanes past the end
-            n[r] = have && l < M.nc ? M.len[l] : 0;
-            pos[r] = e0[r];
-            wid = max(wid, have ? __builtin_amdgcn_readfirstlane(M.swid[sr]) : 0);
-            pv[r] = pre(row[r]);
-            acc[r] = 0.0;
-        }
-        for (int t0 = 0; t0 < wid; t0 += B) {
-            int c[R][B], li[R][B];
-            bool spill = false;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const bool on = t0 + b < n[r];
-                    const unsigned long long bal = __ballot(on);
-                    const int at = pos[r] + __popcll(bal & below);
-                    pos[r] += __popcll(bal);
-                    const int o = at - e0[r];
-                    const bool in_lds = on && o < nlds[r];
-                    spill |= on && !in_lds;
-                    // LDS index (0 is always a valid slot) or, if spilled, -1 - global index
-                    li[r][b] = in_lds ? lds0[r] + o : (on ? -1 - at : 0);
-                    const int cl = W.col[in_lds ? lds0[r] + o : 0];
-                    c[r][b] = in_lds ? cl : row[r];
-                }
-            }
-            if (__any(spill)) {
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                    for (int b = 0; b < B; ++b)
-                        if (li[r][b] < 0) c[r][b] = M.col[-1 - li[r][b]];
-            }
-            double x[R][B];
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int b = 0; b < B; ++b) x[r][b] = xf(c[r][b]);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const int k = li[r][b];
-                    const double v = k < 0 ? M.val[-1 - k] : W.val[k];
-                    const bool on = t0 + b < n[r];
-                    acc[r] += on ? v * x[r][b] : 0.0;
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (n[r] > 0) epi((s + r * NW) * kWave + lane, acc[r], pv[r]);
-    }
-}
-
-__device__ __forceinline__ double project(double v) { return v < 0.0 ? 0.0 : v; }
-
-// BBPGD state per contact: (gamma, g) interleaved so that a column costs one
-// 16-byte gather.
-struct GG {
-    double gam, g;
-};
-
 struct MatSolve {
     MatView M;
     const double *q;
@@ -385,137 +164,12 @@ template <int R, int BS>
 __global__ void __launch_bounds__(BS) k_bbpgd_mat(MatSolve A) {
     GridBarrier bar;
     bar.init(A.sync);
-    const SliceChunk rc = slice_chunk(A.M);
+    const int L = logical_block();
+    const SliceChunk rc = slice_chunk(A.M, L, gridDim.x);
     const WaveCache W = wave_cache<R, BS>(A.M, rc, A.cache);
     fill_cache<R, BS>(A.M, rc, W);
-    const int l0 = rc.l0, l1 = rc.l1;
-    double alpha = 0.0, res = 0.0, tot[4];
-    int iters = 0, mvops = 0, status = SC_NOT_CONVERGED, ndegen = 0;
-    bool ok;
-
-    // step 2: g0 = M gamma0 + q
-    {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        const double *x = A.gamma;
-        GG *z0 = A.z[0];
-        spmv_pass<R, BS>(A.M, rc, W, [&](int l) { return GG{x[l], A.q[l]}; },
-                              [&](int m) { return x[m]; }, [&](int l, double v, GG pq) {
-            const double gl = v + pq.g;
-            const double gm = pq.gam;
-            z0[l] = GG{gm, gl};
-            const double mm = gm < gl ? gm : gl;
-            acc[0] += mm * mm;
-            acc[1] += gl * gl;
-        });
-        write_partial<4, BS>(A.part, acc);
-    }
-    ok = bar.sync();
-    grid_reduce<4, BS>(A.part, tot);
-    mvops = 1;
-    res = sqrt(tot[0]);
-    const double g0g0 = tot[1];
-    int last = 0;  // buffer holding the last iterate
-    if (!ok) {
-        status = SC_ERR_TIMEOUT;
-    } else if (!isfinite(res)) {
-        status = SC_ERR_NONFINITE;
-    } else if (res < A.tol) {
-        status = SC_OK;  // steps 3-5
-    } else {
-        // step 6: alpha0 = g0^T g0 / g0^T M g0 (the diagonal leads each row)
-        {
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            const GG *z0 = A.z[0];
-            spmv_pass<R, BS>(A.M, rc, W,
-                                  [&](int l) { return GG{z0[l].g, mat_diag(A.M, l)}; },
-                                  [&](int m) { return z0[m].g; },
-                                  [&](int l, double v, GG pd) {
-                                      acc[0] += pd.gam * v;
-                                      acc[1] = fmax(acc[1], pd.g);
-                                  });
-            write_partial<4, BS, 1>(A.part, acc);
-        }
-        ok = bar.sync();
-        grid_reduce<4, BS, 1>(A.part, tot);
-        mvops = 2;
-        if (tot[0] > 0.0 && isfinite(tot[0]) && isfinite(g0g0)) {
-            alpha = g0g0 / tot[0];
-        } else {
-            alpha = tot[1] > 0.0 ? 1.0 / tot[1] : 1.0;
-            ++ndegen;
-        }
-        if (!ok) status = SC_ERR_TIMEOUT;
-        for (int j = 1; ok && j <= A.max_iter; ++j) {
-            const GG *zc = A.z[(j - 1) & 1];
-            GG *zn = A.z[j & 1];
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            // steps 8-10 in one pass: gamma_j formed per column on the fly
-            struct Own {
-                GG z;
-                double q;
-            };
-            spmv_pass<R, BS>(
-                A.M, rc, W, [&](int l) { return Own{zc[l], A.q[l]}; },
-                [&](int m) {
-                    const GG zm = zc[m];
-                    return project(zm.gam - alpha * zm.g);
-                },
-                [&](int l, double v, const Own &o) {
-                    const GG zl = o.z;
-                    const double gm = project(zl.gam - alpha * zl.g);
-                    const double gl = v + o.q;
-                    zn[l] = GG{gm, gl};
-                    const double mm = gm < gl ? gm : gl;
-                    const double s = gm - zl.gam, y = gl - zl.g;
-                    acc[0] += mm * mm;
-                    acc[1] += s * s;
-                    acc[2] += s * y;
-                    acc[3] += y * y;
-                });
-            write_partial<4, BS>(A.part, acc);
-            ok = bar.sync();
-            grid_reduce<4, BS>(A.part, tot);
-            iters = j;
-            last = j & 1;
-            ++mvops;
-            res = sqrt(tot[0]);
-            if (!ok) {
-                status = SC_ERR_TIMEOUT;
-                break;
-            }
-            if (!isfinite(res)) {
-                status = SC_ERR_NONFINITE;
-                break;
-            }
-            if (res < A.tol) {
-                status = SC_OK;
-                break;
-            }
-            const bool bb2 = (A.bb == 2) || (A.bb == 3 && (j % 2 == 0));
-            const double num = bb2 ? tot[2] : tot[1];
-            const double den = bb2 ? tot[3] : tot[2];
-            if (den > 0.0 && num > 0.0 && isfinite(num) && isfinite(den))
-                alpha = num / den;
-            else
-                ++ndegen;
-        }
-    }
-    // each workgroup wrote its own rows of the last iterate; copy them out
-    const GG *zf = A.z[last];
-    for (int l = l0 + threadIdx.x; l < l1; l += BS) {
-        const GG zl = zf[l];
-        A.gamma[l] = zl.gam;
-        A.g[l] = zl.g;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        SolveCtrl &c = *A.ctrl;
-        c.alpha = alpha;
-        c.res = res;
-        c.iters = iters;
-        c.mvops = mvops;
-        c.status = status;
-        c.ndegen = ndegen;
-    }
+    bbpgd_rows<R, BS>(A.M, rc, W, A.q, A.gamma, A.gamma, A.g, A.z[0], A.z[1], A.part, kPartHalf,
+                      L, gridDim.x, bar, A.tol, A.max_iter, A.bb, A.ctrl);
 }
 
 // CG state per contact: (r_{i-1}, w_{i-1} = A r_{i-1}, s_{i-2}) interleaved,
@@ -546,7 +200,7 @@ template <int R, int BS>
 __global__ void __launch_bounds__(BS) k_cg_mat(MatCg A) {
     GridBarrier bar;
     bar.init(A.sync);
-    const SliceChunk rc = slice_chunk(A.M);
+    const SliceChunk rc = slice_chunk(A.M, logical_block(), gridDim.x);
     const WaveCache W = wave_cache<R, BS>(A.M, rc, A.cache);
     fill_cache<R, BS>(A.M, rc, W);
     double tot[2];
@@ -563,10 +217,10 @@ __global__ void __launch_bounds__(BS) k_cg_mat(MatCg A) {
             acc[0] += rl * rl;
             acc[1] += wl * rl;
         });
-        write_partial<2, BS>(A.part, acc);
+        write_partial<2, BS>(part_buf(A.part, 0), acc);
     }
     ok = bar.sync();
-    grid_reduce<2, BS>(A.part, tot);
+    grid_reduce<2, BS>(part_buf(A.part, 0), tot);
     const double bnorm2 = tot[0];
     double gam_prev = tot[0], alpha = 0.0, beta = 0.0, res = bnorm2 > 0.0 ? 1.0 : 0.0;
     int iters = 0, status = SC_NOT_CONVERGED;
@@ -604,9 +258,9 @@ __global__ void __launch_bounds__(BS) k_cg_mat(MatCg A) {
                     acc[0] += rl * rl;
                     acc[1] += wl * rl;
                 });
-            write_partial<2, BS>(A.part, acc);
+            write_partial<2, BS>(part_buf(A.part, i), acc);
             ok = bar.sync();
-            grid_reduce<2, BS>(A.part, tot);
+            grid_reduce<2, BS>(part_buf(A.part, i), tot);
             iters = i;
             res = sqrt(tot[0] / bnorm2);
             if (!ok) {

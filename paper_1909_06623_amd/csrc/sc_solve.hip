@@ -332,7 +332,7 @@ size_t solve_ws_bytes(int32_t n, int32_t cap) {
     size_t b = 0;
     b += align_up(4 * cc * sizeof(double), 256);          // second gamma/g buffers or (gamma, g) records
     b += align_up(8 * nn * sizeof(double), 256);          // U (rank order)
-    b += align_up(4 * kMaxReduceBlocks * sizeof(double), 256);
+    b += align_up(2 * kPartHalf * sizeof(double), 256);
     b += align_up(sizeof(GridSync), 256);
     b += align_up(sizeof(Ctrl), 256);
     return b + 2048;
@@ -414,7 +414,7 @@ extern "C" int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
     double *zbuf = cv.take<double>(4 * static_cast<size_t>(c->capacity));
     double *gam1 = zbuf, *g1 = zbuf + c->capacity;
     double *U = cv.take<double>(8 * static_cast<size_t>(n));
-    double *part = cv.take<double>(4 * kMaxReduceBlocks);
+    double *part = cv.take<double>(2 * kPartHalf);
     GridSync *sync = cv.take<GridSync>(1);
     Ctrl *ctrl = cv.take<Ctrl>(1);
     if (!cv.ok) return SC_ERR_WORKSPACE;

@@ -125,4 +125,50 @@ struct GridBarrier {
     }
 };
 
+// Returns false on timeout: waits until the monotonic counter has reached
+// `target` (modulo 2^32; a member is never more than one barrier ahead).
+__device__ __forceinline__ bool spin_reach(unsigned *word, unsigned target, unsigned *err) {
+    unsigned polls = 0;
+    while (static_cast<int>(ld_relaxed(word) - target) < 0) {
+        if (++polls > (1u << 21)) {
+            __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        if (ld_relaxed(err)) return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+// Barrier of a team of workgroups that share one XCD (and so one L2): each
+// member waits for its stores to reach L2, bumps the team's counter and waits
+// until every member has; the acquire invalidates the member's caches. No L2
+// write-back is needed inside one XCD. A team of one is a workgroup barrier.
+struct alignas(256) TeamSync {
+    unsigned cnt[32];   // arrivals, monotonic
+    unsigned item[32];  // work item handed to the team by its leader
+};
+
+struct TeamBarrier {
+    TeamSync *s;
+    unsigned *err;
+    unsigned members, gen;
+
+    __device__ bool sync() {
+        __shared__ int ok;
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (members <= 1) return true;
+        ++gen;
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(&s->cnt[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const bool good = spin_reach(&s->cnt[0], gen * members, err);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            ok = good ? 1 : 0;
+        }
+        __syncthreads();
+        return ok != 0;
+    }
+};
+
 }  // namespace sc

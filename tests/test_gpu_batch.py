@@ -1,0 +1,112 @@
+"""Batched persistent solve: every instance of a batch of uneven, mixed
+sphere/rod suspensions agrees with the oracle; results are reproducible
+(eager and graph replays bitwise equal); the autotuner reports its timings."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _instances(count, n_max, seed):
+    import paper_1909_06623_amd as sc
+    sus, _ = W.batched_instances(count=count, seed=seed, n_min=30, n_max=n_max)
+    items = []
+    for s in sus:
+        P = sc.Particles.from_suspension(s)
+        box = sc.Box(tuple(s.box))
+        u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
+        con = sc.build_contacts(P, box, s.delta, u_nc, s.dt)
+        items.append((P, con))
+    return sus, items
+
+
+def _check_instance(s, con, gam, g, tol_rel, tol):
+    c, u_orc, q = O.setup(s)
+    assert con.count == c.nc
+    if c.nc == 0:
+        return
+    pm = con.canonical_order().cpu().numpy()
+    gg = g.cpu().numpy()[pm]
+    ga = gam.cpu().numpy()[pm]
+    go, g_o, sto = O.bbpgd(s, c, q, tol=1e-10)
+    # g = M gamma + q and F_c = D gamma are unique at the minimum (also for
+    # the singular M of overlapping sphere clusters)
+    np.testing.assert_allclose(gg, g_o, rtol=0, atol=tol_rel * max(1.0, np.abs(g_o).max()))
+    F = O.D_apply(s.n, c, ga)
+    Fo = O.D_apply(s.n, c, go)
+    np.testing.assert_allclose(F, Fo, rtol=0, atol=tol_rel * max(1.0, np.abs(Fo).max()))
+    assert np.all(ga >= 0.0)
+    assert np.linalg.norm(np.minimum(ga, gg)) < tol
+
+
+@pytest.mark.parametrize("team", [1, 4])
+def test_batch_matches_oracle_and_is_reproducible(team):
+    import paper_1909_06623_amd as sc
+    sus, items = _instances(14, 2500, seed=W.SEED_BASE + 700)
+    _say(f"batch team={team}: {len(items)} instances, "
+         f"n_c {sum(c.count for _, c in items)}")
+    b = sc.Batch(items, tol=1e-9, team=team)
+    b.solve()
+    st, info = b.stats()
+    assert info["team"] == team
+    assert all(x["status"] == 0 for x in st), [x["status"] for x in st]
+    g1 = [x.clone() for x in b.gamma]
+    for s, (P, con), gam, g in zip(sus, items, b.gamma, b.g):
+        _check_instance(s, con, gam, g, 1e-6, 1e-9)
+    b.solve()
+    assert all(torch.equal(a, x) for a, x in zip(g1, b.gamma))
+    for _ in range(3):  # graph replays, with eager work in between
+        b.graph_solve()
+        st2, _ = b.stats()
+        assert [x["iters"] for x in st2] == [x["iters"] for x in st]
+        assert all(torch.equal(a, x) for a, x in zip(g1, b.gamma))
+        b.solve()
+        torch.cuda.synchronize()
+    b.close()
+
+
+def test_batch_autotune_and_tiny_instances():
+    import paper_1909_06623_amd as sc
+    sus, items = _instances(9, 400, seed=W.SEED_BASE + 701)
+    _say(f"batch autotune: {len(items)} instances")
+    b = sc.Batch(items, tol=1e-8, team=0)
+    b.solve()
+    st, info = b.stats()
+    assert info["team"] in (1, 2, 4, 8, 16, 32)
+    assert all(t > 0 for t in info["tune_ms"])
+    assert all(x["status"] == 0 for x in st)
+    for s, (P, con), gam, g in zip(sus, items, b.gamma, b.g):
+        _check_instance(s, con, gam, g, 1e-5, 1e-8)
+    b.close()
+
+
+def test_batch_empty_and_contactless():
+    import paper_1909_06623_amd as sc
+    _say("batch: no instances; an instance without contacts")
+    b = sc.Batch([], tol=1e-6, team=1)
+    b.solve()
+    st, info = b.stats()
+    assert st == []
+    s = W.spheres(27, 0.3, seed=2)
+    g = np.stack(np.meshgrid(*[np.arange(3)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    s.pos = 4.0 * g + 1.0
+    s.box = np.full(3, 12.0)
+    P = sc.Particles.from_suspension(s)
+    con = sc.build_contacts(P, sc.Box(tuple(s.box)), s.delta,
+                            sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda()), s.dt)
+    assert con.count == 0
+    s2, items = _instances(2, 300, seed=W.SEED_BASE + 702)
+    b = sc.Batch([(P, con)] + items, tol=1e-8, team=2)
+    b.solve()
+    st, _ = b.stats()
+    assert [x["status"] for x in st] == [0, 0, 0]
+    assert st[0]["mvops"] == 1

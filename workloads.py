@@ -246,10 +246,15 @@ def workload(k, scale=1.0):
 def batched_instances(count=512, seed=None, n_min=200, n_max=20000,
                       phi_lo=0.1, phi_hi=0.4):
     """Independent suspensions of uneven size: N log-uniform in
-    [n_min, n_max], volume fraction uniform in [phi_lo, phi_hi], sphere or
-    rod with probability 1/2. Rod boxes are widened to at least twice the
-    interaction range (the volume fraction is lowered to fit); returns the
-    list of suspensions and the indices of the widened instances."""
+    [n_min, n_max], a density parameter phi uniform in [phi_lo, phi_hi],
+    sphere or rod with probability 1/2. Spheres take phi as their volume
+    fraction. For rods phi sets the contact density instead: 15 phi close
+    pairs per rod (6 at phi = 0.4, as the 100k-rod suspension), because
+    uniformly placed rods of aspect ratio 20 at a volume fraction above
+    about 0.2 have more contacts than 6 N rigid-body degrees of freedom, an
+    over-constrained LCP with a singular M. Rod boxes are widened to at
+    least twice the interaction range (lowering the density to fit); returns
+    the list of suspensions and the indices of the widened instances."""
     base = SEED_BASE + 5 if seed is None else seed
     meta = _rng(base)
     ns = np.rint(np.exp(meta.uniform(math.log(n_min), math.log(n_max), count))).astype(int)
@@ -262,7 +267,7 @@ def batched_instances(count=512, seed=None, n_min=200, n_max=20000,
             s = spheres(int(ns[k]), float(phis[k]), base + 1 + k,
                         name=f"inst{k}_spheres")
         else:
-            s = rods(int(ns[k]), base + 1 + k, phi=float(phis[k]),
+            s = rods(int(ns[k]), base + 1 + k, pairs_per_rod=15.0 * float(phis[k]),
                      min_side=2.0 * rod_range, name=f"inst{k}_rods")
             if abs(s.box[0] - 2.0 * rod_range) < 1e-12:
                 widened.append(k)
