@@ -315,8 +315,21 @@ def bbpgd(s, c, q, gamma0=None, tol=None, max_iter=100000, bb=1):
     return gamma, g, st
 
 
-def _solve_active(M, q, act):
-    """gamma_A solving M_AA gamma_A = -q_A (gamma_I = 0)."""
+def _cg(A, b, x0=None, rtol=1e-14, maxiter=200000):
+    """Jacobi-preconditioned conjugate gradients on an SPD sparse A."""
+    import scipy.sparse.linalg as spla
+    d = A.diagonal()
+    pre = spla.LinearOperator(A.shape, matvec=lambda v: v / d)
+    x, info = spla.cg(A, b, x0=x0, rtol=rtol, atol=0.0, maxiter=maxiter, M=pre)
+    if info != 0:
+        raise RuntimeError(f"oracle CG did not converge ({info})")
+    return x
+
+
+def _solve_active(M, q, act, x0=None):
+    """gamma_A solving M_AA gamma_A = -q_A (gamma_I = 0): a dense solve for
+    small blocks, a sparse LU up to 20000 rows, Jacobi-preconditioned CG to a
+    relative residual of 1e-14 beyond (started from x0 when given)."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla
     gamma = np.zeros(q.shape[0])
@@ -327,8 +340,11 @@ def _solve_active(M, q, act):
     if idx.size <= 3000:
         gamma[idx] = np.linalg.solve(Maa.toarray() if sp.issparse(Maa) else Maa,
                                      -q[idx])
-    else:
+    elif idx.size <= 20000:
         gamma[idx] = spla.splu(sp.csc_matrix(Maa)).solve(-q[idx])
+    else:
+        gamma[idx] = _cg(sp.csr_matrix(Maa), -q[idx],
+                         None if x0 is None else np.asarray(x0, dtype=np.float64)[idx])
     return gamma
 
 
@@ -340,8 +356,9 @@ def polish(s, c, q, gamma, max_pass=50):
     M = M_matrix(s, c)
     q = _f64(q)
     act = np.asarray(gamma) > 0.0
+    gam = np.asarray(gamma, dtype=np.float64)
     for p in range(max_pass):
-        gam = _solve_active(M, q, act)
+        gam = _solve_active(M, q, act, gam)
         g = M @ gam + q
         leave = act & (gam < 0.0)
         join = (~act) & (g < 0.0)
@@ -359,7 +376,7 @@ def adjoint(s, c, q, u_nc, gamma, dL_dgamma=None, dL_dF=None, method="direct"):
     per-contact geometric derivatives (orientations, radii, Mob and U_nc held
     fixed). Pinned by central finite differences of polished solves and by
     the two-sphere closed form; parity unpinned by the paper."""
-    import scipy.sparse.linalg as spla
+    import scipy.sparse as sp
     lib = _load()
     n = s.n
     gamma = _f64(gamma)
@@ -375,8 +392,7 @@ def adjoint(s, c, q, u_nc, gamma, dL_dgamma=None, dL_dF=None, method="direct"):
         if method == "direct":
             w = _solve_active(M, -b, act)
         else:
-            sol, info = spla.cg(Maa, b[idx], rtol=1e-14, maxiter=100000)
-            w[idx] = sol
+            w[idx] = _cg(sp.csr_matrix(Maa), b[idx])
     axis, mob = _f64(s.axis), _f64(s.mob)
     Uc = mobility(axis, mob, D_apply(n, c, gamma))
     Vw = mobility(axis, mob, D_apply(n, c, w))
