@@ -67,8 +67,9 @@ __global__ void k_slice_sums(int nc, int ns, const int32_t *len, int32_t *soff, 
 }
 
 // Walks the entries of row l in storage order: the diagonal first, then the
-// other contacts of ci in ci's incidence order, then those of cj in cj's
-// incidence order. M_lm = b_mk^T (Mob_k a_lk) for the shared particle k.
+// other contacts of its lower-ranked particle in that particle's incidence
+// order, then those of the other particle. M_lm = b_mk^T (Mob_k a_lk) for the
+// shared particle k.
 struct RowWalk {
     int l, ends[2], side, e, e1, own;
     V3 u, w;
@@ -96,8 +97,12 @@ struct RowWalk {
     // the diagonal; leaves the walk on the first off-diagonal entry
     __device__ double start(const ChainView &C, int row) {
         l = row;
-        ends[0] = C.cs[2 * row];
-        ends[1] = C.cs[2 * row + 1];
+        // the lower-ranked particle first: consecutive rows share it (rows are
+        // grouped by it), so their entries line up depth by depth and the
+        // lanes of one gather touch the same records
+        const int a = C.cs[2 * row], b = C.cs[2 * row + 1];
+        ends[0] = a < b ? a : b;
+        ends[1] = a < b ? b : a;
         const double d1 = open(C, 1);
         const double d0 = open(C, 0);
         settle(C);
@@ -203,13 +208,14 @@ __global__ void __launch_bounds__(BS) k_cg_mat(MatCg A) {
     const SliceChunk rc = slice_chunk(A.M, logical_block(), gridDim.x);
     const WaveCache W = wave_cache<R, BS>(A.M, rc, A.cache);
     fill_cache<R, BS>(A.M, rc, W);
+    const WaveMeta<R> Mt = wave_meta<R, BS>(A.M, rc);
     double tot[2];
     bool ok;
     {
         double acc[2] = {0.0, 0.0};
         const RWS *z0 = A.z[0];
         RWS *z1 = A.z[1];
-        spmv_pass<R, BS>(A.M, rc, W, [&](int l) { return GG{z0[l].r, A.gamma[l]}; },
+        spmv_pass<R, BS>(A.M, rc, W, Mt, [&](int l) { return GG{z0[l].r, A.gamma[l]}; },
                               [&](int m) { return z0[m].r; }, [&](int l, double v, GG o) {
             const double rl = o.gam;
             const double wl = o.g > 0.0 ? v : 0.0;
@@ -241,7 +247,7 @@ __global__ void __launch_bounds__(BS) k_cg_mat(MatCg A) {
                 double p, x, act;
             };
             spmv_pass<R, BS>(
-                A.M, rc, W, [&](int l) { return Own{zc[l], A.p[l], A.x[l], A.gamma[l]}; },
+                A.M, rc, W, Mt, [&](int l) { return Own{zc[l], A.p[l], A.x[l], A.gamma[l]}; },
                 [&](int m) {
                     const RWS zm = zc[m];
                     return zm.r - alpha * (zm.w + beta * zm.s);
@@ -254,7 +260,9 @@ __global__ void __launch_bounds__(BS) k_cg_mat(MatCg A) {
                     A.p[l] = pl;
                     const double rl = zl.r - alpha * sl;
                     const double wl = o.act > 0.0 ? v : 0.0;
-                    zn[l] = RWS{rl, wl, sl, 0.0};
+                    __builtin_nontemporal_store(rl, &zn[l].r);
+                    __builtin_nontemporal_store(wl, &zn[l].w);
+                    __builtin_nontemporal_store(sl, &zn[l].s);
                     acc[0] += rl * rl;
                     acc[1] += wl * rl;
                 });

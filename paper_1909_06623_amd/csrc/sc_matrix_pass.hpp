@@ -136,6 +136,44 @@ __device__ void fill_cache(const MatView &M, const SliceChunk &ch, const WaveCac
     __syncthreads();
 }
 
+// Slice metadata of a wave's first kMetaGroups groups of R slices: the
+// lane's row length, each slice's first entry, entry count and width. They
+// do not change during a solve, so the pass reads them from registers
+// instead of starting every iteration with a dependent global load.
+constexpr int kMetaGroups = 2;
+
+template <int R>
+struct WaveMeta {
+    int n[kMetaGroups][R], e0[kMetaGroups][R], ne[kMetaGroups][R], wid[kMetaGroups][R];
+};
+
+template <int R, int BS>
+__device__ __forceinline__ void slice_meta(const MatView &M, const SliceChunk &ch, int sr,
+                                           int &n, int &e0, int &ne, int &wid) {
+    const int lane = threadIdx.x % kWave;
+    n = e0 = ne = wid = 0;
+    if (sr < ch.s1) {
+        const int l = sr * kWave + lane;
+        n = l < M.nc ? M.len[l] : 0;
+        e0 = __builtin_amdgcn_readfirstlane(M.soff[sr]);
+        ne = __builtin_amdgcn_readfirstlane(M.soff[sr + 1]) - e0;
+        wid = __builtin_amdgcn_readfirstlane(M.swid[sr]);
+    }
+}
+
+template <int R, int BS>
+__device__ WaveMeta<R> wave_meta(const MatView &M, const SliceChunk &ch) {
+    constexpr int NW = BS / kWave;
+    WaveMeta<R> m;
+#pragma unroll
+    for (int k = 0; k < kMetaGroups; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            slice_meta<R, BS>(M, ch, ch.s0 + threadIdx.x / kWave + (k * R + r) * NW, m.n[k][r],
+                              m.e0[k][r], m.ne[k][r], m.wid[k][r]);
+    return m;
+}
+
 // One pass over the chunk's rows: acc_l = sum_k val_k x(col_k), summed in
 // storage order (so a row's value does not depend on the launch shape).
 // Each wave takes R slices at a time (one lane per row). Per batch of B
@@ -143,35 +181,45 @@ __device__ void fill_cache(const MatView &M, const SliceChunk &ch, const WaveCac
 // and accumulates. The batch has no per-entry branch, so its gathers are in
 // flight together: a lane without an entry at a depth gathers its own row
 // and adds nothing. pre(l) loads the row's own inputs up front; epi(l, acc,
-// pre) finishes the row.
+// pre) finishes the row. LDS residency follows the walk of fill_cache.
 template <int R, int BS, class P, class X, class E>
 __device__ __forceinline__ void spmv_pass(const MatView &M, const SliceChunk &ch,
-                                          const WaveCache &W, P pre, X xf, E epi) {
+                                          const WaveCache &W, const WaveMeta<R> &Mt, P pre,
+                                          X xf, E epi) {
     constexpr int NW = BS / kWave;
     constexpr int B = 8 / R;  // depths per batch (measured best with 1024 threads)
     using Pre = decltype(pre(0));
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const unsigned long long below = (1ull << lane) - 1ull;
-    int used = 0;
-    for (int s = ch.s0 + wv; s < ch.s1; s += NW * R) {
+    int used = 0, grp = 0;
+    for (int s = ch.s0 + wv; s < ch.s1; s += NW * R, ++grp) {
         int n[R], pos[R], e0[R], lds0[R], nlds[R], row[R];
         Pre pv[R];
         double acc[R];
         int wid = 0;
-        walk_wave_slices<R, BS>(M, ch, W.cap, s, used, [&](int r, int f, int, int at, int k) {
-            e0[r] = f;
-            lds0[r] = at;
-            nlds[r] = k;
-        });
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int sr = s + r * NW;
-            const bool have = sr < ch.s1;
+            int ne, w;
+            if (grp < kMetaGroups) {
+#pragma unroll
+                for (int k = 0; k < kMetaGroups; ++k)
+                    if (k == grp) {
+                        n[r] = Mt.n[k][r];
+                        e0[r] = Mt.e0[k][r];
+                        ne = Mt.ne[k][r];
+                        w = Mt.wid[k][r];
+                    }
+            } else {
+                slice_meta<R, BS>(M, ch, sr, n[r], e0[r], ne, w);
+            }
+            lds0[r] = used;
+            nlds[r] = min(ne, W.cap - used);
+            used += nlds[r];
+            wid = max(wid, w);
             const int l = sr * kWave + lane;
             row[r] = min(l, M.nc - 1);  // a valid row for lanes past the end
-            n[r] = have && l < M.nc ? M.len[l] : 0;
             pos[r] = e0[r];
-            wid = max(wid, have ? __builtin_amdgcn_readfirstlane(M.swid[sr]) : 0);
             pv[r] = pre(row[r]);
             acc[r] = 0.0;
         }
@@ -252,6 +300,7 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
                            Bar &bar,
                            double tol, int max_iter, int bb, SolveCtrl *ctrl) {
     const MatView &M = Mv;
+    const WaveMeta<R> Mt = wave_meta<R, BS>(M, rc);
     GG *const z[2] = {zb0, zb1};
     const int l0 = rc.l0, l1 = rc.l1;
     double alpha = 0.0, res = 0.0, tot[4];
@@ -262,7 +311,7 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
     {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         GG *z0 = z[0];
-        spmv_pass<R, BS>(M, rc, W, [&](int l) { return GG{x0 ? x0[l] : 0.0, q[l]}; },
+        spmv_pass<R, BS>(M, rc, W, Mt, [&](int l) { return GG{x0 ? x0[l] : 0.0, q[l]}; },
                          [&](int m) { return x0 ? x0[m] : 0.0; }, [&](int l, double v, GG pq) {
             const double gl = v + pq.g;
             const double gm = pq.gam;
@@ -290,7 +339,7 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
         {
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
             const GG *z0 = z[0];
-            spmv_pass<R, BS>(M, rc, W, [&](int l) { return GG{z0[l].g, mat_diag(M, l)}; },
+            spmv_pass<R, BS>(M, rc, W, Mt, [&](int l) { return GG{z0[l].g, mat_diag(M, l)}; },
                              [&](int m) { return z0[m].g; }, [&](int l, double v, GG pd) {
                                  acc[0] += pd.gam * v;
                                  acc[1] = fmax(acc[1], pd.g);
@@ -317,7 +366,7 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
                 double q;
             };
             spmv_pass<R, BS>(
-                M, rc, W, [&](int l) { return Own{zc[l], q[l]}; },
+                M, rc, W, Mt, [&](int l) { return Own{zc[l], q[l]}; },
                 [&](int m) {
                     const GG zm = zc[m];
                     return project(zm.gam - alpha * zm.g);
@@ -326,7 +375,9 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
                     const GG zl = o.z;
                     const double gm = project(zl.gam - alpha * zl.g);
                     const double gl = v + o.q;
-                    zn[l] = GG{gm, gl};
+                    // streamed past L2: the next barrier's write-back has less to flush
+                    __builtin_nontemporal_store(gm, &zn[l].gam);
+                    __builtin_nontemporal_store(gl, &zn[l].g);
                     const double mm = gm < gl ? gm : gl;
                     const double s = gm - zl.gam, y = gl - zl.g;
                     acc[0] += mm * mm;

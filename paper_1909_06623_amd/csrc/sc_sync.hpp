@@ -6,11 +6,11 @@
 // A write-back in every workgroup costs ~25 ns per workgroup (serialised in
 // the L2), so the release half works per XCD: every workgroup waits for its
 // own stores to reach L2 and bumps its XCD's counter; the last arrival on an
-// XCD writes back that L2 once and meets the other XCDs' last arrivals on a
-// top counter, then releases its XCD's workgroups. The acquire half (an
-// agent-scope invalidate of L1 and L2) is done by every workgroup: measured
-// on gfx950, a group-scope invalidate does not drop stale L1 lines of the
-// other CUs. Workgroups are grouped by the hardware XCC_ID register, counted
+// XCD writes back that L2 once and then bumps a top counter; the last of
+// those publishes the new generation, which every workgroup polls (all
+// XCDs' data is in memory by then). The acquire half (an agent-scope
+// invalidate of L1 and L2) is done by every workgroup: measured on gfx950,
+// a group-scope invalidate does not drop stale L1 lines of the other CUs. Workgroups are grouped by the hardware XCC_ID register, counted
 // at kernel start. Counters only ever increase (the last
 // arrival of generation g on a group of m members reads g*m - 1, modulo
 // 2^32), so no reset has to be ordered against the next barrier.
@@ -27,7 +27,6 @@ constexpr int kMaxXcc = 16;
 
 struct alignas(256) GridSync {
     unsigned xcnt[kMaxXcc][32];  // arrivals per XCD (one 128-byte line each)
-    unsigned xgen[kMaxXcc][32];  // release generation per XCD
     unsigned xmem[kMaxXcc][32];  // workgroups per XCD
     unsigned top[32];            // XCD arrivals
     unsigned gen[32];            // global generation
@@ -111,10 +110,8 @@ struct GridBarrier {
                 } else {
                     good = spin_until(&s->gen[0], target, s);
                 }
-                __hip_atomic_store(&s->xgen[xcc][0], target, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                good = spin_until(&s->xgen[xcc][0], target, s);
+                good = spin_until(&s->gen[0], target, s);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             ok = good ? 1 : 0;
