@@ -165,12 +165,16 @@ __device__ __forceinline__ PairGeo ranked_geo(int a, int b, const Ranked &R, con
                     pj_[3], R.hl[rj]);
 }
 
-// Visit every partner u > t (by rank) of rank t whose pair has Phi <= delta,
-// calling fn(u, geo).
+// Lanes that share one particle's 27-cell stencil in the pair search (lane j
+// takes the neighbour cells whose index in (z, y, x) order is j modulo this).
+constexpr int kPairLanes = 8;
+
+// Visit every partner u > t (by rank) of rank t whose pair has Phi <= delta
+// among the neighbour cells of lane `lane`'s share, calling fn(u, geo).
 template <class Fn>
-__device__ __forceinline__ void for_close_partners(int t, const Ranked &R, const Plan &pl,
-                                                   const Grid &g, const int *cell_start,
-                                                   Fn fn) {
+__device__ __forceinline__ void for_close_partners(int t, int lane, const Ranked &R,
+                                                   const Plan &pl, const Grid &g,
+                                                   const int *cell_start, Fn fn) {
     const double *pt = R.prec + 4 * static_cast<long long>(t);
     const V3 ct = v3(pt[0], pt[1], pt[2]);
     const double Rt = pt[3], ht = R.hl[t];
@@ -180,60 +184,90 @@ __device__ __forceinline__ void for_close_partners(int t, const Ranked &R, const
     const int kx = neighbours(cx, 0, g, nx), ky = neighbours(cy, 1, g, ny),
               kz = neighbours(cz, 2, g, nz);
     const PBox box = g.box();
-    for (int az = 0; az < kz; ++az)
-        for (int ay = 0; ay < ky; ++ay)
-            for (int ax = 0; ax < kx; ++ax) {
-                const int cc = (nz[az] * g.nc[1] + ny[ay]) * g.nc[0] + nx[ax];
-                int u = cell_start[cc];
-                const int end = cell_start[cc + 1];
-                if (u <= t) u = t + 1;
-                for (; u < end; ++u) {
-                    const double *pu = R.prec + 4 * static_cast<long long>(u);
-                    const V3 r = min_image(ct, v3(pu[0], pu[1], pu[2]), box);
-                    // the core distance is at least |r| - ht - hu
-                    const double reach = ht + R.hl[u] + Rt + pu[3] + g.delta;
-                    if (dot(r, r) > reach * reach * (1.0 + 1e-9)) continue;
-                    bool t_is_i;
-                    const PairGeo G = ranked_geo(t, u, R, pl, box, t_is_i);
-                    if (G.phi <= g.delta) fn(u, G);
-                }
+    const double *at = pl.pdat + 8 * static_cast<long long>(t);
+    const V3 pt_ax = v3(at[0], at[1], at[2]);
+    for (int idx = lane; idx < kx * ky * kz; idx += kPairLanes) {
+        const int ax = idx % kx, ay = (idx / kx) % ky, az = idx / (kx * ky);
+        const int cc = (nz[az] * g.nc[1] + ny[ay]) * g.nc[0] + nx[ax];
+        int u = cell_start[cc];
+        const int end = cell_start[cc + 1];
+        if (u <= t) u = t + 1;
+        for (; u < end; ++u) {
+            const double *pu = R.prec + 4 * static_cast<long long>(u);
+            const V3 r = min_image(ct, v3(pu[0], pu[1], pu[2]), box);
+            // the core distance is at least |r| - ht - hu
+            const double hu = R.hl[u];
+            const double reach = ht + hu + Rt + pu[3] + g.delta;
+            if (dot(r, r) > reach * reach * (1.0 + 1e-9)) continue;
+            if (ht > 0.0 && hu > 0.0) {
+                // two segments are no closer than their lines: skip pairs whose
+                // lines are farther apart than R_t + R_u + delta (near-parallel
+                // axes give w ~ 0 and fall through to the exact test)
+                const double *au = pl.pdat + 8 * static_cast<long long>(u);
+                const V3 w = cross(pt_ax, v3(au[0], au[1], au[2]));
+                const double rw = dot(r, w), lim = Rt + pu[3] + g.delta;
+                if (rw * rw > lim * lim * dot(w, w) * (1.0 + 1e-9)) continue;
             }
+            bool t_is_i;
+            const PairGeo G = ranked_geo(t, u, R, pl, box, t_is_i);
+            if (G.phi <= g.delta) fn(u, G);
+        }
+    }
 }
 
+// Count pass: kPairLanes consecutive threads per rank; per-lane counts go to
+// lane_cnt, the rank's total to cptr.
 __global__ void k_count_pairs(int n, Ranked R, Plan pl, Grid g, const int *cell_start,
-                              int *flags) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
+                              int *lane_cnt, int *flags) {
+    const long long gid = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int t = static_cast<int>(gid / kPairLanes), lane = static_cast<int>(gid % kPairLanes);
+    if (t >= n) return;  // whole groups of kPairLanes leave together
     int cnt = 0, npar = 0, nzero = 0, nborder = 0;
-    for_close_partners(t, R, pl, g, cell_start, [&](int, const PairGeo &G) {
+    for_close_partners(t, lane, R, pl, g, cell_start, [&](int, const PairGeo &G) {
         ++cnt;
         npar += G.flags & 1;
         nzero += (G.flags >> 1) & 1;
         nborder += fabs(G.phi - g.delta) < 1e-12;
     });
-    pl.cptr[t] = cnt;
+    lane_cnt[gid] = cnt;
+    int tot = cnt;
+#pragma unroll
+    for (int off = kPairLanes / 2; off > 0; off >>= 1) tot += __shfl_xor(tot, off, kPairLanes);
+    if (lane == 0) pl.cptr[t] = tot;
     if (npar) atomicAdd(flags + kFlagParallel, npar);
     if (nzero) atomicAdd(flags + kFlagZero, nzero);
     if (nborder) atomicAdd(flags + kFlagBorder, nborder);
 }
 
-// Contacts of rank t (partners of higher rank, ascending): caller indices,
-// Phi, frame [l][9] = n, tau_i, tau_j oriented from ci (lower caller index)
-// to cj, and cs[l] = the ranks of (ci, cj).
+// Write pass: each lane stores its partners' ranks (even slots of cs) after
+// those of the lower lanes of its rank.
 __global__ void k_write_pairs(int n, Ranked R, Plan pl, Grid g, const int *cell_start,
-                              int *ci, int *cj, double *phi, double *frame) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+                              const int *lane_cnt) {
+    const long long gid = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int t = static_cast<int>(gid / kPairLanes), lane = static_cast<int>(gid % kPairLanes);
     if (t >= n) return;
-    const int base = pl.cptr[t], lim = pl.cptr[t + 1] - base;
-    int *part = pl.cs + 2 * static_cast<long long>(base);  // even slots: partner ranks
+    const int lim = lane_cnt[gid];
+    int before = 0;
+    for (int j = 0; j < lane; ++j) before += lane_cnt[gid - lane + j];
+    int *part = pl.cs + 2 * static_cast<long long>(pl.cptr[t] + before);
     int k = 0;
     // the count pass used the same pure predicate, so k ends at lim; the
     // bound only guards the segment
-    for_close_partners(t, R, pl, g, cell_start, [&](int u, const PairGeo &) {
+    for_close_partners(t, lane, R, pl, g, cell_start, [&](int u, const PairGeo &) {
         if (k < lim) part[2 * k] = u;
         ++k;
     });
-    if (k > lim) k = lim;
+}
+
+// Contacts of rank t (partners of higher rank, ascending): caller indices,
+// Phi, frame [l][9] = n, tau_i, tau_j oriented from ci (lower caller index)
+// to cj, and cs[l] = the ranks of (ci, cj).
+__global__ void k_finish_pairs(int n, Ranked R, Plan pl, Grid g, int *ci, int *cj, double *phi,
+                               double *frame) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int base = pl.cptr[t], k = pl.cptr[t + 1] - base;
+    int *part = pl.cs + 2 * static_cast<long long>(base);  // even slots: partner ranks
     for (int a = 1; a < k; ++a) {
         const int v = part[2 * a];
         int b = a - 1;
@@ -373,6 +407,7 @@ size_t contacts_ws_bytes(int32_t n, int32_t cap) {
     size_t b = 0;
     b += align_up(kFlagCount * sizeof(int), 256) + 256;     // flags, max extent
     b += 5 * align_up(nn * sizeof(int), 256);                // cell_of, members, cell_r, deg, fill
+    b += align_up(kPairLanes * nn * sizeof(int), 256);       // per-lane pair counts
     b += align_up(4 * nn * sizeof(double), 256);             // ranked centre + radius
     b += align_up(nn * sizeof(double), 256);                 // ranked half length
     b += 2 * align_up((nb + 1) * sizeof(int), 256);          // cell_start, cell_fill
@@ -430,6 +465,7 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     int *cell_r = cv.take<int>(n);
     int *deg = cv.take<int>(n);
     int *fill = cv.take<int>(n);
+    int *lane_cnt = cv.take<int>(static_cast<size_t>(kPairLanes) * n);
     double *prec = cv.take<double>(4 * static_cast<size_t>(n));
     double *hl = cv.take<double>(n);
     int *cell_start = cv.take<int>(nb + 1);
@@ -488,7 +524,8 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     Ranked R{prec, hl, cell_r};
 
     // partners of higher rank, then offsets
-    k_count_pairs<<<grid_for(n), kBlock, 0, stream>>>(n, R, pl, g, cell_start, flags);
+    const int pair_blocks = grid_for(static_cast<long long>(n) * kPairLanes);
+    k_count_pairs<<<pair_blocks, kBlock, 0, stream>>>(n, R, pl, g, cell_start, lane_cnt, flags);
     scan_exclusive(pl.cptr, pl.cptr, n, scan_tmp, stream);
     SC_HIP_TRY(hipMemcpyAsync(stage, pl.cptr + n, sizeof(int), hipMemcpyDeviceToDevice, stream));
     SC_HIP_TRY(hipMemcpyAsync(stage + 1, flags, kFlagCount * sizeof(int), hipMemcpyDeviceToDevice,
@@ -503,8 +540,9 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     c->n_borderline = hstage[1 + kFlagBorder];
     if (nc > c->capacity) return SC_ERR_CAPACITY;
 
-    k_write_pairs<<<grid_for(n), kBlock, 0, stream>>>(n, R, pl, g, cell_start, c->ci, c->cj,
-                                                      c->phi, c->frame);
+    k_write_pairs<<<pair_blocks, kBlock, 0, stream>>>(n, R, pl, g, cell_start, lane_cnt);
+    k_finish_pairs<<<grid_for(n), kBlock, 0, stream>>>(n, R, pl, g, c->ci, c->cj, c->phi,
+                                                       c->frame);
     // incidence lists and signed column entries
     SC_HIP_TRY(hipMemsetAsync(deg, 0, n * sizeof(int), stream));
     SC_HIP_TRY(hipMemsetAsync(fill, 0, n * sizeof(int), stream));
