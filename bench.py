@@ -66,8 +66,9 @@ def measured_traffic(iters):
 
 def batched(sc, W, torch, np, count):
     """512 independent suspensions (N log-uniform in [200, 20000], spheres or
-    rods): one persistent launch replayed from a HIP graph, against the same
-    instances solved one at a time with solve_lcp on the same GPU."""
+    rods), forward solve + adjoint of L = 1/2 ||D gamma||^2 each: one
+    persistent launch replayed from a HIP graph, against the same instances
+    solved one at a time (solve_lcp + solve_lcp_adjoint) on the same GPU."""
     sus, _ = W.batched_instances(count=count)
     items = []
     t0 = time.perf_counter()
@@ -75,12 +76,12 @@ def batched(sc, W, torch, np, count):
         P = sc.Particles.from_suspension(s)
         box = sc.Box(tuple(s.box))
         u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
-        items.append((P, sc.build_contacts(P, box, s.delta, u_nc, s.dt)))
+        items.append((P, sc.build_contacts(P, box, s.delta, u_nc, s.dt), box, u_nc, s.dt))
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
-    tol = 1e-6
+    tol, atol = 1e-6, 1e-8
     t0 = time.perf_counter()
-    b = sc.Batch(items, tol=tol, team=0)
+    b = sc.Batch(items, tol=tol, team=0, adjoint=1, adjoint_tol=atol)
     tune_s = time.perf_counter() - t0
     b.graph_solve()
     torch.cuda.synchronize()
@@ -90,31 +91,38 @@ def batched(sc, W, torch, np, count):
         b.graph_solve()
     torch.cuda.synchronize()
     batch_ms = 1e3 * (time.perf_counter() - t0) / reps
-    st, info = b.stats()
+    st, adj, info = b.stats()
     ws = sc.Workspace()
-    for P, con in items[:4]:  # warm the single-instance path
-        sc.solve_lcp(P, con, tol=tol, workspace=ws)
+
+    def one(P, con, box, u_nc, dt):
+        gam, g, s1, f_c, _ = sc.solve_lcp(P, con, tol=tol, want_fc=True, workspace=ws)
+        sc.solve_lcp_adjoint(P, box, con, u_nc, dt, gam, dL_df=f_c, tol=atol, workspace=ws)
+        return s1["iters"]
+
+    for it in items[:4]:  # warm the single-instance path
+        one(*it)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    single_iters = []
-    for P, con in items:
-        single_iters.append(sc.solve_lcp(P, con, tol=tol, workspace=ws)[2]["iters"])
+    single_iters = [one(*it) for it in items]
     torch.cuda.synchronize()
     single_ms = 1e3 * (time.perf_counter() - t0)
     b.close()
     n_tot = sum(s.n for s in sus)
     return {"instances": count, "particles": n_tot,
-            "contacts": sum(con.count for _, con in items),
-            "nnz_M": sum(con.nnz for _, con in items),
+            "contacts": sum(it[1].count for it in items),
+            "nnz_M": sum(it[1].nnz for it in items),
             "batch_ms": batch_ms, "one_at_a_time_ms": single_ms,
             "speedup": single_ms / batch_ms,
             "batch_particles_per_s": n_tot / (batch_ms * 1e-3),
             "team": info["team"], "tune_ms": info["tune_ms"], "tune_s": tune_s,
             "all_converged": all(x["status"] == 0 for x in st),
+            "adjoint_all_converged": all(x["status"] == 0 for x in adj),
+            "adjoint_cg_iters_sum": sum(x["iters"] for x in adj),
             "iters_max": max(x["iters"] for x in st),
             "iters_sum": sum(x["iters"] for x in st),
             "single_iters_sum": int(sum(single_iters)),
             "build_s": build_s, "tol": tol,
+            "adjoint_tol": atol, "work": "forward BBPGD + adjoint (CG, geometric gradient) per instance",
             "launch": "reset kernel + one cooperative persistent kernel, HIP graph replay"}
 
 

@@ -258,13 +258,22 @@ int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
 /* One LCP of a batch (an independent suspension): its particles, its
  * contacts from sc_build_contacts with the assembled M (c.mat_ready == 1),
  * and device buffers for gamma (IN: gamma_0 when warm-starting) and g,
- * [c.count] each. The batch keeps the pointers, not the structs' owners:
- * every buffer must outlive the batch. */
+ * [c.count] each. For the adjoint (opts->adjoint != 0) also the box, u_nc
+ * and dt the contacts were built with, an optional dL/dgamma [c.count]
+ * (NULL = 0) and the outputs dL_dq [c.count] and dL_dpos [p.n][3], as in
+ * sc_solve_lcp_adjoint. The batch keeps the pointers, not the structs'
+ * owners: every buffer must outlive the batch. */
 typedef struct sc_batch_item {
     sc_particles p;
     sc_contacts c;
     double *gamma;
     double *g;
+    sc_box box;
+    const double *u_nc;
+    double dt;
+    const double *dL_dgamma;
+    double *dL_dq;
+    double *dL_dpos;
 } sc_batch_item;
 
 typedef struct sc_batch_opts {
@@ -276,6 +285,11 @@ typedef struct sc_batch_opts {
                                16 or 32; 0 = autotune (solves the batch once per size
                                and keeps the fastest; overwrites gamma and g) */
     int32_t block;          /* threads per workgroup: 0 (1024), 256, 512 or 1024 */
+    int32_t adjoint;        /* 0: solve only; 1: then the adjoint of
+                               L = 1/2 ||D gamma||^2 + dL_dgamma . gamma; 2: of the
+                               linear loss dL_dgamma . gamma only */
+    double adjoint_tol;     /* CG tolerance relative to ||b_A|| */
+    int32_t adjoint_max_iter;
     int32_t reserved;
 } sc_batch_opts;
 
@@ -287,8 +301,9 @@ typedef struct sc_batch_info {
 
 typedef struct sc_batch sc_batch;   /* opaque plan (host memory) */
 
-/* Workspace bytes of a batch (device memory, 256-byte aligned). */
-size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *items);
+/* Workspace bytes of a batch (device memory, 256-byte aligned); adjoint as
+ * in sc_batch_opts. */
+size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *items, int32_t adjoint);
 
 /* Plans a batch of `count` LCPs (Algorithm 1 per instance, section 4): checks
  * every item, writes the instance table and the work order (by nonzeros,
@@ -307,9 +322,11 @@ int sc_batch_solve(sc_batch *b, void *stream);
 int sc_batch_graph_launch(sc_batch *b, void *stream);
 
 /* Per-instance results of the last solve (st: host array of count; grid
- * holds the team size) and the launch used (info may be NULL).
- * Synchronises `stream`. */
-int sc_batch_stats(const sc_batch *b, sc_stats *st, sc_batch_info *info, void *stream);
+ * holds the team size), of its adjoint (adj: host array of count or NULL;
+ * iters = CG iterations, residual = relative CG residual) and the launch
+ * used (info may be NULL). Synchronises `stream`. */
+int sc_batch_stats(const sc_batch *b, sc_stats *st, sc_stats *adj, sc_batch_info *info,
+                   void *stream);
 
 void sc_batch_destroy(sc_batch *b);
 

@@ -328,16 +328,21 @@ class Batch:
     """Many independent LCPs solved in one persistent launch (one team of
     workgroups per instance at a time, instances taken largest first).
 
-    ``items``: list of (Particles, Contacts) with assembled M. ``team``: 0
-    autotunes the number of workgroups per instance. ``gamma[k]``, ``g[k]``
-    hold each instance's solution after ``solve()`` / ``graph_solve()``."""
+    ``items``: list of (Particles, Contacts) with assembled M, or, with
+    ``adjoint``, (Particles, Contacts, Box, u_nc, dt). ``team``: 0 autotunes
+    the number of workgroups per instance. After ``solve()`` /
+    ``graph_solve()``, ``gamma[k]`` and ``g[k]`` hold each solution and, with
+    ``adjoint`` (1: loss 1/2 ||D gamma||^2 + dL_dgamma . gamma, 2: the linear
+    term only), ``dL_dq[k]`` and ``dL_dpos[k]`` its gradients."""
 
     def __init__(self, items, tol=1e-6, max_iter=100000, bb=1, team=0, block=0,
-                 gamma0=None):
+                 gamma0=None, adjoint=0, dL_dgamma=None, adjoint_tol=1e-10,
+                 adjoint_max_iter=100000):
         self._keep = []
-        self.gamma, self.g = [], []
+        self.gamma, self.g, self.dL_dq, self.dL_dpos = [], [], [], []
         arr = (A.sc_batch_item * max(1, len(items)))()
-        for k, (P, con) in enumerate(items):
+        for k, it in enumerate(items):
+            P, con = it[0], it[1]
             if not con.mat_ready:
                 con.assemble(P)
             nc = con.count
@@ -352,13 +357,31 @@ class Batch:
             arr[k].gamma = gm.data_ptr()
             arr[k].g = g.data_ptr()
             self._keep += [P, con, gm, g]
+            if adjoint:
+                box, u_nc, dt = it[2], _dev(it[3]), float(it[4])
+                dq = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
+                dpos = torch.empty((max(1, P.n), 3), dtype=torch.float64, device="cuda")
+                arr[k].box = box.c()
+                arr[k].u_nc = u_nc.data_ptr()
+                arr[k].dt = dt
+                arr[k].dL_dq = dq.data_ptr()
+                arr[k].dL_dpos = dpos.data_ptr()
+                if dL_dgamma is not None and dL_dgamma[k] is not None:
+                    dg = _dev(dL_dgamma[k])
+                    arr[k].dL_dgamma = dg.data_ptr()
+                    self._keep.append(dg)
+                self.dL_dq.append(dq[:nc])
+                self.dL_dpos.append(dpos[: P.n])
+                self._keep += [u_nc, dq, dpos]
         self.count = len(items)
-        need = int(A.lib().sc_batch_workspace_bytes(self.count, arr))
+        self.adjoint = int(adjoint)
+        need = int(A.lib().sc_batch_workspace_bytes(self.count, arr, self.adjoint))
         self._ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
         base = (self._ws.data_ptr() + 255) // 256 * 256
         size = need + 256 - (base - self._ws.data_ptr())
         opts = A.sc_batch_opts(float(tol), int(max_iter), int(bb),
-                               1 if gamma0 is not None else 0, int(team), int(block), 0)
+                               1 if gamma0 is not None else 0, int(team), int(block),
+                               self.adjoint, float(adjoint_tol), int(adjoint_max_iter), 0)
         h = ctypes.c_void_p()
         _check("sc_batch_create",
                A.lib().sc_batch_create(self.count, arr, ctypes.byref(opts), ctypes.c_void_p(base),
@@ -373,14 +396,18 @@ class Batch:
         _check("sc_batch_graph_launch", A.lib().sc_batch_graph_launch(self._h, _stream()))
 
     def stats(self):
+        """(per-instance solve stats, per-instance adjoint stats or None, launch info)."""
         st = (A.sc_stats * max(1, self.count))()
+        adj = (A.sc_stats * max(1, self.count))()
         info = A.sc_batch_info()
-        _check("sc_batch_stats", A.lib().sc_batch_stats(self._h, st, ctypes.byref(info),
+        _check("sc_batch_stats", A.lib().sc_batch_stats(self._h, st, adj, ctypes.byref(info),
                                                         _stream()))
         inf = {"team": info.team, "block": info.block, "grid": info.grid,
                "lds_entries_per_wave": info.lds_entries_per_wave,
                "tune_ms": list(info.tune_ms)}
-        return [st[k].as_dict() for k in range(self.count)], inf
+        sts = [st[k].as_dict() for k in range(self.count)]
+        adjs = [adj[k].as_dict() for k in range(self.count)] if self.adjoint else None
+        return sts, adjs, inf
 
     def close(self):
         if self._h:

@@ -21,6 +21,7 @@
 #include "sc_matrix.hpp"
 #include "sc_plan.hpp"
 #include "sc_sync.hpp"
+#include "sc_adjoint_dev.hpp"
 
 namespace sc {
 
@@ -145,15 +146,7 @@ __global__ void k_cg_rhs(int nc, const int *ci, const int *cj, const double *fra
     int cnt = 0;
     for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < nc; l += gridDim.x * blockDim.x) {
         const bool act = gamma[l] > 0.0;
-        double b = dLdg ? dLdg[l] : 0.0;
-        if (dLdF) {
-            const double *f = frame + 9 * static_cast<long long>(l);
-            const double *ui = dLdF + 6 * static_cast<long long>(ci[l]);
-            const double *uj = dLdF + 6 * static_cast<long long>(cj[l]);
-            b += -dot(load3(f), load3(ui)) - dot(load3(f + 3), load3(ui + 3)) +
-                 dot(load3(f), load3(uj)) + dot(load3(f + 6), load3(uj + 3));
-        }
-        r[static_cast<long long>(l) * stride] = act ? b : 0.0;
+        r[static_cast<long long>(l) * stride] = cg_rhs_one(l, ci, cj, frame, gamma, dLdg, dLdF);
         cnt += act;
     }
     for (int off = kWave / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
@@ -167,12 +160,6 @@ __global__ void k_cg_rhs(int nc, const int *ci, const int *cj, const double *fra
     }
 }
 
-// Per-contact derivative of J_l(r) = D_l(r)^T [E_i; E_j] - (w_l/dt) Phi_l(r)
-// with respect to r = c_j - c_i (orientations fixed), where
-// E_k = gamma_l (dL/dF_k - V_w,k) - w_l (U_nc,k + U_c,k). The closest-point
-// parameters s, t move with r only while strictly inside their segment:
-// both free -> implicit differentiation of the 2x2 stationarity conditions;
-// one free -> its 1-D projection; both clamped (or a sphere) -> fixed.
 __global__ void k_contact_grad(int nc, const int *__restrict__ ci, const int *__restrict__ cj,
                                const int *__restrict__ cs, const double *__restrict__ pos,
                                const double *__restrict__ axis,
@@ -183,50 +170,9 @@ __global__ void k_contact_grad(int nc, const int *__restrict__ ci, const int *__
                                double inv_dt, double *__restrict__ grad) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nc) return;
-    const double gl = gamma[l], wl = w[l];
+    const V3 g = contact_grad_one(l, ci, cj, cs, pos, axis, half_len, box, gamma, w, dLdF, Vw,
+                                  Unc, Uc, inv_dt);
     double *gout = grad + 3 * static_cast<long long>(l);
-    if (gl == 0.0 && wl == 0.0) {
-        gout[0] = gout[1] = gout[2] = 0.0;
-        return;
-    }
-    const int i = ci[l], j = cj[l];
-    const long long ri = cs[2 * l], rj = cs[2 * l + 1];
-    const V3 pi = load3(axis + 3 * i), pj = load3(axis + 3 * j);
-    const double hi = half_len[i], hj = half_len[j];
-    const V3 r = min_image(load3(pos + 3 * i), load3(pos + 3 * j), box);
-    double s, t;
-    closest_st(r, pi, hi, pj, hj, s, t);
-    const bool s_free = hi > 0.0 && s > -hi && s < hi;
-    const bool t_free = hj > 0.0 && t > -hj && t < hj;
-    V3 ds = v3(0.0, 0.0, 0.0), dt = v3(0.0, 0.0, 0.0);
-    if (s_free && t_free) {
-        const double b = dot(pi, pj), den = 1.0 - b * b;
-        ds = (1.0 / den) * (pi - b * pj);
-        dt = (1.0 / den) * (b * pi - pj);
-    } else if (t_free) {
-        dt = -1.0 * pj;
-    } else if (s_free) {
-        ds = pi;
-    }
-    const V3 d = r + t * pj - s * pi;
-    const double rho = sqrt(dot(d, d));
-    const V3 n = (1.0 / rho) * d;
-    const long long oi = 6 * static_cast<long long>(i), oj = 6 * static_cast<long long>(j);
-    const V3 zero = v3(0.0, 0.0, 0.0);
-    const V3 fi = dLdF ? load3(dLdF + oi) : zero, tqi = dLdF ? load3(dLdF + oi + 3) : zero;
-    const V3 fj = dLdF ? load3(dLdF + oj) : zero, tqj = dLdF ? load3(dLdF + oj + 3) : zero;
-    const double *Vi = Vw + 8 * ri, *Vj = Vw + 8 * rj, *Ci = Uc + 8 * ri, *Cj = Uc + 8 * rj;
-    const V3 EiF = gl * (fi - load3(Vi)) - wl * (load3(Unc + oi) + load3(Ci));
-    const V3 EiT = gl * (tqi - load3(Vi + 3)) - wl * (load3(Unc + oi + 3) + load3(Ci + 3));
-    const V3 EjF = gl * (fj - load3(Vj)) - wl * (load3(Unc + oj) + load3(Cj));
-    const V3 EjT = gl * (tqj - load3(Vj + 3)) - wl * (load3(Unc + oj + 3) + load3(Cj + 3));
-    // J_d = dd/dr = I + p_j dt^T - p_i ds^T, so J_d^T u = u + dt (p_j.u) - ds (p_i.u);
-    // dn/dr = (I - n n^T) J_d / rho.
-    auto JdT = [&](V3 u) { return u + dot(pj, u) * dt - dot(pi, u) * ds; };
-    auto JnT = [&](V3 v) { return (1.0 / rho) * JdT(v - dot(n, v) * n); };
-    const V3 vn = (EjF - EiF) - s * cross(EiT, pi) + t * cross(EjT, pj);
-    const V3 g = JnT(vn) - dot(cross(pi, n), EiT) * ds + dot(cross(pj, n), EjT) * dt -
-                 (wl * inv_dt) * JdT(n);
     gout[0] = g.x;
     gout[1] = g.y;
     gout[2] = g.z;
@@ -238,18 +184,7 @@ __global__ void k_gather_pos(int n, Plan pl, const double *__restrict__ grad,
                              double *__restrict__ out) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int e = pl.inc_ptr[k]; e < pl.inc_ptr[k + 1]; ++e) {
-        const long long l = pl.inc[e] >> 1;
-        const double sg = pl.cs[2 * l] == k ? -1.0 : 1.0;
-        gx += sg * grad[3 * l + 0];
-        gy += sg * grad[3 * l + 1];
-        gz += sg * grad[3 * l + 2];
-    }
-    const long long o = 3 * static_cast<long long>(pl.order[k]);
-    out[o + 0] = gx;
-    out[o + 1] = gy;
-    out[o + 2] = gz;
+    gather_pos_one(k, pl, grad, out);
 }
 
 __global__ void k_neg_masked(int nc, const double *gamma, const double *x, double *out) {

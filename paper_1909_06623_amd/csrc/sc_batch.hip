@@ -9,17 +9,24 @@
 // instance's M partly resident in LDS, exactly as the single-instance
 // solver does over the whole grid. An instance's arithmetic depends only on
 // the team size, not on which team takes it, so results are reproducible.
-// A reset kernel (no memset) precedes the persistent kernel, so the pair
-// can be captured in a HIP graph and replayed.
+// With the adjoint enabled, the team then differentiates the instance's
+// converged solution (the implicit adjoint on its active set, not in the
+// paper): F_c = D gamma and U_c, the masked right-hand side, the CG on M_AA
+// (same layout as the solve), dL/dq, V_w = Mob D w, the per-contact
+// geometric derivatives and their per-particle sums, with team barriers
+// between the steps. A reset kernel (no memset) precedes the persistent
+// kernel, so the pair can be captured in a HIP graph and replayed.
 #include <algorithm>
 #include <climits>
 #include <numeric>
 #include <vector>
 
+#include "sc_adjoint_dev.hpp"
 #include "sc_chain.hpp"
 #include "sc_common.hpp"
 #include "sc_matrix.hpp"
 #include "sc_matrix_pass.hpp"
+#include "sc_plan.hpp"
 #include "sc_sync.hpp"
 
 namespace sc {
@@ -34,6 +41,19 @@ struct BatchDesc {
     const double *q;
     double *gamma, *g;
     GG *z0, *z1;
+    // adjoint
+    ChainView C;            // C.U holds U_c = Mob D gamma (rank order)
+    Plan pl;
+    PBox box;
+    const int *ci, *cj;
+    const double *pos, *axis, *half_len, *u_nc, *dLdg;
+    double inv_dt;
+    double *dq, *dpos;
+    double *F;              // [n][6] D gamma, caller order
+    double *Vw;             // [n][8] Mob D w, rank order
+    double *grad;           // [nc][3]
+    double *p, *x;          // [nc]
+    RWS *r0, *r1;           // [nc] each
 };
 
 struct alignas(256) BatchCtl {
@@ -53,11 +73,15 @@ struct BatchArgs {
     int count, team, warm, cache;
     double tol;
     int max_iter, bb;
+    int adjoint, adj_max_iter;  // adjoint: 0 none, 1 dL/dF = D gamma (+ dL/dgamma), 2 dL/dgamma
+    double adj_tol;
+    CgCtrl *cgctrl;             // [count]
 };
 
 // Clears the queue, barrier counters and per-instance results (an instance
 // no team reached keeps SC_ERR_TIMEOUT).
-__global__ void k_batch_reset(BatchCtl *ctl, TeamSync *ts, int nteams, SolveCtrl *ctrl, int count) {
+__global__ void k_batch_reset(BatchCtl *ctl, TeamSync *ts, int nteams, SolveCtrl *ctrl,
+                              CgCtrl *cg, int count) {
     unsigned *c = reinterpret_cast<unsigned *>(ctl);
     for (int k = threadIdx.x; k < static_cast<int>(sizeof(BatchCtl) / 4); k += blockDim.x) c[k] = 0u;
     unsigned *t = reinterpret_cast<unsigned *>(ts);
@@ -66,7 +90,53 @@ __global__ void k_batch_reset(BatchCtl *ctl, TeamSync *ts, int nteams, SolveCtrl
     for (int k = threadIdx.x; k < count; k += blockDim.x) {
         ctrl[k] = SolveCtrl{};
         ctrl[k].status = SC_ERR_TIMEOUT;
+        if (cg) {
+            cg[k] = CgCtrl{};
+            cg[k].status = SC_ERR_TIMEOUT;
+        }
     }
+}
+
+// The adjoint steps of one instance on a team (member `member` of t): the
+// member's share of particles [k0, k1), its rows of the solve's chunk.
+template <int R, int BS>
+__device__ void adjoint_rows(const BatchArgs &A, const BatchDesc &D, const SliceChunk &ch,
+                             const WaveCache &W, double *part, int member, int t, TeamBarrier &tb,
+                             int item) {
+    const int n = D.C.n;
+    const int k0 = static_cast<int>(static_cast<long long>(member) * n / t);
+    const int k1 = static_cast<int>(static_cast<long long>(member + 1) * n / t);
+    const bool fc = A.adjoint == 1;
+    bool ok = tb.sync();  // every gamma of the instance is final
+    for (int k = k0 + threadIdx.x; k < k1; k += BS)
+        mob_d_one(D.C, k, D.gamma, D.pl.order, fc ? D.F : nullptr, D.C.U);
+    ok = tb.sync() && ok;
+    for (int l = ch.l0 + threadIdx.x; l < ch.l1; l += BS) {
+        D.r0[l] = RWS{cg_rhs_one(l, D.ci, D.cj, D.C.frame, D.gamma, D.dLdg, fc ? D.F : nullptr),
+                      0.0, 0.0, 0.0};
+        D.p[l] = 0.0;
+        D.x[l] = 0.0;
+    }
+    ok = tb.sync() && ok;
+    const WaveMeta<R> Mt = wave_meta<R, BS>(D.M, ch);
+    cg_rows<R, BS>(D.M, ch, W, Mt, D.gamma, D.r0, D.r1, D.p, D.x, part, kTeamPartHalf, member, t,
+                   tb, A.adj_tol, ok ? A.adj_max_iter : 0, A.cgctrl + item);
+    for (int l = ch.l0 + threadIdx.x; l < ch.l1; l += BS)
+        D.dq[l] = D.gamma[l] > 0.0 ? -D.x[l] : 0.0;
+    for (int k = k0 + threadIdx.x; k < k1; k += BS)
+        mob_d_one(D.C, k, D.x, D.pl.order, nullptr, D.Vw);
+    tb.sync();
+    for (int l = ch.l0 + threadIdx.x; l < ch.l1; l += BS) {
+        const V3 gv = contact_grad_one(l, D.ci, D.cj, D.pl.cs, D.pos, D.axis, D.half_len, D.box,
+                                       D.gamma, D.x, fc ? D.F : nullptr, D.Vw, D.u_nc, D.C.U,
+                                       D.inv_dt);
+        double *go = D.grad + 3 * static_cast<long long>(l);
+        go[0] = gv.x;
+        go[1] = gv.y;
+        go[2] = gv.z;
+    }
+    tb.sync();
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) gather_pos_one(k, D.pl, D.grad, D.dpos);
 }
 
 template <int R, int BS>
@@ -119,6 +189,7 @@ __global__ void __launch_bounds__(BS) k_bbpgd_batch(BatchArgs A) {
         bbpgd_rows<R, BS>(D.M, ch, W, D.q, A.warm ? D.gamma : nullptr, D.gamma, D.g, D.z0, D.z1,
                           part, kTeamPartHalf, member, t, tb, A.tol, A.max_iter, A.bb,
                           A.ctrl + item);
+        if (A.adjoint) adjoint_rows<R, BS>(A, D, ch, W, part, member, t, tb, item);
     }
 }
 
@@ -150,7 +221,14 @@ hipError_t batch_cache(const void *fn, int block, int *per_block, size_t *dyn) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(*dyn));
 }
 
-size_t z_doubles(const sc_contacts &c) { return 4 * static_cast<size_t>(c.count > 0 ? c.count : 1); }
+size_t rows(const sc_contacts &c) { return static_cast<size_t>(c.count > 0 ? c.count : 1); }
+size_t z_doubles(const sc_contacts &c) { return 4 * rows(c); }
+// adjoint scratch per instance: F [n][6], U_c and V_w [n][8] each,
+// grad [nc][3], p, x [nc], two record arrays [nc][4]
+size_t adj_doubles(const sc_batch_item &it) {
+    const size_t n = static_cast<size_t>(it.p.n > 0 ? it.p.n : 1);
+    return 22 * n + 13 * rows(it.c) + 8 * 256;
+}
 
 }  // namespace
 
@@ -173,9 +251,12 @@ struct sc_batch {
 
 namespace {
 
-size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nteams) {
+size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nteams, bool adj) {
     const size_t nd = static_cast<size_t>(std::max(count, 1));
     size_t b = 0;
+    b += align_up(sizeof(CgCtrl) * nd, 256);
+    if (adj)
+        for (int32_t k = 0; k < count; ++k) b += 8 * 256 + sizeof(double) * adj_doubles(items[k]);
     b += align_up(sizeof(BatchCtl), 256);
     b += align_up(sizeof(TeamSync) * static_cast<size_t>(nteams), 256);
     b += align_up(sizeof(double) * 2 * kTeamPartHalf * static_cast<size_t>(nteams), 256);
@@ -188,7 +269,8 @@ size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nteams) {
 
 int enqueue(sc_batch *b, hipStream_t s) {
     const int nteams = b->nteams_max;
-    k_batch_reset<<<1, 256, 0, s>>>(b->args.ctl, b->args.tsync, nteams, b->args.ctrl, b->count);
+    k_batch_reset<<<1, 256, 0, s>>>(b->args.ctl, b->args.tsync, nteams, b->args.ctrl,
+                                     b->args.adjoint ? b->args.cgctrl : nullptr, b->count);
     BatchArgs a = b->args;
     a.team = b->team;
     void *args[] = {&a};
@@ -198,13 +280,14 @@ int enqueue(sc_batch *b, hipStream_t s) {
 
 }  // namespace
 
-extern "C" size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *items) {
+extern "C" size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *items,
+                                           int32_t adjoint) {
     if (count < 0 || (count > 0 && !items)) return 0;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 1024;
-    return batch_ws_bytes(count, items, std::max(cus, 1));
+    return batch_ws_bytes(count, items, std::max(cus, 1), adjoint != 0);
 }
 
 extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const sc_batch_opts *opts,
@@ -214,8 +297,10 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->bb < 1 || opts->bb > 3 ||
         !(opts->team == 0 || opts->team == 1 || opts->team == 2 || opts->team == 4 ||
           opts->team == 8 || opts->team == 16 || opts->team == 32) ||
-        !block_ok(opts->block))
+        !block_ok(opts->block) || opts->adjoint < 0 || opts->adjoint > 2 ||
+        (opts->adjoint && (!(opts->adjoint_tol > 0.0) || opts->adjoint_max_iter < 0)))
         return SC_ERR_INVALID;
+    const bool adj = opts->adjoint != 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<BatchDesc> descs(static_cast<size_t>(count));
     std::vector<long long> nnz(static_cast<size_t>(count));
@@ -227,6 +312,31 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
         MatBufs mb{};
         if (!carve_matrix(c.mat, c.mat_bytes, c.count, c.nnz, mb)) return SC_ERR_INVALID;
         descs[k].M = mat_view(c.count, mb);
+        if (adj) {
+            const sc_batch_item &it = items[k];
+            Plan pl;
+            if (it.p.n < 0 || !carve_plan(c.plan, c.plan_bytes, it.p.n, c.capacity, pl) ||
+                !(it.dt > 0.0) ||
+                (it.p.n > 0 && (!it.u_nc || !it.dL_dpos || !it.p.pos || !it.p.axis ||
+                                !it.p.half_len)) ||
+                (c.count > 0 && (!it.dL_dq || !c.ci || !c.cj || !c.frame)))
+                return SC_ERR_INVALID;
+            BatchDesc &d = descs[k];
+            d.pl = pl;
+            d.C = ChainView{it.p.n, c.count, pl.pdat, pl.inc_ptr, pl.inc, pl.dpm, pl.cs, c.frame,
+                            nullptr};
+            d.box = PBox{{it.box.len[0], it.box.len[1], it.box.len[2]}, it.box.periodic ? 1 : 0};
+            d.ci = c.ci;
+            d.cj = c.cj;
+            d.pos = it.p.pos;
+            d.axis = it.p.axis;
+            d.half_len = it.p.half_len;
+            d.u_nc = it.u_nc;
+            d.dLdg = it.dL_dgamma;
+            d.inv_dt = 1.0 / it.dt;
+            d.dq = it.dL_dq;
+            d.dpos = it.dL_dpos;
+        }
         descs[k].q = c.q;
         descs[k].gamma = items[k].gamma;
         descs[k].g = items[k].g;
@@ -248,7 +358,7 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
         return SC_ERR_HIP;
     }
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 ||
-        ws_bytes < batch_ws_bytes(count, items, b->nteams_max)) {
+        ws_bytes < batch_ws_bytes(count, items, b->nteams_max, adj)) {
         delete b;
         return SC_ERR_WORKSPACE;
     }
@@ -260,11 +370,25 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     BatchDesc *d_descs = cv.take<BatchDesc>(static_cast<size_t>(std::max(count, 1)));
     int *d_order = cv.take<int>(static_cast<size_t>(std::max(count, 1)));
     a.ctrl = cv.take<SolveCtrl>(static_cast<size_t>(std::max(count, 1)));
+    a.cgctrl = cv.take<CgCtrl>(static_cast<size_t>(std::max(count, 1)));
     for (int32_t k = 0; k < count; ++k) {
         GG *z = reinterpret_cast<GG *>(cv.take<double>(z_doubles(items[k].c)));
         descs[k].z0 = z;
         descs[k].z1 = z + std::max(items[k].c.count, 1);
         b->counts.push_back(items[k].c.count);
+        if (adj) {
+            const size_t n = static_cast<size_t>(std::max(items[k].p.n, 1));
+            const size_t nc = rows(items[k].c);
+            BatchDesc &d = descs[k];
+            d.F = cv.take<double>(6 * n);
+            d.C.U = cv.take<double>(8 * n);
+            d.Vw = cv.take<double>(8 * n);
+            d.grad = cv.take<double>(3 * nc);
+            d.p = cv.take<double>(nc);
+            d.x = cv.take<double>(nc);
+            d.r0 = reinterpret_cast<RWS *>(cv.take<double>(4 * nc));
+            d.r1 = reinterpret_cast<RWS *>(cv.take<double>(4 * nc));
+        }
     }
     if (!cv.ok) {
         delete b;
@@ -281,6 +405,9 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     a.tol = opts->tol;
     a.max_iter = opts->max_iter;
     a.bb = opts->bb;
+    a.adjoint = opts->adjoint;
+    a.adj_tol = opts->adjoint_tol;
+    a.adj_max_iter = opts->adjoint_max_iter;
     if (count > 0) {
         if (hipMemcpyAsync(d_descs, descs.data(), sizeof(BatchDesc) * count, hipMemcpyHostToDevice,
                            s) != hipSuccess ||
@@ -407,8 +534,8 @@ extern "C" int sc_batch_graph_launch(sc_batch *b, void *stream) {
     return SC_OK;
 }
 
-extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_batch_info *info,
-                              void *stream) {
+extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_stats *adj,
+                              sc_batch_info *info, void *stream) {
     if (!b || (b->count > 0 && !stats)) return SC_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (info) {
@@ -422,7 +549,25 @@ extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_batch_info 
     std::vector<SolveCtrl> h(static_cast<size_t>(b->count));
     SC_HIP_TRY(hipMemcpyAsync(h.data(), b->args.ctrl, sizeof(SolveCtrl) * b->count,
                               hipMemcpyDeviceToHost, s));
+    std::vector<CgCtrl> hc(static_cast<size_t>(b->count));
+    if (adj && b->args.adjoint)
+        SC_HIP_TRY(hipMemcpyAsync(hc.data(), b->args.cgctrl, sizeof(CgCtrl) * b->count,
+                                  hipMemcpyDeviceToHost, s));
     SC_HIP_TRY(hipStreamSynchronize(s));
+    if (adj) {
+        for (int k = 0; k < b->count; ++k) {
+            adj[k] = sc_stats{};
+            adj[k].status = b->args.adjoint ? hc[k].status : SC_OK;
+            adj[k].iters = hc[k].iters;
+            adj[k].mvops = hc[k].iters + 1;
+            adj[k].residual = hc[k].res;
+            adj[k].alpha = hc[k].alpha;
+            adj[k].grid = b->team;
+            adj[k].block = b->block;
+            adj[k].op = SC_OP_MATRIX;
+            adj[k].n_active = -1;
+        }
+    }
     for (int k = 0; k < b->count; ++k) {
         sc_stats &st = stats[k];
         st = sc_stats{};

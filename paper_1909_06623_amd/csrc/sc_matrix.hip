@@ -177,12 +177,6 @@ __global__ void __launch_bounds__(BS) k_bbpgd_mat(MatSolve A) {
                       L, gridDim.x, bar, A.tol, A.max_iter, A.bb, A.ctrl);
 }
 
-// CG state per contact: (r_{i-1}, w_{i-1} = A r_{i-1}, s_{i-2}) interleaved,
-// so that forming r_i for a column costs one 32-byte gather.
-struct RWS {
-    double r, w, s, pad;
-};
-
 struct MatCg {
     MatView M;
     const double *gamma;
@@ -196,106 +190,17 @@ struct MatCg {
     int cache;              // LDS entries of the workgroup
 };
 
-// Chronopoulos-Gear CG on M_AA (z[0].r holds the masked right-hand side,
-// the other fields and p, x are zero on entry). Iteration i forms
-// r_i = r_{i-1} - alpha (w_{i-1} + beta s_{i-2}) per column on the fly,
-// w_i = A r_i per active row (inactive rows are all zero), the row's own
-// updates of p, s and x, and the dot products (r_i, r_i), (w_i, r_i).
 template <int R, int BS>
 __global__ void __launch_bounds__(BS) k_cg_mat(MatCg A) {
     GridBarrier bar;
     bar.init(A.sync);
-    const SliceChunk rc = slice_chunk(A.M, logical_block(), gridDim.x);
+    const int L = logical_block();
+    const SliceChunk rc = slice_chunk(A.M, L, gridDim.x);
     const WaveCache W = wave_cache<R, BS>(A.M, rc, A.cache);
     fill_cache<R, BS>(A.M, rc, W);
     const WaveMeta<R> Mt = wave_meta<R, BS>(A.M, rc);
-    double tot[2];
-    bool ok;
-    {
-        double acc[2] = {0.0, 0.0};
-        const RWS *z0 = A.z[0];
-        RWS *z1 = A.z[1];
-        spmv_pass<R, BS>(A.M, rc, W, Mt, [&](int l) { return GG{z0[l].r, A.gamma[l]}; },
-                              [&](int m) { return z0[m].r; }, [&](int l, double v, GG o) {
-            const double rl = o.gam;
-            const double wl = o.g > 0.0 ? v : 0.0;
-            z1[l] = RWS{rl, wl, 0.0, 0.0};
-            acc[0] += rl * rl;
-            acc[1] += wl * rl;
-        });
-        write_partial<2, BS>(part_buf(A.part, 0), acc);
-    }
-    ok = bar.sync();
-    grid_reduce<2, BS>(part_buf(A.part, 0), tot);
-    const double bnorm2 = tot[0];
-    double gam_prev = tot[0], alpha = 0.0, beta = 0.0, res = bnorm2 > 0.0 ? 1.0 : 0.0;
-    int iters = 0, status = SC_NOT_CONVERGED;
-    if (!ok) {
-        status = SC_ERR_TIMEOUT;
-    } else if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-        status = SC_ERR_NONFINITE;
-    } else if (bnorm2 == 0.0) {
-        status = SC_OK;
-    } else if (tot[1] > 0.0) {
-        alpha = tot[0] / tot[1];
-        for (int i = 1; i <= A.max_iter; ++i) {
-            const RWS *zc = A.z[i & 1];
-            RWS *zn = A.z[(i & 1) ^ 1];
-            double acc[2] = {0.0, 0.0};
-            struct Own {
-                RWS z;
-                double p, x, act;
-            };
-            spmv_pass<R, BS>(
-                A.M, rc, W, Mt, [&](int l) { return Own{zc[l], A.p[l], A.x[l], A.gamma[l]}; },
-                [&](int m) {
-                    const RWS zm = zc[m];
-                    return zm.r - alpha * (zm.w + beta * zm.s);
-                },
-                [&](int l, double v, const Own &o) {
-                    const RWS zl = o.z;
-                    const double sl = zl.w + beta * zl.s;
-                    const double pl = zl.r + beta * o.p;
-                    A.x[l] = o.x + alpha * pl;
-                    A.p[l] = pl;
-                    const double rl = zl.r - alpha * sl;
-                    const double wl = o.act > 0.0 ? v : 0.0;
-                    __builtin_nontemporal_store(rl, &zn[l].r);
-                    __builtin_nontemporal_store(wl, &zn[l].w);
-                    __builtin_nontemporal_store(sl, &zn[l].s);
-                    acc[0] += rl * rl;
-                    acc[1] += wl * rl;
-                });
-            write_partial<2, BS>(part_buf(A.part, i), acc);
-            ok = bar.sync();
-            grid_reduce<2, BS>(part_buf(A.part, i), tot);
-            iters = i;
-            res = sqrt(tot[0] / bnorm2);
-            if (!ok) {
-                status = SC_ERR_TIMEOUT;
-                break;
-            }
-            if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-                status = SC_ERR_NONFINITE;
-                break;
-            }
-            if (tot[0] <= A.tol * A.tol * bnorm2) {
-                status = SC_OK;
-                break;
-            }
-            beta = tot[0] / gam_prev;
-            const double den = tot[1] - beta * tot[0] / alpha;
-            if (!(den > 0.0)) break;  // lost positive definiteness numerically
-            alpha = tot[0] / den;
-            gam_prev = tot[0];
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        A.ctrl->alpha = alpha;
-        A.ctrl->res = res;
-        A.ctrl->iters = iters;
-        A.ctrl->status = status;
-    }
+    cg_rows<R, BS>(A.M, rc, W, Mt, A.gamma, A.z[0], A.z[1], A.p, A.x, A.part, kPartHalf, L,
+                   gridDim.x, bar, A.tol, A.max_iter, A.ctrl);
 }
 
 using BbMatKernel = void (*)(MatSolve);

@@ -431,4 +431,112 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
     }
 }
 
+// CG state per contact: (r_{i-1}, w_{i-1} = A r_{i-1}, s_{i-2}) interleaved,
+// so that forming r_i for a column costs one 32-byte gather.
+struct RWS {
+    double r, w, s, pad;
+};
+
+// Chronopoulos-Gear CG on M_AA (z0.r holds the masked right-hand side,
+// the other fields and p, x are zero on entry). Iteration i forms
+// r_i = r_{i-1} - alpha (w_{i-1} + beta s_{i-2}) per column on the fly,
+// w_i = A r_i per active row (inactive rows are all zero), the row's own
+// updates of p, s and x, and the dot products (r_i, r_i), (w_i, r_i).
+// Runs on the rows of one part (of `nparts`) with a barrier over all parts,
+// as bbpgd_rows; part 0 writes `ctrl`.
+template <int R, int BS, class Bar>
+__device__ void cg_rows(const MatView &M, const SliceChunk &rc, const WaveCache &W,
+                        const WaveMeta<R> &Mt, const double *gamma, RWS *z0buf, RWS *z1buf,
+                        double *p, double *x, double *part, int half, int slot, int nparts,
+                        Bar &bar, double tol, int max_iter, CgCtrl *ctrl) {
+    RWS *const z[2] = {z0buf, z1buf};
+    double tot[2];
+    bool ok;
+    {
+        double acc[2] = {0.0, 0.0};
+        const RWS *z0 = z[0];
+        RWS *z1 = z[1];
+        spmv_pass<R, BS>(M, rc, W, Mt, [&](int l) { return GG{z0[l].r, gamma[l]}; },
+                              [&](int m) { return z0[m].r; }, [&](int l, double v, GG o) {
+            const double rl = o.gam;
+            const double wl = o.g > 0.0 ? v : 0.0;
+            z1[l] = RWS{rl, wl, 0.0, 0.0};
+            acc[0] += rl * rl;
+            acc[1] += wl * rl;
+        });
+        write_partial<2, BS>(part_buf(part, 0, half), acc, slot);
+    }
+    ok = bar.sync();
+    grid_reduce<2, BS>(part_buf(part, 0, half), tot, nparts);
+    const double bnorm2 = tot[0];
+    double gam_prev = tot[0], alpha = 0.0, beta = 0.0, res = bnorm2 > 0.0 ? 1.0 : 0.0;
+    int iters = 0, status = SC_NOT_CONVERGED;
+    if (!ok) {
+        status = SC_ERR_TIMEOUT;
+    } else if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+        status = SC_ERR_NONFINITE;
+    } else if (bnorm2 == 0.0) {
+        status = SC_OK;
+    } else if (tot[1] > 0.0) {
+        alpha = tot[0] / tot[1];
+        for (int i = 1; i <= max_iter; ++i) {
+            const RWS *zc = z[i & 1];
+            RWS *zn = z[(i & 1) ^ 1];
+            double acc[2] = {0.0, 0.0};
+            struct Own {
+                RWS z;
+                double p, x, act;
+            };
+            spmv_pass<R, BS>(
+                M, rc, W, Mt, [&](int l) { return Own{zc[l], p[l], x[l], gamma[l]}; },
+                [&](int m) {
+                    const RWS zm = zc[m];
+                    return zm.r - alpha * (zm.w + beta * zm.s);
+                },
+                [&](int l, double v, const Own &o) {
+                    const RWS zl = o.z;
+                    const double sl = zl.w + beta * zl.s;
+                    const double pl = zl.r + beta * o.p;
+                    x[l] = o.x + alpha * pl;
+                    p[l] = pl;
+                    const double rl = zl.r - alpha * sl;
+                    const double wl = o.act > 0.0 ? v : 0.0;
+                    __builtin_nontemporal_store(rl, &zn[l].r);
+                    __builtin_nontemporal_store(wl, &zn[l].w);
+                    __builtin_nontemporal_store(sl, &zn[l].s);
+                    acc[0] += rl * rl;
+                    acc[1] += wl * rl;
+                });
+            write_partial<2, BS>(part_buf(part, i, half), acc, slot);
+            ok = bar.sync();
+            grid_reduce<2, BS>(part_buf(part, i, half), tot, nparts);
+            iters = i;
+            res = sqrt(tot[0] / bnorm2);
+            if (!ok) {
+                status = SC_ERR_TIMEOUT;
+                break;
+            }
+            if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+                status = SC_ERR_NONFINITE;
+                break;
+            }
+            if (tot[0] <= tol * tol * bnorm2) {
+                status = SC_OK;
+                break;
+            }
+            beta = tot[0] / gam_prev;
+            const double den = tot[1] - beta * tot[0] / alpha;
+            if (!(den > 0.0)) break;  // lost positive definiteness numerically
+            alpha = tot[0] / den;
+            gam_prev = tot[0];
+        }
+    }
+    if (slot == 0 && threadIdx.x == 0) {
+        ctrl->alpha = alpha;
+        ctrl->res = res;
+        ctrl->iters = iters;
+        ctrl->status = status;
+    }
+}
+
 }  // namespace sc

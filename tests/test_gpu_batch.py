@@ -16,7 +16,7 @@ def _say(msg):
     print(f"[case] {msg}", flush=True)
 
 
-def _instances(count, n_max, seed):
+def _instances(count, n_max, seed, full=False):
     import paper_1909_06623_amd as sc
     sus, _ = W.batched_instances(count=count, seed=seed, n_min=30, n_max=n_max)
     items = []
@@ -25,7 +25,7 @@ def _instances(count, n_max, seed):
         box = sc.Box(tuple(s.box))
         u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
         con = sc.build_contacts(P, box, s.delta, u_nc, s.dt)
-        items.append((P, con))
+        items.append((P, con, box, u_nc, s.dt) if full else (P, con))
     return sus, items
 
 
@@ -56,7 +56,7 @@ def test_batch_matches_oracle_and_is_reproducible(team):
          f"n_c {sum(c.count for _, c in items)}")
     b = sc.Batch(items, tol=1e-9, team=team)
     b.solve()
-    st, info = b.stats()
+    st, _, info = b.stats()
     assert info["team"] == team
     assert all(x["status"] == 0 for x in st), [x["status"] for x in st]
     g1 = [x.clone() for x in b.gamma]
@@ -66,7 +66,7 @@ def test_batch_matches_oracle_and_is_reproducible(team):
     assert all(torch.equal(a, x) for a, x in zip(g1, b.gamma))
     for _ in range(3):  # graph replays, with eager work in between
         b.graph_solve()
-        st2, _ = b.stats()
+        st2, _, _ = b.stats()
         assert [x["iters"] for x in st2] == [x["iters"] for x in st]
         assert all(torch.equal(a, x) for a, x in zip(g1, b.gamma))
         b.solve()
@@ -80,7 +80,7 @@ def test_batch_autotune_and_tiny_instances():
     _say(f"batch autotune: {len(items)} instances")
     b = sc.Batch(items, tol=1e-8, team=0)
     b.solve()
-    st, info = b.stats()
+    st, _, info = b.stats()
     assert info["team"] in (1, 2, 4, 8, 16, 32)
     assert all(t > 0 for t in info["tune_ms"])
     assert all(x["status"] == 0 for x in st)
@@ -94,7 +94,7 @@ def test_batch_empty_and_contactless():
     _say("batch: no instances; an instance without contacts")
     b = sc.Batch([], tol=1e-6, team=1)
     b.solve()
-    st, info = b.stats()
+    st, _, info = b.stats()
     assert st == []
     s = W.spheres(27, 0.3, seed=2)
     g = np.stack(np.meshgrid(*[np.arange(3)] * 3, indexing="ij"), -1).reshape(-1, 3)
@@ -107,6 +107,56 @@ def test_batch_empty_and_contactless():
     s2, items = _instances(2, 300, seed=W.SEED_BASE + 702)
     b = sc.Batch([(P, con)] + items, tol=1e-8, team=2)
     b.solve()
-    st, _ = b.stats()
+    st, _, _ = b.stats()
     assert [x["status"] for x in st] == [0, 0, 0]
     assert st[0]["mvops"] == 1
+
+
+@pytest.mark.parametrize("team", [1, 8])
+def test_batch_adjoint_matches_single_instance_and_oracle(team):
+    """Forward + adjoint of L = 1/2 ||D gamma||^2 for every instance in one
+    persistent launch: the gradients equal the single-instance adjoint of the
+    batch's own solution (both are the same implicit solve), and agree with
+    the oracle's adjoint on rod instances whose active sets match."""
+    import paper_1909_06623_amd as sc
+    sus, items = _instances(10, 1500, seed=W.SEED_BASE + 703, full=True)
+    _say(f"batch adjoint team={team}: {len(items)} instances")
+    b = sc.Batch(items, tol=1e-10, team=team, adjoint=1, adjoint_tol=1e-12)
+    b.solve()
+    st, adj, info = b.stats()
+    assert all(x["status"] == 0 for x in st)
+    assert all(x["status"] == 0 for x in adj), [x["status"] for x in adj]
+    checked = 0
+    for s, (P, con, box, u_nc, dt), gam, dq, dpos in zip(sus, items, b.gamma, b.dL_dq,
+                                                          b.dL_dpos):
+        if con.count == 0:
+            continue
+        _, _, _, f_c, _ = sc.solve_lcp(P, con, tol=1e-10, want_fc=True, max_iter=0,
+                                       gamma0=gam)
+        rq, rpos, _ = sc.solve_lcp_adjoint(P, box, con, u_nc, dt, gam, dL_df=f_c, tol=1e-12)
+        np.testing.assert_allclose(dq.cpu().numpy(), rq.cpu().numpy(), rtol=0,
+                                   atol=1e-8 * max(1.0, float(rq.abs().max())))
+        np.testing.assert_allclose(dpos.cpu().numpy(), rpos.cpu().numpy(), rtol=0,
+                                   atol=1e-8 * max(1.0, float(rpos.abs().max())))
+        if "rods" not in s.name:
+            continue
+        c, u_orc, q = O.setup(s)
+        pm = con.canonical_order().cpu().numpy()
+        go, _, _ = O.bbpgd(s, c, q, tol=1e-10)
+        gp, _, _ = O.polish(s, c, q, go)
+        if not np.array_equal(gam.cpu().numpy()[pm] > 0, gp > 0):
+            continue
+        oq, opos, _ = O.adjoint(s, c, q, u_orc, gp, dL_dF=O.D_apply(s.n, c, gp))
+        np.testing.assert_allclose(dq.cpu().numpy()[pm], oq, rtol=0,
+                                   atol=1e-6 * np.abs(oq).max())
+        np.testing.assert_allclose(dpos.cpu().numpy(), opos, rtol=0,
+                                   atol=1e-6 * np.abs(opos).max())
+        checked += 1
+    _say(f"oracle-checked rod instances: {checked}")
+    assert checked >= 1
+    # graph replay reproduces the gradients bitwise
+    d1 = [x.clone() for x in b.dL_dpos]
+    b.graph_solve()
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, x) for a, x in zip(d1, b.dL_dpos))
+    b.close()
