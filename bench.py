@@ -24,7 +24,8 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE passes, scaled by a plain-copy calibration).
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bbpgd_mat_rods100k_traffic.json")
 # Sources that define the persistent matrix solve kernel.
-KERNEL_SOURCES = ["sc_matrix.hip", "sc_matrix.hpp", "sc_chain.hpp", "sc_sync.hpp", "sc_common.hpp"]
+KERNEL_SOURCES = ["sc_matrix.hip", "sc_matrix.hpp", "sc_matrix_pass.hpp", "sc_chain.hpp", "sc_sync.hpp",
+                  "sc_common.hpp"]
 
 
 def iteration_bytes(nc, n, rods=True):
@@ -123,7 +124,7 @@ def batched(sc, W, torch, np, count):
             "single_iters_sum": int(sum(single_iters)),
             "build_s": build_s, "tol": tol,
             "adjoint_tol": atol, "work": "forward BBPGD + adjoint (CG, geometric gradient) per instance",
-            "launch": "reset kernel + one cooperative persistent kernel, HIP graph replay"}
+            "launch": "reset kernel + cooperative persistent forward kernel + cooperative persistent adjoint kernel, HIP graph replay"}
 
 
 def main():

@@ -314,11 +314,13 @@ int sc_batch_create(int32_t count, const sc_batch_item *items, const sc_batch_op
                     void *ws, size_t ws_bytes, void *stream, sc_batch **out);
 
 /* Solves every instance of the batch in one persistent launch (preceded by a
- * small reset kernel). Enqueues only: no synchronisation, no allocation. */
+ * small reset kernel; with the adjoint enabled, a second persistent launch
+ * differentiates every solution). Enqueues only: no synchronisation, no
+ * allocation. */
 int sc_batch_solve(sc_batch *b, void *stream);
 
 /* As sc_batch_solve, through a HIP graph captured on the first call (the
- * persistent kernel's node is marked cooperative) and replayed after. */
+ * persistent kernels' nodes are marked cooperative) and replayed after. */
 int sc_batch_graph_launch(sc_batch *b, void *stream);
 
 /* Per-instance results of the last solve (st: host array of count; grid

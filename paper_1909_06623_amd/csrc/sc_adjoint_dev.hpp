@@ -33,7 +33,7 @@ __device__ inline double cg_rhs_one(int l, const int *ci, const int *cj, const d
 // parameters s, t move with r only while strictly inside their segment:
 // both free -> implicit differentiation of the 2x2 stationarity conditions;
 // one free -> its 1-D projection; both clamped (or a sphere) -> fixed.
-__device__ inline V3 contact_grad_one(int l, const int *__restrict__ ci, const int *__restrict__ cj,
+__device__ __noinline__ V3 contact_grad_one(int l, const int *__restrict__ ci, const int *__restrict__ cj,
                                      const int *__restrict__ cs, const double *__restrict__ pos,
                                      const double *__restrict__ axis,
                                      const double *__restrict__ half_len, const PBox &box,

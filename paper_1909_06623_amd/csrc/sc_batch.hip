@@ -82,10 +82,11 @@ struct BatchArgs {
 // no team reached keeps SC_ERR_TIMEOUT).
 __global__ void k_batch_reset(BatchCtl *ctl, TeamSync *ts, int nteams, SolveCtrl *ctrl,
                               CgCtrl *cg, int count) {
-    unsigned *c = reinterpret_cast<unsigned *>(ctl);
-    for (int k = threadIdx.x; k < static_cast<int>(sizeof(BatchCtl) / 4); k += blockDim.x) c[k] = 0u;
+    unsigned *c = reinterpret_cast<unsigned *>(ctl);  // one block per stage
+    for (int k = threadIdx.x; k < static_cast<int>(2 * sizeof(BatchCtl) / 4); k += blockDim.x)
+        c[k] = 0u;
     unsigned *t = reinterpret_cast<unsigned *>(ts);
-    const long long nt = static_cast<long long>(nteams) * (sizeof(TeamSync) / 4);
+    const long long nt = 2LL * nteams * (sizeof(TeamSync) / 4);  // one set per stage
     for (long long k = threadIdx.x; k < nt; k += blockDim.x) t[k] = 0u;
     for (int k = threadIdx.x; k < count; k += blockDim.x) {
         ctrl[k] = SolveCtrl{};
@@ -139,7 +140,9 @@ __device__ void adjoint_rows(const BatchArgs &A, const BatchDesc &D, const Slice
     for (int k = k0 + threadIdx.x; k < k1; k += BS) gather_pos_one(k, D.pl, D.grad, D.dpos);
 }
 
-template <int R, int BS>
+// STAGE 0 solves every instance, STAGE 1 (a second launch, so that each
+// kernel keeps its own register budget) runs the adjoint of every solution.
+template <int R, int BS, int STAGE>
 __global__ void __launch_bounds__(BS) k_bbpgd_batch(BatchArgs A) {
     __shared__ int sh[4];
     BatchCtl *ctl = A.ctl;
@@ -186,20 +189,23 @@ __global__ void __launch_bounds__(BS) k_bbpgd_batch(BatchArgs A) {
         const SliceChunk ch = slice_chunk(D.M, member, t);
         const WaveCache W = wave_cache<R, BS>(D.M, ch, A.cache);
         fill_cache<R, BS>(D.M, ch, W);
-        bbpgd_rows<R, BS>(D.M, ch, W, D.q, A.warm ? D.gamma : nullptr, D.gamma, D.g, D.z0, D.z1,
-                          part, kTeamPartHalf, member, t, tb, A.tol, A.max_iter, A.bb,
-                          A.ctrl + item);
-        if (A.adjoint) adjoint_rows<R, BS>(A, D, ch, W, part, member, t, tb, item);
+        if (STAGE == 0)
+            bbpgd_rows<R, BS>(D.M, ch, W, D.q, A.warm ? D.gamma : nullptr, D.gamma, D.g, D.z0,
+                              D.z1, part, kTeamPartHalf, member, t, tb, A.tol, A.max_iter, A.bb,
+                              A.ctrl + item);
+        else
+            adjoint_rows<R, BS>(A, D, ch, W, part, member, t, tb, item);
     }
 }
 
 using BatchKernel = void (*)(BatchArgs);
 
+template <int STAGE>
 BatchKernel batch_kernel(int block) {
     switch (block) {
-    case 256: return k_bbpgd_batch<1, 256>;
-    case 512: return k_bbpgd_batch<1, 512>;
-    default: return k_bbpgd_batch<1, 1024>;
+    case 256: return k_bbpgd_batch<1, 256, STAGE>;
+    case 512: return k_bbpgd_batch<1, 512, STAGE>;
+    default: return k_bbpgd_batch<1, 1024, STAGE>;
     }
 }
 
@@ -243,7 +249,7 @@ struct sc_batch {
     int nteams_max = 0;
     int team = 1, block = 1024, grid = 0;
     size_t dyn = 0;
-    const void *fn = nullptr;
+    const void *fn = nullptr, *fn_adj = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     float tune_ms[6] = {0, 0, 0, 0, 0, 0};
@@ -257,8 +263,8 @@ size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nteams, boo
     b += align_up(sizeof(CgCtrl) * nd, 256);
     if (adj)
         for (int32_t k = 0; k < count; ++k) b += 8 * 256 + sizeof(double) * adj_doubles(items[k]);
-    b += align_up(sizeof(BatchCtl), 256);
-    b += align_up(sizeof(TeamSync) * static_cast<size_t>(nteams), 256);
+    b += align_up(2 * sizeof(BatchCtl), 256);
+    b += align_up(2 * sizeof(TeamSync) * static_cast<size_t>(nteams), 256);
     b += align_up(sizeof(double) * 2 * kTeamPartHalf * static_cast<size_t>(nteams), 256);
     b += align_up(sizeof(BatchDesc) * nd, 256);
     b += align_up(sizeof(int) * nd, 256);
@@ -275,6 +281,14 @@ int enqueue(sc_batch *b, hipStream_t s) {
     a.team = b->team;
     void *args[] = {&a};
     SC_HIP_TRY(hipLaunchCooperativeKernel(b->fn, dim3(b->grid), dim3(b->block), args, b->dyn, s));
+    if (b->args.adjoint) {
+        BatchArgs c = a;
+        c.ctl = b->args.ctl + 1;
+        c.tsync = b->args.tsync + b->nteams_max;
+        void *cargs[] = {&c};
+        SC_HIP_TRY(hipLaunchCooperativeKernel(b->fn_adj, dim3(b->grid), dim3(b->block), cargs,
+                                              b->dyn, s));
+    }
     return SC_OK;
 }
 
@@ -345,13 +359,22 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     auto *b = new sc_batch;
     b->count = count;
     b->block = opts->block ? opts->block : 1024;
-    b->fn = reinterpret_cast<const void *>(batch_kernel(b->block));
-    int per_block = 0;
-    if (batch_cache(b->fn, b->block, &per_block, &b->dyn) != hipSuccess) {
+    b->fn = reinterpret_cast<const void *>(batch_kernel<0>(b->block));
+    b->fn_adj = reinterpret_cast<const void *>(batch_kernel<1>(b->block));
+    int per_block = 0, per_adj = 0;
+    size_t dyn_adj = 0;
+    if (batch_cache(b->fn, b->block, &per_block, &b->dyn) != hipSuccess ||
+        batch_cache(b->fn_adj, b->block, &per_adj, &dyn_adj) != hipSuccess) {
         delete b;
         return SC_ERR_HIP;
     }
-    b->grid = persistent_grid(b->fn, b->block, 0, b->dyn);
+    // both stages use the smaller LDS share, so that one walk serves both
+    if (per_adj < per_block) {
+        per_block = per_adj;
+        b->dyn = dyn_adj;
+    }
+    b->grid = std::min(persistent_grid(b->fn, b->block, 0, b->dyn),
+                       persistent_grid(b->fn_adj, b->block, 0, b->dyn));
     b->nteams_max = b->grid;
     if (b->grid < 1) {
         delete b;
@@ -364,8 +387,8 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     }
     Carver cv{static_cast<char *>(ws), ws_bytes};
     BatchArgs &a = b->args;
-    a.ctl = cv.take<BatchCtl>(1);
-    a.tsync = cv.take<TeamSync>(static_cast<size_t>(b->nteams_max));
+    a.ctl = cv.take<BatchCtl>(2);
+    a.tsync = cv.take<TeamSync>(2 * static_cast<size_t>(b->nteams_max));
     a.part = cv.take<double>(2 * kTeamPartHalf * static_cast<size_t>(b->nteams_max));
     BatchDesc *d_descs = cv.take<BatchDesc>(static_cast<size_t>(std::max(count, 1)));
     int *d_order = cv.take<int>(static_cast<size_t>(std::max(count, 1)));
@@ -497,7 +520,7 @@ int build_graph(sc_batch *b) {
         if (hipGraphNodeGetType(nodes[i], &ty) != hipSuccess) rc = SC_ERR_HIP;
         if (rc != SC_OK || ty != hipGraphNodeTypeKernel) continue;
         if (hipGraphKernelNodeGetParams(nodes[i], &kp) != hipSuccess) rc = SC_ERR_HIP;
-        if (rc != SC_OK || kp.func != b->fn) continue;
+        if (rc != SC_OK || (kp.func != b->fn && kp.func != b->fn_adj)) continue;
         hipKernelNodeAttrValue v{}, chk{};
         v.cooperative = 1;
         if (hipGraphKernelNodeSetAttribute(nodes[i], hipKernelNodeAttributeCooperative, &v) !=
@@ -508,7 +531,7 @@ int build_graph(sc_batch *b) {
             rc = SC_ERR_HIP;
         ++marked;
     }
-    if (rc == SC_OK && marked != 1) rc = SC_ERR_HIP;
+    if (rc == SC_OK && marked != (b->args.adjoint ? 2 : 1)) rc = SC_ERR_HIP;
     if (rc == SC_OK && hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
         b->exec = nullptr;
         rc = SC_ERR_HIP;

@@ -41,7 +41,7 @@ def test_two_spheres_gradient_closed_form_and_fd():
     dt, delta = 1e-3, 0.1
     pos = P.pos.clone().requires_grad_(True)
     gamma, f_c, info = collision_solve(pos, P, box, u_nc, dt, delta, tol=1e-12)
-    assert info.contacts.count == 1 and float(gamma[0]) > 0
+    assert info.contacts.count == 1 and float(gamma.detach()[0]) > 0
     gamma.sum().backward()
     M = 2.0 / (6 * math.pi * 0.5)
     g = pos.grad.cpu().numpy()

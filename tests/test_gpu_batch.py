@@ -160,3 +160,24 @@ def test_batch_adjoint_matches_single_instance_and_oracle(team):
     torch.cuda.synchronize()
     assert all(torch.equal(a, x) for a, x in zip(d1, b.dL_dpos))
     b.close()
+
+
+def test_batch_status_paths_eager_and_graph():
+    """Per-instance status codes come back from the batch in eager and in
+    graph mode: a NaN in one instance's q gives SC_ERR_NONFINITE for that
+    instance only, and a small iteration cap SC_NOT_CONVERGED for the rest."""
+    import paper_1909_06623_amd as sc
+    import paper_1909_06623_amd._abi as A
+    sus, items = _instances(4, 800, seed=W.SEED_BASE + 704)
+    items = [it for it in items if it[1].count > 10][:3]
+    assert len(items) == 3
+    _say("batch status paths")
+    items[1][1].q[2] = float("nan")
+    b = sc.Batch(items, tol=1e-12, max_iter=5, team=2)
+    for run in (b.solve, b.graph_solve, b.graph_solve):
+        run()
+        st, _, _ = b.stats()
+        assert [x["status"] for x in st] == [A.SC_NOT_CONVERGED, A.SC_ERR_NONFINITE,
+                                             A.SC_NOT_CONVERGED]
+        assert st[0]["iters"] == 5 and st[2]["iters"] == 5
+    b.close()
