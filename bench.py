@@ -37,6 +37,41 @@ def iteration_bytes(nc, n, rods=True):
     return 216 * nc + 120 * n if rods else 120 * nc + 56 * n
 
 
+def mixed_iteration_bytes(nc_rod, nc_sph, n_rod, n_sph):
+    """iteration_bytes for a mixture: contacts that involve a rod and rods
+    priced as rods, sphere-sphere contacts and spheres as spheres."""
+    return 216 * nc_rod + 120 * nc_sph + 120 * n_rod + 56 * n_sph
+
+
+def large(sc, W, torch, np):
+    """Forward solve of the 1,000,000-rod + 100,000-sphere suspension (aligned
+    rods, Watson kappa 5): the largest single-GPU configuration, timed on its
+    own (two solves after one warm-up, HIP events of the persistent kernel)."""
+    s = W.workload(3)
+    P = sc.Particles.from_suspension(s)
+    box = sc.Box(tuple(s.box))
+    u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt)
+    sts = [sc.solve_lcp(P, con, tol=s.tol)[2] for _ in range(3)][1:]
+    st = sts[-1]
+    ci = con.i.cpu().numpy()
+    cj = con.j.cpu().numpy()
+    sph = s.half_len == 0
+    nc_sph = int(np.count_nonzero(sph[ci] & sph[cj]))
+    n_sph = int(np.count_nonzero(sph))
+    bytes_iter = mixed_iteration_bytes(con.count - nc_sph, nc_sph, s.n - n_sph, n_sph)
+    products = st["iters"] + 2
+    kernel_ms = float(np.mean([x["kernel_ms"] for x in sts]))
+    achieved = bytes_iter * products / (kernel_ms * 1e-3) / 1e9
+    return {"workload": "1,000,000 spherocylinders (Watson-aligned, kappa 5) + 100,000 "
+                        "spheres D=0.1, periodic box, BBPGD (BB1) to 1e-6",
+            "n": s.n, "n_contacts": con.count, "nnz_M": con.nnz, "iters": st["iters"],
+            "status": st["status"], "solve_ms": kernel_ms,
+            "us_per_product": 1e3 * kernel_ms / products,
+            "bytes_per_product": bytes_iter, "achieved_gbs": achieved,
+            "frac": achieved / HBM_PEAK_GBS, "rods_per_s": s.n / (kernel_ms * 1e-3)}
+
+
 def operator_bytes(nc, nnz):
     """Bytes the assembled-M product itself streams per iteration: each
     nonzero's column and value (12), and per row its length (4), q (8) and
@@ -137,6 +172,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--large", action="store_true",
+                    help="also time the 1.1M-particle forward solve")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
     args = ap.parse_args()
@@ -231,6 +268,7 @@ def main():
                "cg_rel_residual": sta["residual"], "n_active": sta["n_active"]}
 
     batch = None if args.no_batch else batched(sc, W, torch, np, args.batch_count)
+    big = large(sc, W, torch, np) if args.large else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -291,6 +329,7 @@ def main():
         "adjoint": adj,
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],
         "batched": batch,
+        "large": big,
     }
     print(json.dumps(line), flush=True)
 

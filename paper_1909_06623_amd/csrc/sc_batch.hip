@@ -189,10 +189,12 @@ __global__ void __launch_bounds__(BS) k_bbpgd_batch(BatchArgs A) {
         const SliceChunk ch = slice_chunk(D.M, member, t);
         const WaveCache W = wave_cache<R, BS>(D.M, ch, A.cache);
         fill_cache<R, BS>(D.M, ch, W);
-        if (STAGE == 0)
-            bbpgd_rows<R, BS>(D.M, ch, W, D.q, A.warm ? D.gamma : nullptr, D.gamma, D.g, D.z0,
-                              D.z1, part, kTeamPartHalf, member, t, tb, A.tol, A.max_iter, A.bb,
-                              A.ctrl + item);
+        // 4 gathers in flight per wave: the team logic leaves fewer registers
+        constexpr int B = R == 1 ? 4 : 8 / R;
+        if constexpr (STAGE == 0)
+            bbpgd_rows<R, BS, TeamBarrier, B>(D.M, ch, W, D.q, A.warm ? D.gamma : nullptr, D.gamma,
+                                              D.g, D.z0, D.z1, part, kTeamPartHalf, member, t, tb,
+                                              A.tol, A.max_iter, A.bb, A.ctrl + item);
         else
             adjoint_rows<R, BS>(A, D, ch, W, part, member, t, tb, item);
     }

@@ -68,6 +68,23 @@ struct V3 {
     double x, y, z;
 };
 
+// Global-memory view of a generic pointer into device memory. Where the
+// compiler cannot prove a pointer's address space (a pointer picked from a
+// dynamically indexed array, a select between buffers) it emits flat
+// accesses, and a flat access also counts against the LDS counter: every
+// wait for an LDS read would then wait for the outstanding gathers and
+// stores too. Accesses through this view are global loads and stores.
+// (Records are read member by member: a class object cannot be copied out
+// of another address space.)
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p) {
+    return (__attribute__((address_space(1))) T *)(reinterpret_cast<uintptr_t>(p));
+}
+template <class T>
+__device__ __forceinline__ T ld_global(const T *p) {
+    return *gmem(p);
+}
+
 __device__ __forceinline__ V3 v3(double x, double y, double z) { return {x, y, z}; }
 __device__ __forceinline__ V3 load3(const double *p) { return {p[0], p[1], p[2]}; }
 __device__ __forceinline__ void store3(double *p, V3 a) {

@@ -173,8 +173,11 @@ __global__ void __launch_bounds__(BS) k_bbpgd_mat(MatSolve A) {
     const SliceChunk rc = slice_chunk(A.M, L, gridDim.x);
     const WaveCache W = wave_cache<R, BS>(A.M, rc, A.cache);
     fill_cache<R, BS>(A.M, rc, W);
-    bbpgd_rows<R, BS>(A.M, rc, W, A.q, A.gamma, A.gamma, A.g, A.z[0], A.z[1], A.part, kPartHalf,
-                      L, gridDim.x, bar, A.tol, A.max_iter, A.bb, A.ctrl);
+    // 6 gathers in flight per wave (one slice per wave): measured best here
+    constexpr int B = R == 1 ? 6 : 8 / R;
+    bbpgd_rows<R, BS, GridBarrier, B>(A.M, rc, W, A.q, A.gamma, A.gamma, A.g, A.z[0], A.z[1],
+                                      A.part, kPartHalf, L, gridDim.x, bar, A.tol, A.max_iter,
+                                      A.bb, A.ctrl);
 }
 
 struct MatCg {

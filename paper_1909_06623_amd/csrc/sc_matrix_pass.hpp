@@ -180,23 +180,33 @@ __device__ WaveMeta<R> wave_meta(const MatView &M, const SliceChunk &ch) {
 // depths it reads the columns, issues every gather, then reads the values
 // and accumulates. The batch has no per-entry branch, so its gathers are in
 // flight together: a lane without an entry at a depth gathers its own row
-// and adds nothing. pre(l) loads the row's own inputs up front; epi(l, acc,
-// pre) finishes the row. LDS residency follows the walk of fill_cache.
-template <int R, int BS, class P, class X, class E>
+// and adds nothing. pre(l) loads the row's own inputs up front; ld(m) loads
+// column m's record and tf(record) gives x(m); epi(l, acc, pre) finishes the
+// row. A scheduling barrier keeps every gather of a batch ahead of the first
+// use of any of them (left to itself the compiler may interleave each load
+// with its transform and wait for it, one round trip per entry). LDS
+// residency follows the walk of fill_cache. Values of M are read from LDS, or
+// for entries past the wave's share with global loads issued after the
+// gathers.
+template <int R, int BS, int B = 8 / R, class P, class LD, class TF, class E>
 __device__ __forceinline__ void spmv_pass(const MatView &M, const SliceChunk &ch,
                                           const WaveCache &W, const WaveMeta<R> &Mt, P pre,
-                                          X xf, E epi) {
+                                          LD ld, TF tf, E epi) {
+    // B: depths per batch (8 / R measured best for 16-byte records)
     constexpr int NW = BS / kWave;
-    constexpr int B = 8 / R;  // depths per batch (measured best with 1024 threads)
     using Pre = decltype(pre(0));
+    using Xr = decltype(ld(0));
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const unsigned long long below = (1ull << lane) - 1ull;
-    int used = 0, grp = 0;
-    for (int s = ch.s0 + wv; s < ch.s1; s += NW * R, ++grp) {
-        int n[R], pos[R], e0[R], lds0[R], nlds[R], row[R];
-        Pre pv[R];
-        double acc[R];
-        int wid = 0;
+    int used = 0;
+    int n[R], pos[R], e0[R], lds0[R], nlds[R], row[R], wid;
+    Pre pv[R];
+    double acc[R];
+    int li[R][B];
+    Xr xr[R][B];
+    // row metadata of slice group grp (slices s + r NW)
+    auto setup = [&](int s, int grp) {
+        wid = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int sr = s + r * NW;
@@ -223,56 +233,98 @@ __device__ __forceinline__ void spmv_pass(const MatView &M, const SliceChunk &ch
             pv[r] = pre(row[r]);
             acc[r] = 0.0;
         }
-        for (int t0 = 0; t0 < wid; t0 += B) {
-            int c[R][B], li[R][B];
-            bool spill = false;
+    };
+    // columns of depths t0 .. t0 + B - 1 and their gathers
+    bool spill = false;
+    auto load = [&](int t0) {
+        int c[R][B];
+        spill = false;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < R; ++r) {
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const bool on = t0 + b < n[r];
-                    const unsigned long long bal = __ballot(on);
-                    const int at = pos[r] + __popcll(bal & below);
-                    pos[r] += __popcll(bal);
-                    const int o = at - e0[r];
-                    const bool in_lds = on && o < nlds[r];
-                    spill |= on && !in_lds;
-                    // LDS index (0 is always a valid slot) or, if spilled, -1 - global index
-                    li[r][b] = in_lds ? lds0[r] + o : (on ? -1 - at : 0);
-                    const int cl = W.col[in_lds ? lds0[r] + o : 0];
-                    c[r][b] = in_lds ? cl : row[r];
-                }
+            for (int b = 0; b < B; ++b) {
+                const bool on = t0 + b < n[r];
+                const unsigned long long bal = __ballot(on);
+                const int at = pos[r] + __popcll(bal & below);
+                pos[r] += __popcll(bal);
+                const int o = at - e0[r];
+                const bool in_lds = on && o < nlds[r];
+                spill |= on && !in_lds;
+                // LDS index (0 is always a valid slot) or, if spilled, -1 - global index
+                li[r][b] = in_lds ? lds0[r] + o : (on ? -1 - at : 0);
+                const int cl = W.col[in_lds ? lds0[r] + o : 0];
+                c[r][b] = in_lds ? cl : row[r];
             }
-            if (__any(spill)) {
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                    for (int b = 0; b < B; ++b)
-                        if (li[r][b] < 0) c[r][b] = M.col[-1 - li[r][b]];
-            }
-            double x[R][B];
+        }
+        spill = __any(spill);
+        if (spill) {  // entries of M past the wave's LDS share
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int b = 0; b < B; ++b) x[r][b] = xf(c[r][b]);
+                for (int b = 0; b < B; ++b) {
+                    const int cg = ld_global(M.col + (li[r][b] < 0 ? -1 - li[r][b] : 0));
+                    c[r][b] = li[r][b] < 0 ? cg : c[r][b];
+                }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int b = 0; b < B; ++b) xr[r][b] = ld(c[r][b]);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // values (LDS reads; global loads, in flight together, where the batch
+    // holds entries past the wave's LDS share) and the products
+    auto consume = [&](int t0) {
+        if (spill) {
+            double vg[R][B];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int b = 0; b < B; ++b)
+                    vg[r][b] = ld_global(M.val + (li[r][b] < 0 ? -1 - li[r][b] : 0));
 #pragma unroll
             for (int r = 0; r < R; ++r) {
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     const int k = li[r][b];
-                    const double v = k < 0 ? M.val[-1 - k] : W.val[k];
+                    const double vs = W.val[k < 0 ? 0 : k];
+                    const double v = k < 0 ? vg[r][b] : vs;
                     const bool on = t0 + b < n[r];
-                    acc[r] += on ? v * x[r][b] : 0.0;
+                    acc[r] += on ? v * tf(xr[r][b]) : 0.0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const bool on = t0 + b < n[r];
+                    acc[r] += on ? W.val[li[r][b]] * tf(xr[r][b]) : 0.0;
                 }
             }
         }
+    };
+    auto finish = [&](int s) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
             if (n[r] > 0) epi((s + r * NW) * kWave + lane, acc[r], pv[r]);
+    };
+    int grp = 0;
+    for (int s = ch.s0 + wv; s < ch.s1; s += NW * R, ++grp) {
+        setup(s, grp);
+        for (int t0 = 0; t0 < wid; t0 += B) {
+            load(t0);
+            consume(t0);
+        }
+        finish(s);
     }
 }
 
 __device__ inline double project(double v) { return v < 0.0 ? 0.0 : v; }
+
+struct Ident {
+    __device__ double operator()(double x) const { return x; }
+};
 
 // With one barrier per iteration, a workgroup may write the partials of
 // reduction r + 1 while a slower one still reads those of reduction r, so
@@ -284,16 +336,21 @@ __device__ inline double *part_buf(double *part, int r, int half = kPartHalf) {
 
 // BBPGD state per contact: (gamma, g) interleaved so that a column costs one
 // 16-byte gather.
-struct GG {
+struct alignas(16) GG {
     double gam, g;
 };
+
+__device__ __forceinline__ GG ld_gg(const GG *p) {
+    const auto *q = gmem(p);
+    return GG{q->gam, q->g};
+}
 
 // Algorithm 1 on the rows of one part (of `nparts`) of an assembled M: the
 // part's slices `rc`, its LDS share `W`, its partial-sum slot `slot`, and a
 // barrier over all parts (the grid, or a team of workgroups). x0 = gamma_0
 // (nullptr: zero). Partials alternate between part and part + half. Writes
 // gamma and g of its own rows; part 0 writes `ctrl`.
-template <int R, int BS, class Bar>
+template <int R, int BS, class Bar, int B = 8 / R>
 __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCache &W,
                            const double *q, const double *x0, double *gamma, double *g,
                            GG *zb0, GG *zb1, double *part, int half, int slot, int nparts,
@@ -312,7 +369,8 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         GG *z0 = z[0];
         spmv_pass<R, BS>(M, rc, W, Mt, [&](int l) { return GG{x0 ? x0[l] : 0.0, q[l]}; },
-                         [&](int m) { return x0 ? x0[m] : 0.0; }, [&](int l, double v, GG pq) {
+                         [&](int m) { return x0 ? ld_global(x0 + m) : 0.0; }, Ident{},
+                         [&](int l, double v, GG pq) {
             const double gl = v + pq.g;
             const double gm = pq.gam;
             z0[l] = GG{gm, gl};
@@ -340,7 +398,8 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
             const GG *z0 = z[0];
             spmv_pass<R, BS>(M, rc, W, Mt, [&](int l) { return GG{z0[l].g, mat_diag(M, l)}; },
-                             [&](int m) { return z0[m].g; }, [&](int l, double v, GG pd) {
+                             [&](int m) { return ld_global(&z0[m].g); }, Ident{},
+                             [&](int l, double v, GG pd) {
                                  acc[0] += pd.gam * v;
                                  acc[1] = fmax(acc[1], pd.g);
                              });
@@ -365,19 +424,17 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
                 GG z;
                 double q;
             };
-            spmv_pass<R, BS>(
-                M, rc, W, Mt, [&](int l) { return Own{zc[l], q[l]}; },
-                [&](int m) {
-                    const GG zm = zc[m];
-                    return project(zm.gam - alpha * zm.g);
-                },
+            spmv_pass<R, BS, B>(
+                M, rc, W, Mt, [&](int l) { return Own{ld_gg(zc + l), ld_global(q + l)}; },
+                [&](int m) { return ld_gg(zc + m); },
+                [&](const GG &zm) { return project(zm.gam - alpha * zm.g); },
                 [&](int l, double v, const Own &o) {
                     const GG zl = o.z;
                     const double gm = project(zl.gam - alpha * zl.g);
                     const double gl = v + o.q;
                     // streamed past L2: the next barrier's write-back has less to flush
-                    __builtin_nontemporal_store(gm, &zn[l].gam);
-                    __builtin_nontemporal_store(gl, &zn[l].g);
+                    __builtin_nontemporal_store(gm, &gmem(zn)[l].gam);
+                    __builtin_nontemporal_store(gl, &gmem(zn)[l].g);
                     const double mm = gm < gl ? gm : gl;
                     const double s = gm - zl.gam, y = gl - zl.g;
                     acc[0] += mm * mm;
@@ -433,9 +490,14 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
 
 // CG state per contact: (r_{i-1}, w_{i-1} = A r_{i-1}, s_{i-2}) interleaved,
 // so that forming r_i for a column costs one 32-byte gather.
-struct RWS {
+struct alignas(32) RWS {
     double r, w, s, pad;
 };
+
+__device__ __forceinline__ RWS ld_rws(const RWS *p) {
+    const auto *q = gmem(p);
+    return RWS{q->r, q->w, q->s, 0.0};
+}
 
 // Chronopoulos-Gear CG on M_AA (z0.r holds the masked right-hand side,
 // the other fields and p, x are zero on entry). Iteration i forms
@@ -456,11 +518,17 @@ __device__ void cg_rows(const MatView &M, const SliceChunk &rc, const WaveCache 
         double acc[2] = {0.0, 0.0};
         const RWS *z0 = z[0];
         RWS *z1 = z[1];
-        spmv_pass<R, BS>(M, rc, W, Mt, [&](int l) { return GG{z0[l].r, gamma[l]}; },
-                              [&](int m) { return z0[m].r; }, [&](int l, double v, GG o) {
+        spmv_pass<R, BS>(M, rc, W, Mt,
+                         [&](int l) { return GG{ld_global(&z0[l].r), ld_global(gamma + l)}; },
+                         [&](int m) { return ld_global(&z0[m].r); }, Ident{},
+                         [&](int l, double v, GG o) {
             const double rl = o.gam;
             const double wl = o.g > 0.0 ? v : 0.0;
-            z1[l] = RWS{rl, wl, 0.0, 0.0};
+            auto *zo = &gmem(z1)[l];
+            zo->r = rl;
+            zo->w = wl;
+            zo->s = 0.0;
+            zo->pad = 0.0;
             acc[0] += rl * rl;
             acc[1] += wl * rl;
         });
@@ -487,23 +555,26 @@ __device__ void cg_rows(const MatView &M, const SliceChunk &rc, const WaveCache 
                 RWS z;
                 double p, x, act;
             };
-            spmv_pass<R, BS>(
-                M, rc, W, Mt, [&](int l) { return Own{zc[l], p[l], x[l], gamma[l]}; },
-                [&](int m) {
-                    const RWS zm = zc[m];
-                    return zm.r - alpha * (zm.w + beta * zm.s);
+            spmv_pass<R, BS, R == 1 ? 4 : 8 / R>(  // 24-byte records: 4 in flight (measured)
+
+                M, rc, W, Mt,
+                [&](int l) {
+                    return Own{ld_rws(zc + l), ld_global(p + l), ld_global(x + l),
+                               ld_global(gamma + l)};
                 },
+                [&](int m) { return ld_rws(zc + m); },
+                [&](const RWS &zm) { return zm.r - alpha * (zm.w + beta * zm.s); },
                 [&](int l, double v, const Own &o) {
                     const RWS zl = o.z;
                     const double sl = zl.w + beta * zl.s;
                     const double pl = zl.r + beta * o.p;
-                    x[l] = o.x + alpha * pl;
-                    p[l] = pl;
+                    gmem(x)[l] = o.x + alpha * pl;
+                    gmem(p)[l] = pl;
                     const double rl = zl.r - alpha * sl;
                     const double wl = o.act > 0.0 ? v : 0.0;
-                    __builtin_nontemporal_store(rl, &zn[l].r);
-                    __builtin_nontemporal_store(wl, &zn[l].w);
-                    __builtin_nontemporal_store(sl, &zn[l].s);
+                    __builtin_nontemporal_store(rl, &gmem(zn)[l].r);
+                    __builtin_nontemporal_store(wl, &gmem(zn)[l].w);
+                    __builtin_nontemporal_store(sl, &gmem(zn)[l].s);
                     acc[0] += rl * rl;
                     acc[1] += wl * rl;
                 });
