@@ -102,64 +102,94 @@ def measured_traffic(iters):
 
 def batched(sc, W, torch, np, count):
     """512 independent suspensions (N log-uniform in [200, 20000], spheres or
-    rods), forward solve + adjoint of L = 1/2 ||D gamma||^2 each: one
-    persistent launch replayed from a HIP graph, against the same instances
-    solved one at a time (solve_lcp + solve_lcp_adjoint) on the same GPU."""
+    rods): contact build with assembly of M, forward solve and adjoint of
+    L = 1/2 ||D gamma||^2 each, as one HIP graph replayed (the batch builds
+    its contacts on the device), against the same work done one instance at
+    a time (build_contacts + solve_lcp + solve_lcp_adjoint) on the same GPU.
+    The solve + adjoint part alone (contacts prebuilt) is timed both ways
+    too."""
     sus, _ = W.batched_instances(count=count)
-    items = []
-    t0 = time.perf_counter()
+    inst = []
     for s in sus:
         P = sc.Particles.from_suspension(s)
         box = sc.Box(tuple(s.box))
         u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
-        items.append((P, sc.build_contacts(P, box, s.delta, u_nc, s.dt), box, u_nc, s.dt))
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
+        inst.append((s, P, box, u_nc))
     tol, atol = 1e-6, 1e-8
-    t0 = time.perf_counter()
-    b = sc.Batch(items, tol=tol, team=0, adjoint=1, adjoint_tol=atol)
-    tune_s = time.perf_counter() - t0
-    b.graph_solve()
-    torch.cuda.synchronize()
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        b.graph_solve()
-    torch.cuda.synchronize()
-    batch_ms = 1e3 * (time.perf_counter() - t0) / reps
-    st, adj, info = b.stats()
     ws = sc.Workspace()
 
-    def one(P, con, box, u_nc, dt):
-        gam, g, s1, f_c, _ = sc.solve_lcp(P, con, tol=tol, want_fc=True, workspace=ws)
-        sc.solve_lcp_adjoint(P, box, con, u_nc, dt, gam, dL_df=f_c, tol=atol, workspace=ws)
-        return s1["iters"]
+    def graph_ms(b, reps=3):
+        b.graph_solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.graph_solve()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
 
-    for it in items[:4]:  # warm the single-instance path
+    # whole pipeline: build + solve + adjoint in one graph
+    t0 = time.perf_counter()
+    bb = sc.Batch([(P, box, s.delta, u_nc, s.dt) for s, P, box, u_nc in inst], tol=tol, team=0,
+                  adjoint=1, adjoint_tol=atol, build=True)
+    tune_s = time.perf_counter() - t0
+    full_ms = graph_ms(bb)
+    st, adj, info = bb.stats()
+    cnt = bb.counts()
+
+    def one(s, P, box, u_nc):
+        con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, workspace=ws)
+        gam, g, s1, f_c, _ = sc.solve_lcp(P, con, tol=tol, want_fc=True, workspace=ws)
+        sc.solve_lcp_adjoint(P, box, con, u_nc, s.dt, gam, dL_df=f_c, tol=atol, workspace=ws)
+        return con, s1["iters"]
+
+    for it in inst[:4]:  # warm the single-instance path
         one(*it)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    single_iters = [one(*it) for it in items]
+    singles = [one(*it) for it in inst]
     torch.cuda.synchronize()
     single_ms = 1e3 * (time.perf_counter() - t0)
-    b.close()
+
+    # solve + adjoint only, contacts prebuilt
+    items = [(P, con, box, u_nc, s.dt) for (s, P, box, u_nc), (con, _) in zip(inst, singles)]
+    bs = sc.Batch(items, tol=tol, team=info["team"], adjoint=1, adjoint_tol=atol)
+    solve_ms = graph_ms(bs)
+
+    def solve_one(P, con, box, u_nc, dt):
+        gam, g, s1, f_c, _ = sc.solve_lcp(P, con, tol=tol, want_fc=True, workspace=ws)
+        sc.solve_lcp_adjoint(P, box, con, u_nc, dt, gam, dL_df=f_c, tol=atol, workspace=ws)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in items:
+        solve_one(*it)
+    torch.cuda.synchronize()
+    single_solve_ms = 1e3 * (time.perf_counter() - t0)
+    bs.close()
+    bb.close()
     n_tot = sum(s.n for s in sus)
     return {"instances": count, "particles": n_tot,
-            "contacts": sum(it[1].count for it in items),
-            "nnz_M": sum(it[1].nnz for it in items),
-            "batch_ms": batch_ms, "one_at_a_time_ms": single_ms,
-            "speedup": single_ms / batch_ms,
-            "batch_particles_per_s": n_tot / (batch_ms * 1e-3),
+            "contacts": sum(c for c, _, _ in cnt),
+            "contacts_match_single_builds": [c for c, _, _ in cnt] == [c.count for c, _ in singles],
+            "nnz_M": sum(z for _, z, _ in cnt),
+            "batch_ms": full_ms, "one_at_a_time_ms": single_ms,
+            "speedup": single_ms / full_ms,
+            "batch_particles_per_s": n_tot / (full_ms * 1e-3),
+            "solve_adjoint_batch_ms": solve_ms,
+            "solve_adjoint_one_at_a_time_ms": single_solve_ms,
+            "solve_adjoint_speedup": single_solve_ms / solve_ms,
             "team": info["team"], "tune_ms": info["tune_ms"], "tune_s": tune_s,
             "all_converged": all(x["status"] == 0 for x in st),
             "adjoint_all_converged": all(x["status"] == 0 for x in adj),
             "adjoint_cg_iters_sum": sum(x["iters"] for x in adj),
             "iters_max": max(x["iters"] for x in st),
             "iters_sum": sum(x["iters"] for x in st),
-            "single_iters_sum": int(sum(single_iters)),
-            "build_s": build_s, "tol": tol,
-            "adjoint_tol": atol, "work": "forward BBPGD + adjoint (CG, geometric gradient) per instance",
-            "launch": "reset kernel + cooperative persistent forward kernel + cooperative persistent adjoint kernel, HIP graph replay"}
+            "single_iters_sum": int(sum(i for _, i in singles)),
+            "tol": tol, "adjoint_tol": atol,
+            "work": "contact build with assembly of M + forward BBPGD + adjoint (CG, geometric "
+                    "gradient) per instance",
+            "launch": "batched build kernels + reset + cooperative persistent forward and "
+                      "adjoint kernels, one HIP graph replay"}
 
 
 def main():

@@ -261,8 +261,23 @@ int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
  * [c.count] each. For the adjoint (opts->adjoint != 0) also the box, u_nc
  * and dt the contacts were built with, an optional dL/dgamma [c.count]
  * (NULL = 0) and the outputs dL_dq [c.count] and dL_dpos [p.n][3], as in
- * sc_solve_lcp_adjoint. The batch keeps the pointers, not the structs'
- * owners: every buffer must outlive the batch. */
+ * sc_solve_lcp_adjoint.
+ *
+ * With opts->build = 1 the batch builds the contacts itself on every solve
+ * (section 3.2's close-pair set, the frames of Eq. Dmatdef, q of LCP LCPdef
+ * and M, as sc_build_contacts + sc_assemble_matrix do) from the particles'
+ * current positions: box, delta, u_nc and dt are then the build's inputs, c
+ * holds caller-allocated OUTPUT buffers of c.capacity rows (ci, cj, phi, q,
+ * frame; plan of sc_plan_bytes(p.n, c.capacity) bytes; mat of
+ * sc_matrix_bytes(c.capacity, c.nnz) bytes with c.nnz the nonzero capacity),
+ * and gamma, g, dL_dgamma and dL_dq have c.capacity rows. c.count is
+ * ignored; the contacts of the last solve are counted on the device
+ * (sc_batch_contacts). The search grid of each suspension is fixed when the
+ * batch is created (from its particles' largest R + h); positions may change
+ * between solves, radii and lengths may not grow.
+ *
+ * The batch keeps the pointers, not the structs' owners: every buffer must
+ * outlive the batch. */
 typedef struct sc_batch_item {
     sc_particles p;
     sc_contacts c;
@@ -271,6 +286,7 @@ typedef struct sc_batch_item {
     sc_box box;
     const double *u_nc;
     double dt;
+    double delta;           /* build only: pair threshold on Phi (>= 0) */
     const double *dL_dgamma;
     double *dL_dq;
     double *dL_dpos;
@@ -290,7 +306,8 @@ typedef struct sc_batch_opts {
                                linear loss dL_dgamma . gamma only */
     double adjoint_tol;     /* CG tolerance relative to ||b_A|| */
     int32_t adjoint_max_iter;
-    int32_t reserved;
+    int32_t build;          /* 1: each solve first builds every instance's contacts
+                               and M on the device (see sc_batch_item) */
 } sc_batch_opts;
 
 typedef struct sc_batch_info {
@@ -301,9 +318,10 @@ typedef struct sc_batch_info {
 
 typedef struct sc_batch sc_batch;   /* opaque plan (host memory) */
 
-/* Workspace bytes of a batch (device memory, 256-byte aligned); adjoint as
- * in sc_batch_opts. */
-size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *items, int32_t adjoint);
+/* Workspace bytes of a batch (device memory, 256-byte aligned) for these
+ * items and options (adjoint and build matter). 0 on invalid arguments. */
+size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *items,
+                                const sc_batch_opts *opts);
 
 /* Plans a batch of `count` LCPs (Algorithm 1 per instance, section 4): checks
  * every item, writes the instance table and the work order (by nonzeros,
@@ -315,8 +333,12 @@ int sc_batch_create(int32_t count, const sc_batch_item *items, const sc_batch_op
 
 /* Solves every instance of the batch in one persistent launch (preceded by a
  * small reset kernel; with the adjoint enabled, a second persistent launch
- * differentiates every solution). Enqueues only: no synchronisation, no
- * allocation. */
+ * differentiates every solution; with build, the contact build of every
+ * instance comes first, as one sequence of launches over the whole batch).
+ * Enqueues only: no synchronisation, no allocation. An instance whose build
+ * fails (SC_ERR_NONFINITE, SC_ERR_BOX: a particle grew past the planned grid,
+ * SC_ERR_CAPACITY: contacts or nonzeros beyond c.capacity / c.nnz) reports
+ * that status and is not solved; the others are unaffected. */
 int sc_batch_solve(sc_batch *b, void *stream);
 
 /* As sc_batch_solve, through a HIP graph captured on the first call (the
@@ -329,6 +351,12 @@ int sc_batch_graph_launch(sc_batch *b, void *stream);
  * used (info may be NULL). Synchronises `stream`. */
 int sc_batch_stats(const sc_batch *b, sc_stats *st, sc_stats *adj, sc_batch_info *info,
                    void *stream);
+
+/* Build mode: per-instance contact count, nonzeros of M and build status of
+ * the last solve (host arrays of count; any may be NULL). Synchronises
+ * `stream`. SC_ERR_INVALID if the batch does not build its contacts. */
+int sc_batch_contacts(const sc_batch *b, int32_t *count, int64_t *nnz, int32_t *status,
+                      void *stream);
 
 void sc_batch_destroy(sc_batch *b);
 

@@ -80,7 +80,8 @@ class sc_adjoint_opts(ctypes.Structure):
 class sc_batch_item(ctypes.Structure):
     _fields_ = [("p", sc_particles), ("c", sc_contacts), ("gamma", c_dp), ("g", c_dp),
                 ("box", sc_box), ("u_nc", c_dp), ("dt", ctypes.c_double),
-                ("dL_dgamma", c_dp), ("dL_dq", c_dp), ("dL_dpos", c_dp)]
+                ("delta", ctypes.c_double), ("dL_dgamma", c_dp), ("dL_dq", c_dp),
+                ("dL_dpos", c_dp)]
 
 
 class sc_batch_opts(ctypes.Structure):
@@ -88,7 +89,7 @@ class sc_batch_opts(ctypes.Structure):
                 ("bb", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("team", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("adjoint", ctypes.c_int32), ("adjoint_tol", ctypes.c_double),
-                ("adjoint_max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("adjoint_max_iter", ctypes.c_int32), ("build", ctypes.c_int32)]
 
 
 class sc_batch_info(ctypes.Structure):
@@ -117,12 +118,14 @@ SIGNATURES = {
                                             c_dp, c_dp, P(sc_adjoint_opts), P(sc_stats),
                                             c_dp, ctypes.c_size_t, c_dp]),
     "sc_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, P(sc_batch_item),
-                                                   ctypes.c_int32]),
+                                                   P(sc_batch_opts)]),
     "sc_batch_create": (ctypes.c_int, [ctypes.c_int32, P(sc_batch_item), P(sc_batch_opts),
                                        c_dp, ctypes.c_size_t, c_dp, P(ctypes.c_void_p)]),
     "sc_batch_solve": (ctypes.c_int, [c_dp, c_dp]),
     "sc_batch_graph_launch": (ctypes.c_int, [c_dp, c_dp]),
     "sc_batch_stats": (ctypes.c_int, [c_dp, P(sc_stats), P(sc_stats), P(sc_batch_info), c_dp]),
+    "sc_batch_contacts": (ctypes.c_int, [c_dp, P(ctypes.c_int32), P(ctypes.c_int64),
+                                         P(ctypes.c_int32), c_dp]),
     "sc_batch_destroy": (None, [c_dp]),
     "sc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sc_version": (ctypes.c_int, []),

@@ -333,61 +333,123 @@ class Batch:
     the number of workgroups per instance. After ``solve()`` /
     ``graph_solve()``, ``gamma[k]`` and ``g[k]`` hold each solution and, with
     ``adjoint`` (1: loss 1/2 ||D gamma||^2 + dL_dgamma . gamma, 2: the linear
-    term only), ``dL_dq[k]`` and ``dL_dpos[k]`` its gradients."""
+    term only), ``dL_dq[k]`` and ``dL_dpos[k]`` its gradients.
+
+    With ``build=True`` the items are (Particles, Box, delta, u_nc, dt) and
+    every solve first builds all contacts and M on the device from the
+    particles' current positions (so ``graph_solve`` replays build, solves
+    and adjoints as one graph). ``capacity`` / ``nnz_capacity`` (lists) bound
+    each instance's contacts and nonzeros; by default they are measured by
+    one build per instance with headroom. Then ``contacts[k]`` holds the
+    contact arrays, ``gamma[k]``, ``g[k]`` and ``dL_dq[k]`` have capacity
+    rows, and ``counts()`` gives the rows in use."""
 
     def __init__(self, items, tol=1e-6, max_iter=100000, bb=1, team=0, block=0,
                  gamma0=None, adjoint=0, dL_dgamma=None, adjoint_tol=1e-10,
-                 adjoint_max_iter=100000):
+                 adjoint_max_iter=100000, build=False, capacity=None, nnz_capacity=None):
         self._keep = []
         self.gamma, self.g, self.dL_dq, self.dL_dpos = [], [], [], []
+        self.build = bool(build)
+        self.contacts = []
         arr = (A.sc_batch_item * max(1, len(items)))()
         for k, it in enumerate(items):
-            P, con = it[0], it[1]
-            if not con.mat_ready:
-                con.assemble(P)
-            nc = con.count
-            gm = torch.zeros(max(1, nc), dtype=torch.float64, device="cuda")
-            if gamma0 is not None and nc:
-                gm[:nc] = _dev(gamma0[k])
-            g = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
-            self.gamma.append(gm[:nc])
-            self.g.append(g[:nc])
+            if self.build:
+                P, box, delta, u_nc, dt = it[0], it[1], float(it[2]), _dev(it[3]), float(it[4])
+                cap, nnzc = self._capacities(k, P, box, delta, u_nc, dt, capacity, nnz_capacity)
+                con = Contacts(P.n, cap)
+                con.nnz = nnzc
+                mb = int(A.lib().sc_matrix_bytes(cap, nnzc))
+                if mb == 0:
+                    raise RuntimeError(f"M with {nnzc} nonzeros cannot be assembled")
+                con._mat = torch.empty(mb + 256, dtype=torch.uint8, device="cuda")
+                con.mat_ptr = (con._mat.data_ptr() + 255) // 256 * 256
+                con.mat_bytes = mb + 256 - (con.mat_ptr - con._mat.data_ptr())
+                self.contacts.append(con)
+                rows = cap
+                arr[k].box = box.c()
+                arr[k].u_nc = u_nc.data_ptr()
+                arr[k].dt = dt
+                arr[k].delta = delta
+                self._keep += [u_nc]
+            else:
+                P, con = it[0], it[1]
+                if not con.mat_ready:
+                    con.assemble(P)
+                rows = con.count
+            gm = torch.zeros(max(1, rows), dtype=torch.float64, device="cuda")
+            if gamma0 is not None and rows:
+                g0 = _dev(gamma0[k])
+                gm[: g0.numel()] = g0
+            g = torch.empty(max(1, rows), dtype=torch.float64, device="cuda")
+            self.gamma.append(gm[:rows])
+            self.g.append(g[:rows])
             arr[k].p = P.c()
             arr[k].c = con.c()
             arr[k].gamma = gm.data_ptr()
             arr[k].g = g.data_ptr()
             self._keep += [P, con, gm, g]
             if adjoint:
-                box, u_nc, dt = it[2], _dev(it[3]), float(it[4])
-                dq = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
+                if not self.build:
+                    box, u_nc, dt = it[2], _dev(it[3]), float(it[4])
+                    arr[k].box = box.c()
+                    arr[k].u_nc = u_nc.data_ptr()
+                    arr[k].dt = dt
+                    self._keep.append(u_nc)
+                dq = torch.empty(max(1, rows), dtype=torch.float64, device="cuda")
                 dpos = torch.empty((max(1, P.n), 3), dtype=torch.float64, device="cuda")
-                arr[k].box = box.c()
-                arr[k].u_nc = u_nc.data_ptr()
-                arr[k].dt = dt
                 arr[k].dL_dq = dq.data_ptr()
                 arr[k].dL_dpos = dpos.data_ptr()
                 if dL_dgamma is not None and dL_dgamma[k] is not None:
                     dg = _dev(dL_dgamma[k])
                     arr[k].dL_dgamma = dg.data_ptr()
                     self._keep.append(dg)
-                self.dL_dq.append(dq[:nc])
+                self.dL_dq.append(dq[:rows])
                 self.dL_dpos.append(dpos[: P.n])
-                self._keep += [u_nc, dq, dpos]
+                self._keep += [dq, dpos]
         self.count = len(items)
         self.adjoint = int(adjoint)
-        need = int(A.lib().sc_batch_workspace_bytes(self.count, arr, self.adjoint))
+        opts = A.sc_batch_opts(float(tol), int(max_iter), int(bb),
+                               1 if gamma0 is not None else 0, int(team), int(block),
+                               self.adjoint, float(adjoint_tol), int(adjoint_max_iter),
+                               1 if self.build else 0)
+        need = int(A.lib().sc_batch_workspace_bytes(self.count, arr, ctypes.byref(opts)))
+        if need == 0:
+            raise RuntimeError("sc_batch_workspace_bytes: invalid arguments")
         self._ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
         base = (self._ws.data_ptr() + 255) // 256 * 256
         size = need + 256 - (base - self._ws.data_ptr())
-        opts = A.sc_batch_opts(float(tol), int(max_iter), int(bb),
-                               1 if gamma0 is not None else 0, int(team), int(block),
-                               self.adjoint, float(adjoint_tol), int(adjoint_max_iter), 0)
         h = ctypes.c_void_p()
         _check("sc_batch_create",
                A.lib().sc_batch_create(self.count, arr, ctypes.byref(opts), ctypes.c_void_p(base),
                                        ctypes.c_size_t(size), _stream(), ctypes.byref(h)))
         self._items = arr
         self._h = h
+
+    @staticmethod
+    def _capacities(k, P, box, delta, u_nc, dt, capacity, nnz_capacity):
+        if capacity is not None and nnz_capacity is not None:
+            return int(capacity[k]), int(nnz_capacity[k])
+        c0 = build_contacts(P, box, delta, u_nc, dt)
+        cap = int(capacity[k]) if capacity is not None else int(1.25 * c0.count) + 64
+        nnzc = (int(nnz_capacity[k]) if nnz_capacity is not None
+                else int(1.5 * c0.nnz) + 16 * (cap - c0.count) + 1024)
+        return cap, nnzc
+
+    def counts(self):
+        """Build mode: (contacts, nonzeros of M, build status) per instance for
+        the last solve; also sets ``contacts[k].count``."""
+        if not self.build:
+            raise RuntimeError("counts() needs a batch created with build=True")
+        n = max(1, self.count)
+        cnt = (ctypes.c_int32 * n)()
+        nnz = (ctypes.c_int64 * n)()
+        st = (ctypes.c_int32 * n)()
+        _check("sc_batch_contacts", A.lib().sc_batch_contacts(self._h, cnt, nnz, st, _stream()))
+        out = [(int(cnt[k]), int(nnz[k]), int(st[k])) for k in range(self.count)]
+        for con, (c, z, s) in zip(self.contacts, out):
+            con.count = c if s == A.SC_OK else 0
+            con.nnz = z
+        return out
 
     def solve(self):
         _check("sc_batch_solve", A.lib().sc_batch_solve(self._h, _stream()))

@@ -15,13 +15,18 @@
 // (same layout as the solve), dL/dq, V_w = Mob D w, the per-contact
 // geometric derivatives and their per-particle sums, with team barriers
 // between the steps. A reset kernel (no memset) precedes the persistent
-// kernel, so the pair can be captured in a HIP graph and replayed.
+// kernel, so the pair can be captured in a HIP graph and replayed. A batch
+// in build mode first builds every instance's contacts and M on the device
+// (sc_batch_build.hip); a finalize kernel then writes each instance's row
+// and slice counts into its descriptor and orders the queue, so that build,
+// solves and adjoints are one graph.
 #include <algorithm>
 #include <climits>
 #include <numeric>
 #include <vector>
 
 #include "sc_adjoint_dev.hpp"
+#include "sc_batch_build.hpp"
 #include "sc_chain.hpp"
 #include "sc_common.hpp"
 #include "sc_matrix.hpp"
@@ -95,6 +100,28 @@ __global__ void k_batch_reset(BatchCtl *ctl, TeamSync *ts, int nteams, SolveCtrl
             cg[k] = CgCtrl{};
             cg[k].status = SC_ERR_TIMEOUT;
         }
+    }
+}
+
+// After a build: each instance's row and slice counts into its descriptor
+// (none for an instance whose build failed) and the work order by nonzeros,
+// largest first, ties by index (the host's order for prebuilt batches).
+__global__ void k_batch_finalize(BatchDesc *items, const BuildOut *out, int *order, int count) {
+    for (int k = threadIdx.x; k < count; k += blockDim.x) {
+        const bool ok = out[k].status == SC_OK;
+        BatchDesc &d = items[k];
+        d.M.nc = ok ? out[k].nc : 0;
+        d.M.ns = ok ? out[k].ns : 0;
+        d.C.nc = d.M.nc;
+    }
+    for (int k = threadIdx.x; k < count; k += blockDim.x) {
+        const long long nk = out[k].status == SC_OK ? out[k].nnz : 0;
+        int r = 0;
+        for (int j = 0; j < count; ++j) {
+            const long long nj = out[j].status == SC_OK ? out[j].nnz : 0;
+            r += nj > nk || (nj == nk && j < k);
+        }
+        order[r] = k;
     }
 }
 
@@ -229,13 +256,18 @@ hipError_t batch_cache(const void *fn, int block, int *per_block, size_t *dyn) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(*dyn));
 }
 
-size_t rows(const sc_contacts &c) { return static_cast<size_t>(c.count > 0 ? c.count : 1); }
-size_t z_doubles(const sc_contacts &c) { return 4 * rows(c); }
+// rows an instance's solve buffers hold: its contacts, or in build mode its
+// capacity
+size_t rows(const sc_contacts &c, bool build) {
+    const int r = build ? c.capacity : c.count;
+    return static_cast<size_t>(r > 0 ? r : 1);
+}
+size_t z_doubles(const sc_contacts &c, bool build) { return 4 * rows(c, build); }
 // adjoint scratch per instance: F [n][6], U_c and V_w [n][8] each,
 // grad [nc][3], p, x [nc], two record arrays [nc][4]
-size_t adj_doubles(const sc_batch_item &it) {
+size_t adj_doubles(const sc_batch_item &it, bool build) {
     const size_t n = static_cast<size_t>(it.p.n > 0 ? it.p.n : 1);
-    return 22 * n + 13 * rows(it.c) + 8 * 256;
+    return 22 * n + 13 * rows(it.c, build) + 8 * 256;
 }
 
 }  // namespace
@@ -252,6 +284,11 @@ struct sc_batch {
     int team = 1, block = 1024, grid = 0;
     size_t dyn = 0;
     const void *fn = nullptr, *fn_adj = nullptr;
+    bool build = false;
+    BatchBuild bld;                    // build mode: tables and scratch
+    std::vector<BuildInst> bhost;
+    BatchDesc *descs = nullptr;        // device copies the finalize kernel updates
+    int *order = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     float tune_ms[6] = {0, 0, 0, 0, 0, 0};
@@ -259,24 +296,33 @@ struct sc_batch {
 
 namespace {
 
-size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nteams, bool adj) {
+size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nteams, bool adj,
+                      bool build) {
     const size_t nd = static_cast<size_t>(std::max(count, 1));
     size_t b = 0;
     b += align_up(sizeof(CgCtrl) * nd, 256);
     if (adj)
-        for (int32_t k = 0; k < count; ++k) b += 8 * 256 + sizeof(double) * adj_doubles(items[k]);
+        for (int32_t k = 0; k < count; ++k)
+            b += 8 * 256 + sizeof(double) * adj_doubles(items[k], build);
     b += align_up(2 * sizeof(BatchCtl), 256);
     b += align_up(2 * sizeof(TeamSync) * static_cast<size_t>(nteams), 256);
     b += align_up(sizeof(double) * 2 * kTeamPartHalf * static_cast<size_t>(nteams), 256);
     b += align_up(sizeof(BatchDesc) * nd, 256);
     b += align_up(sizeof(int) * nd, 256);
     b += align_up(sizeof(SolveCtrl) * nd, 256);
-    for (int32_t k = 0; k < count; ++k) b += align_up(sizeof(double) * z_doubles(items[k].c), 256);
+    for (int32_t k = 0; k < count; ++k)
+        b += align_up(sizeof(double) * z_doubles(items[k].c, build), 256);
+    if (build) b += batch_build_bytes(count, items);
     return b + 256;
 }
 
 int enqueue(sc_batch *b, hipStream_t s) {
     const int nteams = b->nteams_max;
+    if (b->build) {
+        const int rc = batch_build_enqueue(b->bld, s);
+        if (rc != SC_OK) return rc;
+        k_batch_finalize<<<1, 1024, 0, s>>>(b->descs, b->bld.out, b->order, b->count);
+    }
     k_batch_reset<<<1, 256, 0, s>>>(b->args.ctl, b->args.tsync, nteams, b->args.ctrl,
                                      b->args.adjoint ? b->args.cgctrl : nullptr, b->count);
     BatchArgs a = b->args;
@@ -297,13 +343,13 @@ int enqueue(sc_batch *b, hipStream_t s) {
 }  // namespace
 
 extern "C" size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *items,
-                                           int32_t adjoint) {
-    if (count < 0 || (count > 0 && !items)) return 0;
+                                           const sc_batch_opts *opts) {
+    if (count < 0 || (count > 0 && !items) || !opts) return 0;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 1024;
-    return batch_ws_bytes(count, items, std::max(cus, 1), adjoint != 0);
+    return batch_ws_bytes(count, items, std::max(cus, 1), opts->adjoint != 0, opts->build != 0);
 }
 
 extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const sc_batch_opts *opts,
@@ -314,20 +360,24 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
         !(opts->team == 0 || opts->team == 1 || opts->team == 2 || opts->team == 4 ||
           opts->team == 8 || opts->team == 16 || opts->team == 32) ||
         !block_ok(opts->block) || opts->adjoint < 0 || opts->adjoint > 2 ||
-        (opts->adjoint && (!(opts->adjoint_tol > 0.0) || opts->adjoint_max_iter < 0)))
+        (opts->adjoint && (!(opts->adjoint_tol > 0.0) || opts->adjoint_max_iter < 0)) ||
+        opts->build < 0 || opts->build > 1)
         return SC_ERR_INVALID;
     const bool adj = opts->adjoint != 0;
+    const bool build = opts->build != 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<BatchDesc> descs(static_cast<size_t>(count));
     std::vector<long long> nnz(static_cast<size_t>(count));
     for (int32_t k = 0; k < count; ++k) {
         const sc_contacts &c = items[k].c;
-        if (c.count < 0 || c.count > c.capacity || !c.mat_ready || !c.q ||
-            (c.count > 0 && (!items[k].gamma || !items[k].g)))
+        const int rows_k = build ? c.capacity : c.count;
+        if (build ? (c.capacity < 0 || c.nnz < 0)
+                  : (c.count < 0 || c.count > c.capacity || !c.mat_ready))
             return SC_ERR_INVALID;
+        if (!c.q || (rows_k > 0 && (!items[k].gamma || !items[k].g))) return SC_ERR_INVALID;
         MatBufs mb{};
-        if (!carve_matrix(c.mat, c.mat_bytes, c.count, c.nnz, mb)) return SC_ERR_INVALID;
-        descs[k].M = mat_view(c.count, mb);
+        if (!carve_matrix(c.mat, c.mat_bytes, rows_k, c.nnz, mb)) return SC_ERR_INVALID;
+        descs[k].M = mat_view(build ? 0 : c.count, mb);
         if (adj) {
             const sc_batch_item &it = items[k];
             Plan pl;
@@ -335,12 +385,12 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
                 !(it.dt > 0.0) ||
                 (it.p.n > 0 && (!it.u_nc || !it.dL_dpos || !it.p.pos || !it.p.axis ||
                                 !it.p.half_len)) ||
-                (c.count > 0 && (!it.dL_dq || !c.ci || !c.cj || !c.frame)))
+                (rows_k > 0 && (!it.dL_dq || !c.ci || !c.cj || !c.frame)))
                 return SC_ERR_INVALID;
             BatchDesc &d = descs[k];
             d.pl = pl;
-            d.C = ChainView{it.p.n, c.count, pl.pdat, pl.inc_ptr, pl.inc, pl.dpm, pl.cs, c.frame,
-                            nullptr};
+            d.C = ChainView{it.p.n, build ? 0 : c.count, pl.pdat, pl.inc_ptr, pl.inc, pl.dpm,
+                            pl.cs, c.frame, nullptr};
             d.box = PBox{{it.box.len[0], it.box.len[1], it.box.len[2]}, it.box.periodic ? 1 : 0};
             d.ci = c.ci;
             d.cj = c.cj;
@@ -360,6 +410,7 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     }
     auto *b = new sc_batch;
     b->count = count;
+    b->build = build;
     b->block = opts->block ? opts->block : 1024;
     b->fn = reinterpret_cast<const void *>(batch_kernel<0>(b->block));
     b->fn_adj = reinterpret_cast<const void *>(batch_kernel<1>(b->block));
@@ -383,7 +434,7 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
         return SC_ERR_HIP;
     }
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 ||
-        ws_bytes < batch_ws_bytes(count, items, b->nteams_max, adj)) {
+        ws_bytes < batch_ws_bytes(count, items, b->nteams_max, adj, build)) {
         delete b;
         return SC_ERR_WORKSPACE;
     }
@@ -397,13 +448,13 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     a.ctrl = cv.take<SolveCtrl>(static_cast<size_t>(std::max(count, 1)));
     a.cgctrl = cv.take<CgCtrl>(static_cast<size_t>(std::max(count, 1)));
     for (int32_t k = 0; k < count; ++k) {
-        GG *z = reinterpret_cast<GG *>(cv.take<double>(z_doubles(items[k].c)));
+        GG *z = reinterpret_cast<GG *>(cv.take<double>(z_doubles(items[k].c, build)));
         descs[k].z0 = z;
-        descs[k].z1 = z + std::max(items[k].c.count, 1);
+        descs[k].z1 = z + rows(items[k].c, build);
         b->counts.push_back(items[k].c.count);
         if (adj) {
             const size_t n = static_cast<size_t>(std::max(items[k].p.n, 1));
-            const size_t nc = rows(items[k].c);
+            const size_t nc = rows(items[k].c, build);
             BatchDesc &d = descs[k];
             d.F = cv.take<double>(6 * n);
             d.C.U = cv.take<double>(8 * n);
@@ -419,6 +470,15 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
         delete b;
         return SC_ERR_WORKSPACE;
     }
+    if (build) {
+        const int rc = batch_build_plan(count, items, cv, s, b->bld, b->bhost);
+        if (rc != SC_OK) {
+            delete b;
+            return rc == SC_ERR_INVALID && !cv.ok ? SC_ERR_WORKSPACE : rc;
+        }
+    }
+    b->descs = d_descs;
+    b->order = d_order;
     std::vector<int> order(static_cast<size_t>(count));
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nnz[x] > nnz[y]; });
@@ -578,7 +638,19 @@ extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_stats *adj,
     if (adj && b->args.adjoint)
         SC_HIP_TRY(hipMemcpyAsync(hc.data(), b->args.cgctrl, sizeof(CgCtrl) * b->count,
                                   hipMemcpyDeviceToHost, s));
+    std::vector<BuildOut> ho(static_cast<size_t>(b->build ? b->count : 0));
+    if (b->build)
+        SC_HIP_TRY(hipMemcpyAsync(ho.data(), b->bld.out, sizeof(BuildOut) * b->count,
+                                  hipMemcpyDeviceToHost, s));
     SC_HIP_TRY(hipStreamSynchronize(s));
+    // an instance whose build failed reports the build's status
+    for (int k = 0; k < static_cast<int>(ho.size()); ++k)
+        if (ho[k].status != SC_OK) {
+            h[k] = SolveCtrl{};
+            h[k].status = ho[k].status;
+            hc[k] = CgCtrl{};
+            hc[k].status = ho[k].status;
+        }
     if (adj) {
         for (int k = 0; k < b->count; ++k) {
             adj[k] = sc_stats{};
@@ -608,6 +680,23 @@ extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_stats *adj,
         st.slices_per_wave = 1;
         st.lds_entries_per_wave = b->args.cache / (b->block / kWave);
         st.n_active = -1;
+    }
+    return SC_OK;
+}
+
+extern "C" int sc_batch_contacts(const sc_batch *b, int32_t *count, int64_t *nnz,
+                                 int32_t *status, void *stream) {
+    if (!b || !b->build) return SC_ERR_INVALID;
+    if (b->count == 0) return SC_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<BuildOut> ho(static_cast<size_t>(b->count));
+    SC_HIP_TRY(hipMemcpyAsync(ho.data(), b->bld.out, sizeof(BuildOut) * b->count,
+                              hipMemcpyDeviceToHost, s));
+    SC_HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < b->count; ++k) {
+        if (count) count[k] = ho[k].nc;
+        if (nnz) nnz[k] = ho[k].nnz;
+        if (status) status[k] = ho[k].status;
     }
     return SC_OK;
 }
