@@ -72,6 +72,29 @@ def large(sc, W, torch, np):
             "frac": achieved / HBM_PEAK_GBS, "rods_per_s": s.n / (kernel_ms * 1e-3)}
 
 
+def timestepping(sc, W, torch, np, steps):
+    """Euler time steps (contacts rebuilt, LCP solved, centres and
+    quaternions advanced) of the 100,000-rod suspension, with and without
+    warm-starting each LCP from the previous step's forces."""
+    from paper_1909_06623_amd import timestep as ts
+    out = {"steps": steps}
+    for warm in (True, False):
+        s = W.workload(2)
+        P = sc.Particles.from_suspension(s)
+        stp = ts.TimeStepper(P, sc.Box(tuple(s.box)), s.delta, s.dt,
+                             torch.from_numpy(s.f_ext).cuda(), tol=s.tol, warm_start=warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [stp.step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        key = "warm" if warm else "cold"
+        out[key] = {"ms_per_step": ms, "iters": [x.stats["iters"] for x in infos],
+                    "contacts": [x.contacts.count for x in infos],
+                    "all_converged": all(x.stats["status"] == 0 for x in infos)}
+    return out
+
+
 def operator_bytes(nc, nnz):
     """Bytes the assembled-M product itself streams per iteration: each
     nonzero's column and value (12), and per row its length (4), q (8) and
@@ -202,6 +225,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--no-timestep", action="store_true")
+    ap.add_argument("--timestep-steps", type=int, default=8)
     ap.add_argument("--large", action="store_true",
                     help="also time the 1.1M-particle forward solve")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -299,6 +324,7 @@ def main():
 
     batch = None if args.no_batch else batched(sc, W, torch, np, args.batch_count)
     big = large(sc, W, torch, np) if args.large else None
+    tsl = None if args.no_timestep else timestepping(sc, W, torch, np, args.timestep_steps)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -360,6 +386,7 @@ def main():
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],
         "batched": batch,
         "large": big,
+        "timestep": tsl,
     }
     print(json.dumps(line), flush=True)
 

@@ -360,6 +360,36 @@ int sc_batch_contacts(const sc_batch *b, int32_t *count, int64_t *nnz, int32_t *
 
 void sc_batch_destroy(sc_batch *b);
 
+/* ------------------------------------------------------- time stepping */
+
+/* One first-order Euler step of the configuration (section 3.2, Eq.
+ * time-step; orientation kinematics of section 2): with U = u_nc + u_c per
+ * particle ([n][6] each, u_c may be NULL = 0),
+ *   c     += dt U[0:3]
+ *   theta += dt Psi(theta) U[3:6],  Psi = 1/2 [-p^T; s I - [p]x]
+ * for the unit quaternion theta = (s, p) ([n][4], s first), which is then
+ * normalised (reading: the paper's update leaves the norm free), and
+ * axis = R(theta) e_z ([n][3], written for every particle). pos, quat and
+ * axis are device arrays updated in place. Enqueues only. SC_ERR_INVALID on
+ * n < 0, dt <= 0 or a missing array. */
+int sc_advance(int32_t n, double *pos, double *quat, double *axis, const double *u_nc,
+               const double *u_c, double dt, void *stream);
+
+/* quat [n][4] = the unit quaternion of the shortest rotation taking e_z to
+ * the unit axis [n][3] (the half turn about x for axis = -e_z), the state
+ * sc_advance starts from. Enqueues only. */
+int sc_quat_from_axis(int32_t n, const double *axis, double *quat, void *stream);
+
+/* Warm start of a step's LCP (the previous step's collision forces as
+ * gamma_0 of Algorithm 1): gamma0[l] for each contact l = (i, j) of `cur` is
+ * gamma_prev of the same pair in `prev` (the previous step's contacts of the
+ * same n particles, from sc_build_contacts), or 0 if the pair is new. Pairs
+ * are matched through prev's incidence lists, so the cost is the degree of
+ * i per contact. All arrays device; gamma_prev [prev->count], gamma0
+ * [cur->count]. Enqueues only. */
+int sc_map_gamma(int32_t n, const sc_contacts *prev, const double *gamma_prev,
+                 const sc_contacts *cur, double *gamma0, void *stream);
+
 /* Static string describing a return code. */
 const char *sc_strerror(int code);
 

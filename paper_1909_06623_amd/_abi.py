@@ -127,6 +127,11 @@ SIGNATURES = {
     "sc_batch_contacts": (ctypes.c_int, [c_dp, P(ctypes.c_int32), P(ctypes.c_int64),
                                          P(ctypes.c_int32), c_dp]),
     "sc_batch_destroy": (None, [c_dp]),
+    "sc_advance": (ctypes.c_int, [ctypes.c_int32, c_dp, c_dp, c_dp, c_dp, c_dp,
+                                  ctypes.c_double, c_dp]),
+    "sc_quat_from_axis": (ctypes.c_int, [ctypes.c_int32, c_dp, c_dp, c_dp]),
+    "sc_map_gamma": (ctypes.c_int, [ctypes.c_int32, P(sc_contacts), c_dp, P(sc_contacts),
+                                    c_dp, c_dp]),
     "sc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sc_version": (ctypes.c_int, []),
 }
