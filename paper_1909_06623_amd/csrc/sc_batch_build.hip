@@ -126,7 +126,7 @@ __global__ void kb_count_pairs(BatchBuild B) {
     if (input_bad(B.out[k])) return;
     const BuildInst &I = B.inst[k];
     count_partners(x - I.pbase, lane, ranked_of(B, I), I.pl, I.g, B.cell_start + I.cbase,
-                   I.pbase, B.lane_cnt + gid, B.out[k].flags);
+                   I.pbase, B.lane_cnt + gid, B.slots + kLaneSlots * gid, B.out[k].flags);
 }
 
 // After the scan of the per-rank counts: the contact count and the status.
@@ -155,7 +155,7 @@ __global__ void kb_write_pairs(BatchBuild B) {
     if (B.out[k].status != SC_OK) return;
     const BuildInst &I = B.inst[k];
     write_partners(x - I.pbase, lane, ranked_of(B, I), I.pl, I.g, B.cell_start + I.cbase,
-                   I.pbase, B.lane_cnt + (gid - lane));
+                   I.pbase, B.lane_cnt + (gid - lane), B.slots + kLaneSlots * gid);
 }
 
 __global__ void kb_finish_pairs(BatchBuild B) {
@@ -331,6 +331,7 @@ size_t batch_build_bytes(int32_t count, const sc_batch_item *items) {
     const size_t nn = std::max<size_t>(n, 1);
     b += 6 * align_up(sizeof(int) * nn, 256);                  // cell_of .. fill, spare
     b += align_up(sizeof(int) * kPairLanes * nn, 256);         // per-lane pair counts
+    b += align_up(sizeof(int) * kLaneSlots * kPairLanes * nn, 256);  // per-lane partners
     b += align_up(sizeof(double) * 4 * nn, 256) + align_up(sizeof(double) * nn, 256);
     b += 2 * align_up(sizeof(int) * (cells + 1), 256);
     b += align_up(sizeof(int) * scan_tmp_ints(static_cast<int>(cells + 1)), 256);
@@ -398,6 +399,7 @@ int batch_build_plan(int32_t count, const sc_batch_item *items, Carver &cv, hipS
     b.fill = cv.take<int>(n);
     cv.take<int>(n);  // spare (keeps the layout of batch_build_bytes)
     b.lane_cnt = cv.take<int>(kPairLanes * n);
+    b.slots = cv.take<int>(static_cast<size_t>(kLaneSlots) * kPairLanes * n);
     b.prec = cv.take<double>(4 * n);
     b.hl = cv.take<double>(n);
     b.cell_start = cv.take<int>(cells_budget + 1);

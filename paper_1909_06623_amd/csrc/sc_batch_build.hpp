@@ -51,8 +51,8 @@ struct BatchBuild {
     BuildOut *out = nullptr;          // [count]
     int *pbase = nullptr, *lbase = nullptr, *sbase = nullptr;  // [count + 1] each
     int *cell_of = nullptr, *members = nullptr, *cell_r = nullptr, *deg = nullptr,
-        *fill = nullptr, *lane_cnt = nullptr, *cell_start = nullptr, *cell_fill = nullptr,
-        *scan_tmp = nullptr;
+        *fill = nullptr, *lane_cnt = nullptr, *slots = nullptr, *cell_start = nullptr,
+        *cell_fill = nullptr, *scan_tmp = nullptr;
     double *prec = nullptr, *hl = nullptr;
     unsigned long long *ext_bits = nullptr;  // [count], used when planning
 };

@@ -149,6 +149,9 @@ __device__ __forceinline__ PairGeo ranked_geo(int a, int b, const Ranked &R, con
 // Lanes that share one particle's 27-cell stencil in the pair search (lane j
 // takes the neighbour cells whose index in (z, y, x) order is j modulo this).
 constexpr int kPairLanes = 8;
+// Partners each lane keeps from the count pass (a lane with more is searched
+// again by the write pass).
+constexpr int kLaneSlots = 8;
 
 // Visit every partner u > t (by local rank) of rank t whose pair has
 // Phi <= delta among the neighbour cells of lane `lane`'s share, calling
@@ -198,14 +201,16 @@ __device__ __forceinline__ void for_close_partners(int t, int lane, const Ranked
     }
 }
 
-// Count pass of lane `lane` of rank t: its partners go to lane_cnt[0], the
-// rank's total (over the kPairLanes lanes, which must be consecutive
+// Count pass of lane `lane` of rank t: the number of its partners goes to
+// lane_cnt[0] and the first kLaneSlots of them (in search order) to slots,
+// the rank's total (over the kPairLanes lanes, which must be consecutive
 // threads) to cptr[t]; diagnostic counts to flags.
 __device__ __forceinline__ void count_partners(int t, int lane, const Ranked &R, const Plan &pl,
                                                const Grid &g, const int *cstart, int rbase,
-                                               int *lane_cnt, int *flags) {
+                                               int *lane_cnt, int *slots, int *flags) {
     int cnt = 0, npar = 0, nzero = 0, nborder = 0;
-    for_close_partners(t, lane, R, pl, g, cstart, rbase, [&](int, const PairGeo &G) {
+    for_close_partners(t, lane, R, pl, g, cstart, rbase, [&](int u, const PairGeo &G) {
+        if (cnt < kLaneSlots) slots[cnt] = u;
         ++cnt;
         npar += G.flags & 1;
         nzero += (G.flags >> 1) & 1;
@@ -222,14 +227,20 @@ __device__ __forceinline__ void count_partners(int t, int lane, const Ranked &R,
 }
 
 // Write pass: lane `lane` of rank t stores its partners' ranks (even slots of
-// cs) after those of the rank's lower lanes. lane_cnt points at lane 0's count.
+// cs) after those of the rank's lower lanes, from the count pass's slots, or
+// by searching again if it had more than kLaneSlots. lane_cnt points at lane
+// 0's count, slots at this lane's slots.
 __device__ __forceinline__ void write_partners(int t, int lane, const Ranked &R, const Plan &pl,
                                                const Grid &g, const int *cstart, int rbase,
-                                               const int *lane_cnt) {
+                                               const int *lane_cnt, const int *slots) {
     const int lim = lane_cnt[lane];
     int before = 0;
     for (int j = 0; j < lane; ++j) before += lane_cnt[j];
     int *part = pl.cs + 2 * static_cast<long long>(pl.cptr[t] + before);
+    if (lim <= kLaneSlots) {
+        for (int k = 0; k < lim; ++k) part[2 * k] = slots[k];
+        return;
+    }
     int k = 0;
     // the count pass used the same pure predicate, so k ends at lim; the
     // bound only guards the segment

@@ -64,19 +64,21 @@ __global__ void k_rank(Parts P, const int *cell_of, const int *cell_start, const
 // Count pass: kPairLanes consecutive threads per rank; per-lane counts go to
 // lane_cnt, the rank's total to cptr.
 __global__ void k_count_pairs(int n, Ranked R, Plan pl, Grid g, const int *cell_start,
-                              int *lane_cnt, int *flags) {
+                              int *lane_cnt, int *slots, int *flags) {
     const long long gid = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int t = static_cast<int>(gid / kPairLanes), lane = static_cast<int>(gid % kPairLanes);
     if (t >= n) return;  // whole groups of kPairLanes leave together
-    count_partners(t, lane, R, pl, g, cell_start, 0, lane_cnt + gid, flags);
+    count_partners(t, lane, R, pl, g, cell_start, 0, lane_cnt + gid, slots + kLaneSlots * gid,
+                   flags);
 }
 
 __global__ void k_write_pairs(int n, Ranked R, Plan pl, Grid g, const int *cell_start,
-                              const int *lane_cnt) {
+                              const int *lane_cnt, const int *slots) {
     const long long gid = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int t = static_cast<int>(gid / kPairLanes), lane = static_cast<int>(gid % kPairLanes);
     if (t >= n) return;
-    write_partners(t, lane, R, pl, g, cell_start, 0, lane_cnt + (gid - lane));
+    write_partners(t, lane, R, pl, g, cell_start, 0, lane_cnt + (gid - lane),
+                   slots + kLaneSlots * gid);
 }
 
 __global__ void k_finish_pairs(int n, Ranked R, Plan pl, Grid g, int *ci, int *cj, double *phi,
@@ -149,6 +151,7 @@ size_t contacts_ws_bytes(int32_t n, int32_t cap) {
     b += align_up(kFlagCount * sizeof(int), 256) + 256;     // flags, max extent
     b += 5 * align_up(nn * sizeof(int), 256);                // cell_of, members, cell_r, deg, fill
     b += align_up(kPairLanes * nn * sizeof(int), 256);       // per-lane pair counts
+    b += align_up(kLaneSlots * kPairLanes * nn * sizeof(int), 256);  // per-lane partners
     b += align_up(4 * nn * sizeof(double), 256);             // ranked centre + radius
     b += align_up(nn * sizeof(double), 256);                 // ranked half length
     b += 2 * align_up((nb + 1) * sizeof(int), 256);          // cell_start, cell_fill
@@ -207,6 +210,7 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     int *deg = cv.take<int>(n);
     int *fill = cv.take<int>(n);
     int *lane_cnt = cv.take<int>(static_cast<size_t>(kPairLanes) * n);
+    int *slots = cv.take<int>(static_cast<size_t>(kLaneSlots) * kPairLanes * n);
     double *prec = cv.take<double>(4 * static_cast<size_t>(n));
     double *hl = cv.take<double>(n);
     int *cell_start = cv.take<int>(nb + 1);
@@ -250,7 +254,8 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
 
     // partners of higher rank, then offsets
     const int pair_blocks = grid_for(static_cast<long long>(n) * kPairLanes);
-    k_count_pairs<<<pair_blocks, kBlock, 0, stream>>>(n, R, pl, g, cell_start, lane_cnt, flags);
+    k_count_pairs<<<pair_blocks, kBlock, 0, stream>>>(n, R, pl, g, cell_start, lane_cnt, slots,
+                                                      flags);
     scan_exclusive(pl.cptr, pl.cptr, n, scan_tmp, stream);
     SC_HIP_TRY(hipMemcpyAsync(stage, pl.cptr + n, sizeof(int), hipMemcpyDeviceToDevice, stream));
     SC_HIP_TRY(hipMemcpyAsync(stage + 1, flags, kFlagCount * sizeof(int), hipMemcpyDeviceToDevice,
@@ -265,7 +270,7 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     c->n_borderline = hstage[1 + kFlagBorder];
     if (nc > c->capacity) return SC_ERR_CAPACITY;
 
-    k_write_pairs<<<pair_blocks, kBlock, 0, stream>>>(n, R, pl, g, cell_start, lane_cnt);
+    k_write_pairs<<<pair_blocks, kBlock, 0, stream>>>(n, R, pl, g, cell_start, lane_cnt, slots);
     k_finish_pairs<<<grid_for(n), kBlock, 0, stream>>>(n, R, pl, g, c->ci, c->cj, c->phi,
                                                        c->frame);
     // incidence lists and signed column entries
