@@ -138,7 +138,10 @@ typedef struct sc_solve_opts {
     int32_t lds_entries_per_wave; /* assembled-M product: entries of M each wave keeps in
                                 LDS for the whole solve; 0 = as many as fit, -1 = none,
                                 > 0 = at most that many */
-    int32_t reserved;
+    int32_t spin_limit;     /* 0: a wait at a grid barrier gives up after 2^21 polls
+                               (SC_ERR_TIMEOUT, every workgroup leaves its loop);
+                               > 0: after this many (a small value forces the timeout
+                               path, for tests of it) */
 } sc_solve_opts;
 
 typedef struct sc_stats {

@@ -53,7 +53,7 @@ class sc_solve_opts(ctypes.Structure):
                 ("lanes_per_particle", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("op", ctypes.c_int32),
                 ("slices_per_wave", ctypes.c_int32), ("lds_entries_per_wave", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("spin_limit", ctypes.c_int32)]
 
 
 class sc_stats(ctypes.Structure):

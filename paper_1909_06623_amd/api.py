@@ -266,9 +266,10 @@ def solve_lcp(particles: Particles, contacts: Contacts, tol: float = 1e-6,
               want_fc: bool = False, lanes_per_particle: int = 0, grid: int = 0,
               block: int = 0, op: int = 0, workspace: Optional[Workspace] = None,
               raise_on_nonconverged=False, slices_per_wave: int = 0,
-              lds_entries_per_wave: int = 0):
+              lds_entries_per_wave: int = 0, spin_limit: int = 0):
     """BBPGD (Algorithm 1). Returns (gamma, g, stats dict, f_c, u_c); f_c and
-    u_c are None unless want_fc."""
+    u_c are None unless want_fc. ``spin_limit`` > 0 caps every barrier wait
+    at that many polls (forces the SC_ERR_TIMEOUT path, for tests)."""
     nc = contacts.count
     gamma = torch.zeros(max(1, nc), dtype=torch.float64, device="cuda")
     if gamma0 is not None and nc:
@@ -280,7 +281,7 @@ def solve_lcp(particles: Particles, contacts: Contacts, tol: float = 1e-6,
         u_c = torch.empty((particles.n, 6), dtype=torch.float64, device="cuda")
     opts = A.sc_solve_opts(float(tol), int(max_iter), int(bb), 1 if gamma0 is not None else 0,
                            int(lanes_per_particle), int(grid), int(block), int(op),
-                           int(slices_per_wave), int(lds_entries_per_wave), 0)
+                           int(slices_per_wave), int(lds_entries_per_wave), int(spin_limit))
     st = A.sc_stats()
     ws = workspace or default_workspace()
     wsp, wsn = ws.get(particles.n, contacts.capacity)

@@ -398,7 +398,7 @@ extern "C" int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
     if (!opts || !st) return SC_ERR_INVALID;
     if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->bb < 1 || opts->bb > 3 ||
         !lanes_ok(opts->lanes_per_particle) || !spw_ok(opts->slices_per_wave) ||
-        opts->lds_entries_per_wave < -1 || opts->grid < 0 ||
+        opts->lds_entries_per_wave < -1 || opts->grid < 0 || opts->spin_limit < 0 ||
         !block_ok(opts->block) || opts->op < 0 ||
         opts->op > SC_OP_MATRIX || (opts->op == SC_OP_MATRIX && !c->mat_ready))
         return SC_ERR_INVALID;
@@ -455,6 +455,9 @@ extern "C" int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
 
     if (!opts->warm_start) SC_HIP_TRY(hipMemsetAsync(gamma, 0, sizeof(double) * nc, s));
     SC_HIP_TRY(hipMemsetAsync(sync, 0, sizeof(GridSync), s));
+    if (opts->spin_limit > 0)
+        SC_HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(&sync->limit[0]),
+                                     opts->spin_limit, 1, s));
     SC_HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), s));
     void *args[] = {&A};
     SC_HIP_TRY(hipEventRecord(tm.t0, s));

@@ -32,6 +32,7 @@ struct alignas(256) GridSync {
     unsigned gen[32];            // global generation
     unsigned init[32];           // start-up arrivals
     unsigned err[32];            // timeout flag
+    unsigned limit[32];          // polls before a wait gives up (0: 2^21)
 };
 
 __device__ __forceinline__ unsigned xcc_id() {
@@ -46,8 +47,10 @@ __device__ __forceinline__ unsigned ld_relaxed(const unsigned *p) {
 // Returns false on timeout (the flag is raised for everybody).
 __device__ __forceinline__ bool spin_until(unsigned *word, unsigned target, GridSync *s) {
     unsigned polls = 0;
+    const unsigned lim = ld_relaxed(&s->limit[0]);
+    const unsigned cap = lim ? lim : (1u << 21);
     while (ld_relaxed(word) != target) {
-        if (++polls > (1u << 21)) {
+        if (++polls > cap) {
             __hip_atomic_fetch_or(&s->err[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }

@@ -72,7 +72,8 @@ def test_invalid_arguments_rejected_without_device_work():
     assert L.sc_solve_lcp(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(bad), None, None,
                           None, None, ctypes.byref(st), None, 0, None) == A.SC_ERR_INVALID
     for field, value in (("slices_per_wave", 3), ("lds_entries_per_wave", -2),
-                         ("lanes_per_particle", 16), ("block", 768), ("op", 3)):
+                         ("lanes_per_particle", 16), ("block", 768), ("op", 3),
+                         ("spin_limit", -1)):
         bad = A.sc_solve_opts(1e-6, 100, 1, 0, 0)
         setattr(bad, field, value)
         assert L.sc_solve_lcp(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(bad), None, None,
@@ -80,6 +81,15 @@ def test_invalid_arguments_rejected_without_device_work():
     box = A.sc_box()
     assert L.sc_build_contacts(ctypes.byref(p0), ctypes.byref(box), 0.1, None, 1e-3,
                                ctypes.byref(c), None, 0, None) == A.SC_ERR_INVALID
+    # time stepping and batch queries reject bad arguments before any launch
+    assert L.sc_advance(-1, None, None, None, None, None, 0.1, None) == A.SC_ERR_INVALID
+    assert L.sc_advance(4, None, None, None, None, None, 0.0, None) == A.SC_ERR_INVALID
+    assert L.sc_advance(4, None, None, None, None, None, 0.1, None) == A.SC_ERR_INVALID
+    assert L.sc_advance(0, None, None, None, None, None, 0.1, None) == A.SC_OK
+    assert L.sc_quat_from_axis(-1, None, None, None) == A.SC_ERR_INVALID
+    assert L.sc_map_gamma(3, None, None, None, None, None) == A.SC_ERR_INVALID
+    assert L.sc_batch_contacts(None, None, None, None, None) == A.SC_ERR_INVALID
+    assert L.sc_batch_workspace_bytes(1, None, None) == 0
 
 
 def test_product_path_has_no_cpu_fallback():
@@ -88,7 +98,9 @@ def test_product_path_has_no_cpu_fallback():
     import paper_1909_06623_amd._abi as A
     import paper_1909_06623_amd.api as api
     import paper_1909_06623_amd.autograd as AG
-    src = open(api.__file__).read() + open(A.__file__).read() + open(AG.__file__).read()
+    import paper_1909_06623_amd.timestep as TS
+    src = (open(api.__file__).read() + open(A.__file__).read() + open(AG.__file__).read()
+           + open(TS.__file__).read())
     assert "oracle" not in src.replace("oracle.", "")
     saved = A._lib, A.LIB_PATH
     try:
