@@ -154,13 +154,18 @@ constexpr int kPairLanes = 8;
 constexpr int kLaneSlots = 8;
 
 // Visit every partner u > t (by local rank) of rank t whose pair has
-// Phi <= delta among the neighbour cells of lane `lane`'s share, calling
-// fn(u, geo). cstart: the suspension's cell starts (shared ranks), rbase
-// subtracted to make them local.
+// Phi <= delta, calling fn(u, geo). The candidates are the ranks of the 27
+// neighbour cells: per (y, z) row the x-neighbours are merged into runs of
+// consecutive cells, which are consecutive ranks (cells are row-major), and
+// the kPairLanes lanes of rank t take every kPairLanes-th candidate of the
+// runs laid end to end, so the lanes share the work evenly and neighbouring
+// lanes read neighbouring records. cstart: the suspension's cell starts
+// (shared ranks), rbase subtracted to make them local.
 template <class Fn>
 __device__ __forceinline__ void for_close_partners(int t, int lane, const Ranked &R,
                                                    const Plan &pl, const Grid &g,
                                                    const int *cstart, int rbase, Fn fn) {
+    static_assert((kPairLanes & (kPairLanes - 1)) == 0, "lanes per rank: a power of two");
     const double *pt = R.prec + 4 * static_cast<long long>(t);
     const V3 ct = v3(pt[0], pt[1], pt[2]);
     const double Rt = pt[3], ht = R.hl[t];
@@ -169,36 +174,59 @@ __device__ __forceinline__ void for_close_partners(int t, int lane, const Ranked
     int nx[3], ny[3], nz[3];
     const int kx = neighbours(cx, 0, g, nx), ky = neighbours(cy, 1, g, ny),
               kz = neighbours(cz, 2, g, nz);
+    // x-neighbours in increasing order, as runs [x0, x1) of consecutive cells
+    for (int a = 1; a < kx; ++a)
+        for (int b = a; b > 0 && nx[b - 1] > nx[b]; --b) {
+            const int tmp = nx[b];
+            nx[b] = nx[b - 1];
+            nx[b - 1] = tmp;
+        }
+    int rx0[3], rx1[3], nrun = 0;
+    for (int a = 0; a < kx; ++a) {
+        if (nrun > 0 && rx1[nrun - 1] == nx[a]) {
+            rx1[nrun - 1] = nx[a] + 1;
+        } else {
+            rx0[nrun] = nx[a];
+            rx1[nrun] = nx[a] + 1;
+            ++nrun;
+        }
+    }
     const PBox box = g.box();
     const double *at = pl.pdat + 8 * static_cast<long long>(t);
     const V3 pt_ax = v3(at[0], at[1], at[2]);
-    for (int idx = lane; idx < kx * ky * kz; idx += kPairLanes) {
-        const int ax = idx % kx, ay = (idx / kx) % ky, az = idx / (kx * ky);
-        const int cc = (nz[az] * g.nc[1] + ny[ay]) * g.nc[0] + nx[ax];
-        int u = cstart[cc] - rbase;
-        const int end = cstart[cc + 1] - rbase;
-        if (u <= t) u = t + 1;
-        for (; u < end; ++u) {
-            const double *pu = R.prec + 4 * static_cast<long long>(u);
-            const V3 r = min_image(ct, v3(pu[0], pu[1], pu[2]), box);
-            // the core distance is at least |r| - ht - hu
-            const double hu = R.hl[u];
-            const double reach = ht + hu + Rt + pu[3] + g.delta;
-            if (dot(r, r) > reach * reach * (1.0 + 1e-9)) continue;
-            if (ht > 0.0 && hu > 0.0) {
-                // two segments are no closer than their lines: skip pairs whose
-                // lines are farther apart than R_t + R_u + delta (near-parallel
-                // axes give w ~ 0 and fall through to the exact test)
-                const double *au = pl.pdat + 8 * static_cast<long long>(u);
-                const V3 w = cross(pt_ax, v3(au[0], au[1], au[2]));
-                const double rw = dot(r, w), lim = Rt + pu[3] + g.delta;
-                if (rw * rw > lim * lim * dot(w, w) * (1.0 + 1e-9)) continue;
+    int seen = 0;  // candidates in the runs before the current one
+    for (int az = 0; az < kz; ++az)
+        for (int ay = 0; ay < ky; ++ay) {
+            const int row = (nz[az] * g.nc[1] + ny[ay]) * g.nc[0];
+            for (int q = 0; q < nrun; ++q) {
+                int u0 = cstart[row + rx0[q]] - rbase;
+                const int end = cstart[row + rx1[q]] - rbase;
+                if (u0 <= t) u0 = t + 1;
+                if (end <= u0) continue;
+                for (int u = u0 + ((lane - seen) & (kPairLanes - 1)); u < end; u += kPairLanes) {
+                    const double *pu = R.prec + 4 * static_cast<long long>(u);
+                    const V3 r = min_image(ct, v3(pu[0], pu[1], pu[2]), box);
+                    // the core distance is at least |r| - ht - hu
+                    const double hu = R.hl[u];
+                    const double reach = ht + hu + Rt + pu[3] + g.delta;
+                    if (dot(r, r) > reach * reach * (1.0 + 1e-9)) continue;
+                    if (ht > 0.0 && hu > 0.0) {
+                        // two segments are no closer than their lines: skip pairs
+                        // whose lines are farther apart than R_t + R_u + delta
+                        // (near-parallel axes give w ~ 0 and fall through to the
+                        // exact test)
+                        const double *au = pl.pdat + 8 * static_cast<long long>(u);
+                        const V3 w = cross(pt_ax, v3(au[0], au[1], au[2]));
+                        const double rw = dot(r, w), lim = Rt + pu[3] + g.delta;
+                        if (rw * rw > lim * lim * dot(w, w) * (1.0 + 1e-9)) continue;
+                    }
+                    bool t_is_i;
+                    const PairGeo G = ranked_geo(t, u, R, pl, box, t_is_i);
+                    if (G.phi <= g.delta) fn(u, G);
+                }
+                seen += end - u0;
             }
-            bool t_is_i;
-            const PairGeo G = ranked_geo(t, u, R, pl, box, t_is_i);
-            if (G.phi <= g.delta) fn(u, G);
         }
-    }
 }
 
 // Count pass of lane `lane` of rank t: the number of its partners goes to
