@@ -48,7 +48,8 @@ def _load():
                                       _dp, ctypes.c_int, _dp]
     lib.orc_find_contacts.restype = ctypes.c_long
     lib.orc_find_contacts.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp,
-                                      _dp, _dp, _dp, ctypes.c_int, ctypes.c_double,
+                                      _dp, _dp, _dp, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_double,
                                       ctypes.c_long, _ip, _ip, _dp, _dp, _dp, _dp,
                                       _dp, _lp]
     lib.orc_mobility.restype = None
@@ -161,7 +162,7 @@ def find_contacts(s, method="cells", delta=None):
         fl = np.zeros(2, dtype=np.int64)
         cnt = lib.orc_find_contacts(
             m, s.n, _d(pos), _d(axis), _d(rad), _d(hl), _d(lo), _d(box),
-            int(s.periodic), delta, cap, ci.ctypes.data_as(_ip),
+            int(s.periodic), int(getattr(s, "walls", 0)), delta, cap, ci.ctypes.data_as(_ip),
             cj.ctypes.data_as(_ip), _d(phi), _d(nrm), _d(ti), _d(tj), _d(st),
             fl.ctypes.data_as(_lp))
         if cnt <= cap:
@@ -258,7 +259,9 @@ def D_matrix(n, c):
         vals[:, 6 + a] = c.nrm[:, a]
         vals[:, 9 + a] = c.tau_j[:, a]
     cols = np.repeat(np.arange(nc), 12)
-    return sp.csc_matrix((vals.ravel(), (rows.ravel(), cols)), shape=(6 * n, nc))
+    keep = np.ones((nc, 12), bool)
+    keep[c.j < 0, 6:] = False   # a wall contact has the particle's entries only
+    return sp.csc_matrix((vals[keep], (rows[keep], cols[keep.ravel()])), shape=(6 * n, nc))
 
 
 def mobility_matrix(axis, mob):

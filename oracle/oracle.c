@@ -165,6 +165,62 @@ int orc_pair_geometry(const double *ci, const double *pi, double Ri, double hi,
     return pair_geometry(ci, pi, Ri, hi, cj, pj, Rj, hj, L, periodic, out);
 }
 
+/* Particle-wall geometry (the boundary constraints of section 3.2's
+ * extensions: a column of D with the 6 entries of the particle only). Face
+ * f = 2a + side is the plane x_a = lo_a (side 0) or x_a = lo_a + L_a
+ * (side 1) of a non-periodic box; its inward normal m is +e_a or -e_a. The
+ * core point closest to the plane is c + s p with s = -h sign(m.p) (s = 0 if
+ * the rod lies parallel to the plane, the midpoint reading), so
+ * Phi = m.(c - x_face) - h |m.p| - R. The contact normal points from the
+ * particle to the wall, n = -m, and tau_i = (s p) x n. Output as
+ * pair_geometry's g with tau_j = 0; returns the parallel flag. */
+static int wall_geometry(const double *c, const double *p, double R, double h,
+                         const double *lo, const double *L, int face, double *g)
+{
+    int a = face / 2, up = face % 2;
+    double sg = up ? -1.0 : 1.0;
+    double d = up ? lo[a] + L[a] - c[a] : c[a] - lo[a];
+    double mp = sg * p[a];
+    double s = 0.0;
+    int par = 0;
+    if (h > 0.0) {
+        if (fabs(mp) < 1e-12)
+            par = 1;
+        else
+            s = mp > 0.0 ? -h : h;
+    }
+    double n[3] = {0.0, 0.0, 0.0};
+    n[a] = -sg;
+    double sp[3] = {s * p[0], s * p[1], s * p[2]}, ti[3];
+    cross3(sp, n, ti);
+    g[0] = d + s * mp - R;
+    for (int b = 0; b < 3; ++b) {
+        g[1 + b] = n[b];
+        g[6 + b] = ti[b];
+        g[9 + b] = 0.0;
+    }
+    g[4] = s;
+    g[5] = 0.0;
+    return par;
+}
+
+/* Wall contacts of particle i (faces in decreasing order, so that their
+ * codes j = -1 - face come out increasing). */
+static void push_walls(int i, const double *pos, const double *axis, const double *radius,
+                       const double *half_len, const double *lo, const double *L, int walls,
+                       double delta, void (*push)(void *, int, int, const double *, int),
+                       void *k)
+{
+    double g[12];
+    for (int f = 5; f >= 0; --f) {
+        if (!(walls & (1 << f)))
+            continue;
+        int fl = wall_geometry(pos + 3 * i, axis + 3 * i, radius[i], half_len[i], lo, L, f, g);
+        if (g[0] <= delta)
+            push(k, i, -1 - f, g, fl);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Close-pair set A(C, delta) = { l : Phi_l <= delta } (section 3.2),   */
 /* one constraint per pair i < j, in canonical order (by i, then j).    */
@@ -196,14 +252,21 @@ static void sink_push(contact_sink *k, int i, int j, const double *g, int flags)
     k->st[2 * l + 1] = g[5];
 }
 
-/* O(N^2) enumeration of every pair i < j. */
+static void sink_push_v(void *k, int i, int j, const double *g, int flags)
+{
+    sink_push((contact_sink *)k, i, j, g, flags);
+}
+
+/* O(N^2) enumeration of every pair i < j (each particle's wall contacts
+ * first). */
 static void contacts_brute(int n, const double *pos, const double *axis,
                            const double *radius, const double *half_len,
-                           const double *L, int periodic, double delta,
-                           contact_sink *k)
+                           const double *lo, const double *L, int periodic, int walls,
+                           double delta, contact_sink *k)
 {
     double g[12];
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
+        push_walls(i, pos, axis, radius, half_len, lo, L, walls, delta, sink_push_v, k);
         for (int j = i + 1; j < n; ++j) {
             int fl = pair_geometry(pos + 3 * i, axis + 3 * i, radius[i],
                                    half_len[i], pos + 3 * j, axis + 3 * j,
@@ -211,6 +274,7 @@ static void contacts_brute(int n, const double *pos, const double *axis,
             if (g[0] <= delta)
                 sink_push(k, i, j, g, fl);
         }
+    }
 }
 
 static int cmp_int(const void *a, const void *b)
@@ -226,7 +290,7 @@ static int cmp_int(const void *a, const void *b)
  * keeps nearby particles in the same or adjacent cells. */
 static void contacts_cells(int n, const double *pos, const double *axis,
                            const double *radius, const double *half_len,
-                           const double *lo, const double *L, int periodic,
+                           const double *lo, const double *L, int periodic, int walls,
                            double delta, contact_sink *k)
 {
     double rmax = 0.0;
@@ -311,6 +375,7 @@ static void contacts_cells(int n, const double *pos, const double *axis,
                     }
                 }
         qsort(list, (size_t)cnt, sizeof(int), cmp_int);
+        push_walls(i, pos, axis, radius, half_len, lo, L, walls, delta, sink_push_v, k);
         for (int m = 0; m < cnt; ++m) {
             int j = list[m];
             int fl = pair_geometry(pos + 3 * i, axis + 3 * i, radius[i],
@@ -326,22 +391,25 @@ static void contacts_cells(int n, const double *pos, const double *axis,
     free(members);
 }
 
-/* method 0 = brute force, 1 = cell list. Writes min(count, cap) contacts
- * and returns the full count. flags_out[2] = (#parallel-rule pairs,
- * #zero-distance pairs) among the emitted contacts. */
+/* method 0 = brute force, 1 = cell list. walls: bit f set = wall on face f
+ * (non-periodic boxes only). Writes min(count, cap) contacts and returns the
+ * full count; a wall contact has j = -1 - face. flags_out[2] =
+ * (#parallel-rule pairs, #zero-distance pairs) among the emitted contacts. */
 long orc_find_contacts(int method, int n, const double *pos,
                        const double *axis, const double *radius,
                        const double *half_len, const double *lo,
-                       const double *L, int periodic, double delta, long cap,
+                       const double *L, int periodic, int walls, double delta, long cap,
                        int *ci, int *cj, double *phi, double *nrm,
                        double *tau_i, double *tau_j, double *st,
                        long *flags_out)
 {
     contact_sink k = {cap, 0, ci, cj, phi, nrm, tau_i, tau_j, st, 0, 0};
+    if (periodic)
+        walls = 0;
     if (method == 0)
-        contacts_brute(n, pos, axis, radius, half_len, L, periodic, delta, &k);
+        contacts_brute(n, pos, axis, radius, half_len, lo, L, periodic, walls, delta, &k);
     else
-        contacts_cells(n, pos, axis, radius, half_len, lo, L, periodic,
+        contacts_cells(n, pos, axis, radius, half_len, lo, L, periodic, walls,
                        delta, &k);
     if (flags_out) {
         flags_out[0] = k.nflag_parallel;
@@ -353,7 +421,8 @@ long orc_find_contacts(int method, int n, const double *pos,
 /* ------------------------------------------------------------------ */
 /* Mobility, D and D^T (Eqs. Dmatdef and Dtranspose; LCP LCPdef).       */
 /* Column l of D puts (-n, -tau_i) on particle i and (+n, +tau_j) on    */
-/* particle j, so that D_l^T U = dPhi_l/dt for rigid velocities U.      */
+/* particle j, so that D_l^T U = dPhi_l/dt for rigid velocities U. A    */
+/* wall contact (j < 0) has the particle's 6 entries only.              */
 /* ------------------------------------------------------------------ */
 
 /* U = Mob F, per particle. */
@@ -381,10 +450,14 @@ void orc_D_apply(int n, long nc, const int *ci, const int *cj,
     memset(F, 0, sizeof(double) * 6 * (size_t)n);
     for (long l = 0; l < nc; ++l) {
         double *fi = F + 6 * (size_t)ci[l];
-        double *fj = F + 6 * (size_t)cj[l];
         for (int a = 0; a < 3; ++a) {
             fi[a] -= nrm[3 * l + a] * gamma[l];
             fi[3 + a] -= tau_i[3 * l + a] * gamma[l];
+        }
+        if (cj[l] < 0)
+            continue;
+        double *fj = F + 6 * (size_t)cj[l];
+        for (int a = 0; a < 3; ++a) {
             fj[a] += nrm[3 * l + a] * gamma[l];
             fj[3 + a] += tau_j[3 * l + a] * gamma[l];
         }
@@ -398,10 +471,12 @@ void orc_DT_apply(long nc, const int *ci, const int *cj, const double *nrm,
 {
     for (long l = 0; l < nc; ++l) {
         const double *ui = U + 6 * (size_t)ci[l];
-        const double *uj = U + 6 * (size_t)cj[l];
         const double *nn = nrm + 3 * l;
-        out[l] = -dot3(nn, ui) - dot3(tau_i + 3 * l, ui + 3)
-                 + dot3(nn, uj) + dot3(tau_j + 3 * l, uj + 3);
+        out[l] = -dot3(nn, ui) - dot3(tau_i + 3 * l, ui + 3);
+        if (cj[l] >= 0) {
+            const double *uj = U + 6 * (size_t)cj[l];
+            out[l] += dot3(nn, uj) + dot3(tau_j + 3 * l, uj + 3);
+        }
     }
 }
 
@@ -452,6 +527,8 @@ void orc_M_diag(long nc, const int *ci, const int *cj, const double *nrm,
         double acc = 0.0;
         for (int side = 0; side < 2; ++side) {
             int k = side ? cj[l] : ci[l];
+            if (k < 0)
+                continue;
             const double *tau = side ? tau_j + 3 * l : tau_i + 3 * l;
             double f[6], u[6];
             for (int a = 0; a < 3; ++a) {
@@ -698,6 +775,14 @@ void orc_adjoint_positions(int n, long nc, const double *pos,
             continue;
         int i = ci[l], j = cj[l];
         double Ei[6], Ej[6], gr[3];
+        if (j < 0) {
+            /* a plane wall: n and tau_i do not move with c_i, and
+             * dPhi/dc_i is the face's inward normal m = -n */
+            int face = -1 - j, a = face / 2;
+            double m = face % 2 ? -1.0 : 1.0;
+            dLdpos[3 * (size_t)i + a] += (-w[l] / dt) * m;
+            continue;
+        }
         for (int a = 0; a < 6; ++a) {
             double fi = dLdF ? dLdF[6 * (size_t)i + a] : 0.0;
             double fj = dLdF ? dLdF[6 * (size_t)j + a] : 0.0;

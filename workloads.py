@@ -59,6 +59,8 @@ class Suspension:
     tol: float = 1e-6      # absolute tolerance on ||min(gamma, g)||_2
     lo: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(3))
     periodic: int = 1
+    walls: int = 0         # non-periodic boxes: bit 2a (2a+1) = wall at the lower
+                           # (upper) face of axis a
 
     @property
     def n(self) -> int:
