@@ -68,12 +68,17 @@ typedef struct sc_particles {
 /* Simulation box. periodic != 0: minimum-image convention on [lo, lo+len)
  * (positions may lie anywhere; they are wrapped for binning only).
  * periodic == 0: free space; len only sizes the search grid (particles
- * outside [lo, lo+len) are still found). */
+ * outside [lo, lo+len) are still found), and `walls` may close faces of the
+ * box with planar walls (section 3.2's boundary extension: a particle
+ * within delta of a wall gets a constraint whose column of D holds its own
+ * 6 entries only). */
 typedef struct sc_box {
     double lo[3];
     double len[3];
     int32_t periodic;
-    int32_t reserved;
+    int32_t walls;          /* periodic == 0 only: bit 2a = wall at x_a = lo[a], bit
+                               2a + 1 = wall at x_a = lo[a] + len[a]; a wall contact has
+                               cj = -1 - face and tau_j = 0 */
 } sc_box;
 
 /* Contacts: one constraint per close pair i < j (section 3.1).

@@ -472,11 +472,12 @@ void orc_DT_apply(long nc, const int *ci, const int *cj, const double *nrm,
     for (long l = 0; l < nc; ++l) {
         const double *ui = U + 6 * (size_t)ci[l];
         const double *nn = nrm + 3 * l;
-        out[l] = -dot3(nn, ui) - dot3(tau_i + 3 * l, ui + 3);
+        double v = -dot3(nn, ui) - dot3(tau_i + 3 * l, ui + 3);
         if (cj[l] >= 0) {
             const double *uj = U + 6 * (size_t)cj[l];
-            out[l] += dot3(nn, uj) + dot3(tau_j + 3 * l, uj + 3);
+            v = v + dot3(nn, uj) + dot3(tau_j + 3 * l, uj + 3);
         }
+        out[l] = v;
     }
 }
 

@@ -34,7 +34,7 @@ class sc_particles(ctypes.Structure):
 
 class sc_box(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_double * 3), ("len", ctypes.c_double * 3),
-                ("periodic", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("periodic", ctypes.c_int32), ("walls", ctypes.c_int32)]
 
 
 class sc_contacts(ctypes.Structure):

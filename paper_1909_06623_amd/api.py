@@ -70,9 +70,13 @@ class Particles:
 
 @dataclasses.dataclass
 class Box:
+    """Periodic box, or (periodic=False) free space with optional planar
+    walls on its faces: bit 2a of ``walls`` closes x_a = lo_a, bit 2a + 1
+    closes x_a = lo_a + len_a."""
     len: tuple
     lo: tuple = (0.0, 0.0, 0.0)
     periodic: bool = True
+    walls: int = 0
 
     def c(self):
         b = A.sc_box()
@@ -80,6 +84,7 @@ class Box:
             b.lo[k] = float(self.lo[k])
             b.len[k] = float(self.len[k])
         b.periodic = 1 if self.periodic else 0
+        b.walls = int(self.walls)
         return b
 
 

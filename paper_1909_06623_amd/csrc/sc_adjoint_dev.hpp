@@ -20,9 +20,12 @@ __device__ inline double cg_rhs_one(int l, const int *ci, const int *cj, const d
     if (dLdF) {
         const double *f = frame + 9 * static_cast<long long>(l);
         const double *ui = dLdF + 6 * static_cast<long long>(ci[l]);
-        const double *uj = dLdF + 6 * static_cast<long long>(cj[l]);
-        b += -dot(load3(f), load3(ui)) - dot(load3(f + 3), load3(ui + 3)) +
-             dot(load3(f), load3(uj)) + dot(load3(f + 6), load3(uj + 3));
+        double v = -dot(load3(f), load3(ui)) - dot(load3(f + 3), load3(ui + 3));
+        if (cj[l] >= 0) {
+            const double *uj = dLdF + 6 * static_cast<long long>(cj[l]);
+            v = v + dot(load3(f), load3(uj)) + dot(load3(f + 6), load3(uj + 3));
+        }
+        b += v;
     }
     return act ? b : 0.0;
 }
@@ -44,6 +47,15 @@ __device__ __noinline__ V3 contact_grad_one(int l, const int *__restrict__ ci, c
     const double gl = gamma[l], wl = w[l];
     if (gl == 0.0 && wl == 0.0) return v3(0.0, 0.0, 0.0);
     const int i = ci[l], j = cj[l];
+    if (j < 0) {
+        // a plane wall: n and tau_i do not move with c_i and dPhi/dc_i is the
+        // face's inward normal m, so dJ/dc_i = -(w_l/dt) m; the gather puts
+        // -grad on particle i
+        const int face = -1 - j, a = face >> 1;
+        const double m = (face & 1) ? -1.0 : 1.0;
+        const double gv = wl * inv_dt * m;
+        return v3(a == 0 ? gv : 0.0, a == 1 ? gv : 0.0, a == 2 ? gv : 0.0);
+    }
     const long long ri = cs[2 * l], rj = cs[2 * l + 1];
     const V3 pi = load3(axis + 3 * i), pj = load3(axis + 3 * j);
     const double hi = half_len[i], hj = half_len[j];

@@ -14,9 +14,12 @@
 
 namespace sc {
 
+// Row l lists the contacts of its particles: deg(ci) + deg(cj) - 1 entries
+// (the contact itself once), deg(ci) for a wall contact (no second rank).
 __device__ __forceinline__ int row_length(const ChainView &C, int l) {
     const int ri = C.cs[2 * l], rj = C.cs[2 * l + 1];
-    return (C.inc_ptr[ri + 1] - C.inc_ptr[ri]) + (C.inc_ptr[rj + 1] - C.inc_ptr[rj]) - 1;
+    const int di = C.inc_ptr[ri + 1] - C.inc_ptr[ri];
+    return rj < 0 ? di : di + (C.inc_ptr[rj + 1] - C.inc_ptr[rj]) - 1;
 }
 
 __device__ __forceinline__ int wave_sum_int(int v) {
@@ -71,9 +74,17 @@ struct RowWalk {
         const double *b = C.dpm + 6 * static_cast<long long>(x);
         return b[0] * u.x + b[1] * u.y + b[2] * u.z + b[3] * w.x + b[4] * w.y + b[5] * w.z;
     }
-    // the diagonal; leaves the walk on the first off-diagonal entry
+    // the diagonal; leaves the walk on the first off-diagonal entry (a wall
+    // contact's row has its particle's side only)
     __device__ double start(const ChainView &C, int row) {
         l = row;
+        if (C.cs[2 * row + 1] < 0) {
+            ends[0] = C.cs[2 * row];
+            ends[1] = -1;
+            const double d0 = open(C, 0);
+            settle(C);
+            return d0;
+        }
         // the lower-ranked particle first: consecutive rows share it (rows are
         // grouped by it), so their entries line up depth by depth and the
         // lanes of one gather touch the same records
@@ -86,7 +97,7 @@ struct RowWalk {
         return d0 + d1;
     }
     __device__ void settle(const ChainView &C) {
-        if (e >= e1 && side == 0) open(C, 1);
+        if (e >= e1 && side == 0 && ends[1] >= 0) open(C, 1);
     }
     __device__ void next(const ChainView &C) {
         ++e;

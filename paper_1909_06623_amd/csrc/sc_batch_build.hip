@@ -355,6 +355,8 @@ int batch_build_plan(int32_t count, const sc_batch_item *items, Carver &cv, hipS
             if (!(it.box.len[a] > 0.0) || !std::isfinite(it.box.len[a]) ||
                 !std::isfinite(it.box.lo[a]))
                 return SC_ERR_INVALID;
+        if (it.box.walls < 0 || it.box.walls > 63 || (it.box.periodic && it.box.walls))
+            return SC_ERR_INVALID;
         if (n > 0 && (!it.p.pos || !it.p.axis || !it.p.radius || !it.p.half_len || !it.p.mob ||
                       !it.u_nc))
             return SC_ERR_INVALID;
@@ -443,7 +445,7 @@ int batch_build_plan(int32_t count, const sc_batch_item *items, Carver &cv, hipS
             I.ncell = 0;
             continue;
         }
-        if (!make_grid(items[k].box, items[k].delta, 2.0 * e + items[k].delta,
+        if (!make_grid(items[k].box, I.P.n, items[k].delta, 2.0 * e + items[k].delta,
                        cell_budget(I.P.n), I.g))
             return SC_ERR_BOX;
         I.ncell = I.g.nc[0] * I.g.nc[1] * I.g.nc[2];

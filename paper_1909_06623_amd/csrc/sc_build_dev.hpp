@@ -27,6 +27,7 @@ enum BuildFlag {
     kFlagBorder = 3,     // |Phi - delta| < 1e-12
     kFlagNonfiniteQ = 4, // q not finite (bad u_nc)
     kFlagExtent = 5,     // a particle reaches further than the search grid allows
+    kFlagWalls = 6,      // particle-wall contacts
     kFlagCount = 8,
 };
 
@@ -34,6 +35,8 @@ struct Grid {
     double lo[3], len[3], side[3];
     int nc[3];
     int periodic;
+    int walls;              // faces with a wall (bit 2a: x_a = lo_a, 2a + 1: x_a = lo_a + len_a)
+    int npart;              // particles; partner code npart + f stands for the wall on face f
     double delta;
     __host__ __device__ PBox box() const { return PBox{{len[0], len[1], len[2]}, periodic}; }
 };
@@ -146,6 +149,38 @@ __device__ __forceinline__ PairGeo ranked_geo(int a, int b, const Ranked &R, con
                     pj_[3], R.hl[rj]);
 }
 
+// Particle-wall geometry (section 3.2's boundary extension: the constraint's
+// column of D holds the particle's 6 entries only) for face f of a closed
+// box. With m the face's inward normal, the core point nearest the plane is
+// c + s p with s = -h sign(m.p) (s = 0 for a rod parallel to the plane: the
+// midpoint), Phi = m.(c - plane) - h |m.p| - R, and the contact normal
+// points from the particle to the wall, n = -m.
+__device__ __forceinline__ PairGeo wall_geo(V3 c, V3 p, double R, double h, const Grid &g,
+                                            int face) {
+    const int a = face >> 1;
+    const bool up = face & 1;
+    const double sg = up ? -1.0 : 1.0;
+    const double ca = a == 0 ? c.x : (a == 1 ? c.y : c.z);
+    const double pa = a == 0 ? p.x : (a == 1 ? p.y : p.z);
+    const double d = up ? g.lo[a] + g.len[a] - ca : ca - g.lo[a];
+    const double mp = sg * pa;
+    double s = 0.0;
+    int par = 0;
+    if (h > 0.0) {
+        if (fabs(mp) < 1e-12)
+            par = 1;
+        else
+            s = mp > 0.0 ? -h : h;
+    }
+    PairGeo G;
+    G.phi = d + s * mp - R;
+    G.n = v3(a == 0 ? -sg : 0.0, a == 1 ? -sg : 0.0, a == 2 ? -sg : 0.0);
+    G.s = s;
+    G.t = 0.0;
+    G.flags = par;
+    return G;
+}
+
 // Lanes that share one particle's 27-cell stencil in the pair search (lane j
 // takes the neighbour cells whose index in (z, y, x) order is j modulo this).
 constexpr int kPairLanes = 8;
@@ -154,7 +189,8 @@ constexpr int kPairLanes = 8;
 constexpr int kLaneSlots = 8;
 
 // Visit every partner u > t (by local rank) of rank t whose pair has
-// Phi <= delta, calling fn(u, geo). The candidates are the ranks of the 27
+// Phi <= delta, calling fn(u, geo), and lane 0 also every wall within delta
+// (u = npart + face). The candidates are the ranks of the 27
 // neighbour cells: per (y, z) row the x-neighbours are merged into runs of
 // consecutive cells, which are consecutive ranks (cells are row-major), and
 // the kPairLanes lanes of rank t take every kPairLanes-th candidate of the
@@ -227,6 +263,12 @@ __device__ __forceinline__ void for_close_partners(int t, int lane, const Ranked
                 seen += end - u0;
             }
         }
+    if (g.walls && lane == 0)
+        for (int f = 0; f < 6; ++f) {
+            if (!(g.walls & (1 << f))) continue;
+            const PairGeo G = wall_geo(ct, pt_ax, Rt, ht, g, f);
+            if (G.phi <= g.delta) fn(g.npart + f, G);
+        }
 }
 
 // Count pass of lane `lane` of rank t: the number of its partners goes to
@@ -236,10 +278,11 @@ __device__ __forceinline__ void for_close_partners(int t, int lane, const Ranked
 __device__ __forceinline__ void count_partners(int t, int lane, const Ranked &R, const Plan &pl,
                                                const Grid &g, const int *cstart, int rbase,
                                                int *lane_cnt, int *slots, int *flags) {
-    int cnt = 0, npar = 0, nzero = 0, nborder = 0;
+    int cnt = 0, npar = 0, nzero = 0, nborder = 0, nwall = 0;
     for_close_partners(t, lane, R, pl, g, cstart, rbase, [&](int u, const PairGeo &G) {
         if (cnt < kLaneSlots) slots[cnt] = u;
         ++cnt;
+        nwall += u >= g.npart;
         npar += G.flags & 1;
         nzero += (G.flags >> 1) & 1;
         nborder += fabs(G.phi - g.delta) < 1e-12;
@@ -252,6 +295,7 @@ __device__ __forceinline__ void count_partners(int t, int lane, const Ranked &R,
     if (npar) atomicAdd(flags + kFlagParallel, npar);
     if (nzero) atomicAdd(flags + kFlagZero, nzero);
     if (nborder) atomicAdd(flags + kFlagBorder, nborder);
+    if (nwall) atomicAdd(flags + kFlagWalls, nwall);
 }
 
 // Write pass: lane `lane` of rank t stores its partners' ranks (even slots of
@@ -278,9 +322,10 @@ __device__ __forceinline__ void write_partners(int t, int lane, const Ranked &R,
     });
 }
 
-// Contacts of rank t (partners of higher rank, ascending): caller indices,
-// Phi, frame [l][9] = n, tau_i, tau_j oriented from ci (lower caller index)
-// to cj, and cs[l] = the ranks of (ci, cj).
+// Contacts of rank t (partners of higher rank, ascending, then walls):
+// caller indices, Phi, frame [l][9] = n, tau_i, tau_j oriented from ci
+// (lower caller index) to cj, and cs[l] = the ranks of (ci, cj). A wall
+// contact has cj = -1 - face, tau_j = 0 and no second rank (-1).
 __device__ __forceinline__ void finish_partners(int t, const Ranked &R, const Plan &pl,
                                                 const Grid &g, int *ci, int *cj, double *phi,
                                                 double *frame) {
@@ -300,6 +345,23 @@ __device__ __forceinline__ void finish_partners(int t, const Ranked &R, const Pl
     for (int a = 0; a < k; ++a) {
         const long long l = base + a;
         const int u = part[2 * a];
+        if (u >= g.npart) {
+            const double *pr = R.prec + 4 * static_cast<long long>(t);
+            const double *ax = pl.pdat + 8 * static_cast<long long>(t);
+            const V3 p = v3(ax[0], ax[1], ax[2]);
+            const PairGeo G = wall_geo(v3(pr[0], pr[1], pr[2]), p, pr[3], R.hl[t], g, u - g.npart);
+            const V3 ti = cross(G.s * p, G.n);
+            ci[l] = ot;
+            cj[l] = -1 - (u - g.npart);
+            phi[l] = G.phi;
+            double *f = frame + 9 * l;
+            f[0] = G.n.x; f[1] = G.n.y; f[2] = G.n.z;
+            f[3] = ti.x;  f[4] = ti.y;  f[5] = ti.z;
+            f[6] = 0.0;   f[7] = 0.0;   f[8] = 0.0;
+            part[2 * a] = t;
+            part[2 * a + 1] = -1;
+            continue;
+        }
         bool t_is_i;
         const PairGeo G = ranked_geo(t, u, R, pl, box, t_is_i);
         const int ri = t_is_i ? t : u, rj = t_is_i ? u : t;
@@ -326,6 +388,7 @@ __device__ __forceinline__ void finish_partners(int t, const Ranked &R, const Pl
 // placed by an atomic cursor and sorted by contact index afterwards.
 __device__ __forceinline__ void count_second(int l, const Plan &pl, int *deg) {
     const int a = pl.cs[2 * l], b = pl.cs[2 * l + 1];
+    if (b < 0) return;  // a wall contact belongs to its particle only
     atomicAdd(deg + (a > b ? a : b), 1);
 }
 
@@ -335,6 +398,10 @@ __device__ __forceinline__ void incidence_count(int k, const Plan &pl, const int
 
 __device__ __forceinline__ void incidence_fill(int l, const Plan &pl, int *fill) {
     const int a = pl.cs[2 * l], b = pl.cs[2 * l + 1];
+    if (b < 0) {  // wall contact: in its particle's own group
+        pl.inc[pl.inc_ptr[a] + (l - pl.cptr[a])] = 2 * l + 1;
+        return;
+    }
     const int lo = a < b ? a : b, hi = a < b ? b : a;
     pl.inc[pl.inc_ptr[lo] + (l - pl.cptr[lo])] = 2 * l + 1;
     const int first_hi = pl.cptr[hi + 1] - pl.cptr[hi];
@@ -376,9 +443,11 @@ __device__ __forceinline__ double contact_q(int l, const int *ci, const int *cj,
     const double *f = frame + 9 * static_cast<long long>(l);
     const V3 n = load3(f), ti = load3(f + 3), tj = load3(f + 6);
     const double *ui = u_nc + 6 * static_cast<long long>(ci[l]);
-    const double *uj = u_nc + 6 * static_cast<long long>(cj[l]);
-    const double v = -dot(n, load3(ui)) - dot(ti, load3(ui + 3)) + dot(n, load3(uj)) +
-                     dot(tj, load3(uj + 3));
+    double v = -dot(n, load3(ui)) - dot(ti, load3(ui + 3));
+    if (cj[l] >= 0) {
+        const double *uj = u_nc + 6 * static_cast<long long>(cj[l]);
+        v = v + dot(n, load3(uj)) + dot(tj, load3(uj + 3));
+    }
     return phi[l] / dt + v;
 }
 
@@ -386,8 +455,11 @@ __device__ __forceinline__ double contact_q(int l, const int *ci, const int *cj,
 // rmax, at most 1024 per axis, the total within `budget`). Returns false if a
 // periodic side is shorter than 2 rmax (the minimum image would be
 // ambiguous).
-inline bool make_grid(const sc_box &box, double delta, double rmax, size_t budget, Grid &g) {
+inline bool make_grid(const sc_box &box, int n, double delta, double rmax, size_t budget,
+                      Grid &g) {
     g = Grid{};
+    g.npart = n;
+    g.walls = box.periodic ? 0 : box.walls;
     for (int a = 0; a < 3; ++a) {
         g.lo[a] = box.lo[a];
         g.len[a] = box.len[a];

@@ -99,10 +99,11 @@ __device__ __forceinline__ double dt_u(const ChainView &C, int l) {
     const int ri = C.cs[2 * l], rj = C.cs[2 * l + 1];
     const double *f = C.frame + 9 * static_cast<long long>(l);
     const double *Ui = C.U + 8 * static_cast<long long>(ri);
+    const double vi = -(f[0] * Ui[0] + f[1] * Ui[1] + f[2] * Ui[2]) -
+                      (f[3] * Ui[3] + f[4] * Ui[4] + f[5] * Ui[5]);
+    if (rj < 0) return vi;  // wall contact: the particle's side only
     const double *Uj = C.U + 8 * static_cast<long long>(rj);
-    return -(f[0] * Ui[0] + f[1] * Ui[1] + f[2] * Ui[2]) -
-           (f[3] * Ui[3] + f[4] * Ui[4] + f[5] * Ui[5]) +
-           (f[0] * Uj[0] + f[1] * Uj[1] + f[2] * Uj[2]) +
+    return vi + (f[0] * Uj[0] + f[1] * Uj[1] + f[2] * Uj[2]) +
            (f[6] * Uj[3] + f[7] * Uj[4] + f[8] * Uj[5]);
 }
 

@@ -179,6 +179,7 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     for (int a = 0; a < 3; ++a)
         if (!(box->len[a] > 0.0) || !std::isfinite(box->len[a]) || !std::isfinite(box->lo[a]))
             return SC_ERR_INVALID;
+    if (box->walls < 0 || box->walls > 63 || (box->periodic && box->walls)) return SC_ERR_INVALID;
     c->count = 0;
     c->n_parallel = c->n_zero_dist = c->n_borderline = 0;
     c->grid[0] = c->grid[1] = c->grid[2] = 0;
@@ -238,7 +239,7 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     }
     const double rmax = 2.0 * ext + delta;
     Grid g;
-    if (!make_grid(*box, delta, rmax, nb, g)) return SC_ERR_BOX;
+    if (!make_grid(*box, n, delta, rmax, nb, g)) return SC_ERR_BOX;
     const size_t ncell = static_cast<size_t>(g.nc[0]) * g.nc[1] * g.nc[2];
     for (int a = 0; a < 3; ++a) c->grid[a] = g.nc[a];
 
@@ -293,7 +294,8 @@ extern "C" int sc_build_contacts(const sc_particles *p, const sc_box *box, doubl
     SC_HIP_TRY(hipMemcpyAsync(&hdsq, dsq, sizeof(hdsq), hipMemcpyDeviceToHost, stream));
     SC_HIP_TRY(hipStreamSynchronize(stream));
     SC_HIP_TRY(hipGetLastError());
-    c->nnz = nc > 0 ? static_cast<int64_t>(hdsq) - nc : 0;
+    // rows: deg(i) + deg(j) - 1 for a pair, deg(i) for a wall contact
+    c->nnz = nc > 0 ? static_cast<int64_t>(hdsq) - (nc - hflags[kFlagWalls]) : 0;
     if (hflags[kFlagNonfiniteQ]) return SC_ERR_NONFINITE;
     return SC_OK;
 }

@@ -49,6 +49,7 @@ __device__ __forceinline__ double m_diag(const ChainView &C, int l) {
     const V3 n = load3(f), ti = load3(f + 3), tj = load3(f + 6);
     V3 ui, wi, uj, wj;
     plan_mobility(C.pdat + 8 * static_cast<long long>(ri), n, ti, ui, wi);
+    if (rj < 0) return dot(n, ui) + dot(ti, wi);  // wall contact
     plan_mobility(C.pdat + 8 * static_cast<long long>(rj), n, tj, uj, wj);
     return dot(n, ui) + dot(ti, wi) + dot(n, uj) + dot(tj, wj);
 }
