@@ -69,7 +69,7 @@ typedef struct sc_particles {
  * (positions may lie anywhere; they are wrapped for binning only).
  * periodic == 0: free space; len only sizes the search grid (particles
  * outside [lo, lo+len) are still found), and `walls` may close faces of the
- * box with planar walls (section 3.2's boundary extension: a particle
+ * box with planar walls (section 3.3's boundary extension: a particle
  * within delta of a wall gets a constraint whose column of D holds its own
  * 6 entries only). */
 typedef struct sc_box {
@@ -232,11 +232,11 @@ int sc_mvop(const sc_particles *p, const sc_contacts *c, const double *x,
  * from gamma_0 (zero, or the contents of gamma if opts->warm_start), g_0 = M gamma_0 + q, alpha_0 = g0^T g0 /
  * g0^T M g0, then gamma_j = max(0, gamma_{j-1} - alpha_{j-1} g_{j-1}),
  * g_j = M gamma_j + q, stopping when ||min(gamma_j, g_j)||_2 < tol (Eq.
- * mmapnorm), with the BB1/BB2 step of Algorithm 1 step 15. A non-positive
+ * mmapnorm), with the BB1/BB2 step size of Algorithm 1. A non-positive
  * BB denominator keeps the previous step (g0^T M g0 <= 0 takes 1/max_l
  * M_ll). gamma, g: [c->count], OUT: the last iterate and M gamma + q.
  * f_c, u_c: [n][6] or NULL; OUT: contact forces D gamma and velocities
- * Mob D gamma (section 3.2, procedure step 3). st: host pointer, OUT.
+ * Mob D gamma (computed with gamma, as section 3.2's procedure asks). st: host pointer, OUT.
  * Returns SC_OK, SC_NOT_CONVERGED (outputs hold the last iterate) or an
  * error. Iterates are bitwise reproducible for a given launch shape (grid,
  * lanes_per_particle). Synchronises `stream`. */

@@ -165,7 +165,7 @@ int orc_pair_geometry(const double *ci, const double *pi, double Ri, double hi,
     return pair_geometry(ci, pi, Ri, hi, cj, pj, Rj, hj, L, periodic, out);
 }
 
-/* Particle-wall geometry (the boundary constraints of section 3.2's
+/* Particle-wall geometry (the boundary constraints of section 3.3's
  * extensions: a column of D with the 6 entries of the particle only). Face
  * f = 2a + side is the plane x_a = lo_a (side 0) or x_a = lo_a + L_a
  * (side 1) of a non-periodic box; its inward normal m is +e_a or -e_a. The
@@ -579,7 +579,7 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
     long ndegen = 0;
     double res, alpha = 0.0;
 
-    /* step 2: g0 = M gamma0 + q */
+    /* g0 = M gamma0 + q */
     mvop(&c, gamma, g);
     mvops++;
     for (long l = 0; l < nc; ++l)
@@ -589,10 +589,10 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
         status = 3;
         goto done;
     }
-    /* steps 3-5 */
+    /* gamma0 may already satisfy the tolerance */
     if (res < tol)
         goto done;
-    /* step 6: alpha0 = g0^T g0 / g0^T M g0 */
+    /* initial step size alpha0 = g0^T g0 / g0^T M g0 */
     mvop(&c, g, tmp);
     mvops++;
     {
@@ -616,12 +616,12 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
     for (int j = 1; j <= max_iter; ++j) {
         memcpy(gamma_prev, gamma, sz);
         memcpy(g_prev, g, sz);
-        /* steps 8-9: descent step, then projection onto gamma >= 0 */
+        /* descent step, then projection onto gamma >= 0 */
         for (long l = 0; l < nc; ++l) {
             double v = gamma_prev[l] - alpha * g_prev[l];
             gamma[l] = v < 0.0 ? 0.0 : v;
         }
-        /* step 10 */
+        /* new gradient g = M gamma + q */
         mvop(&c, gamma, g);
         mvops++;
         for (long l = 0; l < nc; ++l)
@@ -632,12 +632,12 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
             status = 3;
             break;
         }
-        /* steps 11-13 */
+        /* stopping test */
         if (res < tol) {
             status = 0;
             break;
         }
-        /* steps 14-15 */
+        /* BB step size from s = gamma_j - gamma_{j-1}, y = g_j - g_{j-1} */
         double ss = 0.0, sy = 0.0, yy = 0.0;
         for (long l = 0; l < nc; ++l) {
             double s = gamma[l] - gamma_prev[l];

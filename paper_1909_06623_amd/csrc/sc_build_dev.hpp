@@ -149,7 +149,7 @@ __device__ __forceinline__ PairGeo ranked_geo(int a, int b, const Ranked &R, con
                     pj_[3], R.hl[rj]);
 }
 
-// Particle-wall geometry (section 3.2's boundary extension: the constraint's
+// Particle-wall geometry (section 3.3's boundary extension: the constraint's
 // column of D holds the particle's 6 entries only) for face f of a closed
 // box. With m the face's inward normal, the core point nearest the plane is
 // c + s p with s = -h sign(m.p) (s = 0 for a rod parallel to the plane: the

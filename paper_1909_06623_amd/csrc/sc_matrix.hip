@@ -5,9 +5,9 @@
 // only through a shared particle k, M_lm = a_lk^T Mob_k a_mk (a_lk the signed
 // column entries of contact l on particle k), so row l has
 // deg(ci) + deg(cj) - 1 entries. Forming it once turns each BBPGD iteration
-// into a single contact-major pass: the projected step of Algorithm 1 (steps
-// 8-9) is formed on the fly for every column, g = M gamma + q (step 10) and
-// the sums of steps 11 and 14-15 are accumulated, then one grid barrier and
+// into a single contact-major pass: the projected descent step of Algorithm
+// 1 is formed on the fly for every column, g = M gamma + q and the sums of
+// the stopping test and the BB step size are accumulated, then one grid barrier and
 // a fixed-order reduction decide the next step. The adjoint's masked CG is
 // laid out the same way. Rows are in solver order, so column gathers stay
 // local.

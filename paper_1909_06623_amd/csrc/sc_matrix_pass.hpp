@@ -364,7 +364,7 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
     int iters = 0, mvops = 0, status = SC_NOT_CONVERGED, ndegen = 0;
     bool ok;
 
-    // step 2: g0 = M gamma0 + q
+    // g0 = M gamma0 + q
     {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         GG *z0 = z[0];
@@ -391,9 +391,9 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
     } else if (!isfinite(res)) {
         status = SC_ERR_NONFINITE;
     } else if (res < tol) {
-        status = SC_OK;  // steps 3-5
+        status = SC_OK;  // gamma0 already satisfies the tolerance
     } else {
-        // step 6: alpha0 = g0^T g0 / g0^T M g0 (the diagonal leads each row)
+        // initial step size alpha0 = g0^T g0 / g0^T M g0 (the diagonal leads each row)
         {
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
             const GG *z0 = z[0];
@@ -419,7 +419,7 @@ __device__ void bbpgd_rows(const MatView &Mv, const SliceChunk &rc, const WaveCa
             const GG *zc = z[(j - 1) & 1];
             GG *zn = z[j & 1];
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            // steps 8-10 in one pass: gamma_j formed per column on the fly
+            // projected step and new gradient in one pass: gamma_j formed per column on the fly
             struct Own {
                 GG z;
                 double q;

@@ -4,13 +4,13 @@
 // One iteration is two passes of the chain (sc_chain.hpp) separated by grid
 // barriers (sc_sync.hpp):
 //   pass A: gamma_j = max(0, gamma_{j-1} - alpha g_{j-1}) formed on the fly
-//     for every incidence (steps 8-9; the owning incidence stores it), and
-//     U = Mob D gamma_j;
-//   pass B: g_j = D^T U + q (step 10) with the partial sums of
+//     for every incidence (the projected descent step; the owning incidence
+//     stores it), and U = Mob D gamma_j;
+//   pass B: g_j = D^T U + q (the new gradient) with the partial sums of
 //     ||min(gamma_j, g_j)||^2 (Eq. mmapnorm), s^T s, s^T y and y^T y.
 // After the second barrier every workgroup reduces all partials in the same
-// fixed order and takes the same decision: stop (step 11) or the BB step
-// (steps 14-15). No floating-point atomics are used, so the iterates are
+// fixed order and takes the same decision: stop, or the next BB step size.
+// No floating-point atomics are used, so the iterates are
 // bitwise reproducible for a given launch shape.
 #include <cstring>
 
@@ -38,7 +38,7 @@ struct SolveArgs {
     int max_iter, bb;
 };
 
-// Projection of step 9 (negative components set to zero), written so that a
+// Projection onto gamma >= 0 (negative components set to zero), written so that a
 // NaN propagates instead of being clamped away.
 __device__ __forceinline__ double project(double v) { return v < 0.0 ? 0.0 : v; }
 
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(BS) k_bbpgd(SolveArgs A) {
     int iters = 0, mvops = 0, status = SC_NOT_CONVERGED, ndegen = 0;
     bool ok = true;
 
-    // step 2: g0 = M gamma0 + q
+    // g0 = M gamma0 + q
     pass_a<LPP, BS>(C, k0, k1, [&](int code, int) { return A.gam[0][code >> 1]; });
     ok = bar.sync();
     {
@@ -93,9 +93,9 @@ __global__ void __launch_bounds__(BS) k_bbpgd(SolveArgs A) {
     } else if (!isfinite(res)) {
         status = SC_ERR_NONFINITE;
     } else if (res < A.tol) {
-        status = SC_OK;  // steps 3-5
+        status = SC_OK;  // gamma0 already satisfies the tolerance
     } else {
-        // step 6: alpha0 = g0^T g0 / g0^T M g0
+        // initial step size alpha0 = g0^T g0 / g0^T M g0
         pass_a<LPP, BS>(C, k0, k1, [&](int code, int) { return A.gg[0][code >> 1]; });
         ok = bar.sync();
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(BS) k_bbpgd(SolveArgs A) {
             const int cur = (j - 1) & 1, nxt = j & 1;
             const double *gc = A.gam[cur], *gr = A.gg[cur];
             double *gn = A.gam[nxt];
-            // steps 8-10, pass A: projected step on the fly, owner stores it
+            // pass A: projected step on the fly, owner stores it
             pass_a<LPP, BS>(C, k0, k1, [&](int code, int) {
                 const int l = code >> 1;
                 const double w = project(gc[l] - alpha * gr[l]);
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(BS) k_bbpgd(SolveArgs A) {
                 return w;
             });
             ok = bar.sync();
-            // step 10, pass B, and the sums of steps 11 and 14-15
+            // pass B: new gradient, residual and BB sums
             double acc2[4] = {0.0, 0.0, 0.0, 0.0};
             double *gnew = A.gg[nxt];
             for (int l = l0 + threadIdx.x; l < l1; l += BS) {

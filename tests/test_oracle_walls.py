@@ -1,5 +1,5 @@
 """Pins of the oracle's particle-wall constraints (the boundary extension of
-section 3.2: a D column with the particle's 6 entries only) for the planar
+section 3.3: a D column with the particle's 6 entries only) for the planar
 faces of a closed box."""
 import math
 
