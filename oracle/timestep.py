@@ -4,7 +4,8 @@ smoke check and the benchmark's CPU leg use the oracle).
 
 One step, in the paper's order:
 
-1. U_nc = Mob F_ext at the current configuration (dry mobility).
+1. U_nc = Mob F_ext at the current configuration (the dry mobility, or the
+   RPY mobility of ``oracle.hydro``).
 2. The close-pair set A(C^k, delta), its contact frames and q
    (``find_contacts``, ``build_q``; LCP LCPdef).
 3. The LCP solved by Algorithm 1 (``bbpgd``), started from zero or, with
@@ -92,18 +93,35 @@ class StepRecord:
     U: np.ndarray          # [n,6] U_nc + U_c used for the update
 
 
-def step(s, quat, prev: StepRecord | None = None, warm=True, tol=None):
+def step(s, quat, prev: StepRecord | None = None, warm=True, tol=None, hydro=None, mu=1.0):
     """One step from suspension ``s`` (its pos and axis) and quaternions
-    ``quat``; returns (next suspension, next quaternions, record)."""
+    ``quat``; returns (next suspension, next quaternions, record).
+    ``hydro="rpy"``: the mobility is the RPY mobility of spheres of radii
+    ``s.hydro_radius`` (else ``s.radius``) and viscosity ``mu``, and the LCP
+    is solved on the explicit M = D^T Mob D (``bbpgd_dense``)."""
     c = find_contacts(s)
-    u_nc = mobility(s.axis, s.mob, s.f_ext)
-    q = build_q(c, u_nc, s.dt)
     gamma0 = None
     if warm and prev is not None and c.nc:
         old = {(int(a), int(b)): g for a, b, g in zip(prev.i, prev.j, prev.gamma)}
         gamma0 = np.array([old.get((int(a), int(b)), 0.0) for a, b in zip(c.i, c.j)])
-    gamma, g, st = bbpgd(s, c, q, gamma0=gamma0, tol=tol)
-    u_c = mobility(s.axis, s.mob, D_apply(s.n, c, gamma))
+    if hydro == "rpy":
+        from . import D_matrix, M_diag
+        from .hydro import bbpgd_dense, contact_matrix, rpy_dense
+        rad = s.radius if s.hydro_radius is None else s.hydro_radius
+        Mob = rpy_dense(s.pos, rad, mu)
+        u_nc = (Mob @ s.f_ext.ravel()).reshape(s.n, 6)
+        q = build_q(c, u_nc, s.dt)
+        M = contact_matrix(D_matrix(s.n, c), Mob)
+        gamma, g, st = bbpgd_dense(M, q, M_diag(s, c), gamma0=gamma0,
+                                   tol=s.tol if tol is None else tol)
+        u_c = (Mob @ D_apply(s.n, c, gamma).ravel()).reshape(s.n, 6)
+    elif hydro is None:
+        u_nc = mobility(s.axis, s.mob, s.f_ext)
+        q = build_q(c, u_nc, s.dt)
+        gamma, g, st = bbpgd(s, c, q, gamma0=gamma0, tol=tol)
+        u_c = mobility(s.axis, s.mob, D_apply(s.n, c, gamma))
+    else:
+        raise ValueError(f"unknown mobility {hydro!r}")
     U = u_nc + u_c
     pos, qn, axis = advance(s.pos, quat, U, s.dt)
     rec = StepRecord(c.i.copy(), c.j.copy(), c.phi.copy(), gamma, st.iters, st.mvops,
@@ -111,13 +129,13 @@ def step(s, quat, prev: StepRecord | None = None, warm=True, tol=None):
     return dataclasses.replace(s, pos=pos, axis=axis), qn, rec
 
 
-def run(s, steps, warm=True, tol=None, quat=None):
+def run(s, steps, warm=True, tol=None, quat=None, hydro=None, mu=1.0):
     """``steps`` steps from ``s``; returns (final suspension, quaternions,
     records)."""
     quat = quat_from_axis(s.axis) if quat is None else np.asarray(quat, dtype=np.float64)
     recs = []
     prev = None
     for _ in range(steps):
-        s, quat, prev = step(s, quat, prev, warm, tol)
+        s, quat, prev = step(s, quat, prev, warm, tol, hydro, mu)
         recs.append(prev)
     return s, quat, recs

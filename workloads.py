@@ -61,6 +61,8 @@ class Suspension:
     periodic: int = 1
     walls: int = 0         # non-periodic boxes: bit 2a (2a+1) = wall at the lower
                            # (upper) face of axis a
+    hydro_radius: np.ndarray | None = None   # [N] radii of a hydrodynamic mobility
+                                              # (None: the collision radius)
 
     @property
     def n(self) -> int:
@@ -75,7 +77,8 @@ class Suspension:
         return dataclasses.replace(
             self, pos=self.pos[idx].copy(), axis=self.axis[idx].copy(),
             radius=self.radius[idx].copy(), half_len=self.half_len[idx].copy(),
-            mob=self.mob[idx].copy(), f_ext=self.f_ext[idx].copy())
+            mob=self.mob[idx].copy(), f_ext=self.f_ext[idx].copy(),
+            hydro_radius=None if self.hydro_radius is None else self.hydro_radius[idx].copy())
 
 
 # ---------------------------------------------------------------- properties
@@ -163,6 +166,64 @@ def spheres(n, phi, seed, radius=SPHERE_RADIUS, delta=SPHERE_DELTA, dt=1e-3,
     return Suspension(name or f"spheres_n{n}_phi{phi:g}", pos, axis, rad,
                       np.zeros(n), sphere_mobility(rad), f_ext, box, delta,
                       dt, tol)
+
+
+def sphere_cluster(n, seed, phi=0.2, a=1.0, collision_scale=1.05, force=1.0, mu=MU,
+                   tol=1e-6, squeeze=0.0, name=None):
+    """The dense sedimenting cluster of the paper's section 6.3: ``n`` spheres
+    of hydrodynamic radius ``a`` in a ball whose hydrodynamic volume
+    fraction is ``phi``, placed by random sequential addition without
+    overlap of their collision spheres (radius ``collision_scale * a``);
+    the same force ``-force e_z`` on each, no torque; unbounded fluid (a
+    non-periodic box that only sizes the search grid); delta = 30% of the
+    sum of two collision radii and dt = 0.05 mu a^2 / force. ``squeeze`` > 0
+    adds an inward radial force of that many times ``force`` (a compressed
+    cluster, with many active contacts)."""
+    rng = _rng(seed)
+    rc = collision_scale * a
+    R = a * (n / phi) ** (1.0 / 3.0)
+    cell = 2.0 * rc
+    grid = {}
+    pos = np.empty((n, 3))
+    k = 0
+    while k < n:
+        x = rng.uniform(-R, R, 3)
+        if x @ x > (R - rc) ** 2:
+            continue
+        key = tuple(np.floor(x / cell).astype(int))
+        ok = True
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    for m in grid.get((key[0] + dx, key[1] + dy, key[2] + dz), ()):
+                        d = pos[m] - x
+                        if d @ d < cell * cell:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if not ok:
+            continue
+        pos[k] = x
+        grid.setdefault(key, []).append(k)
+        k += 1
+    f_ext = np.zeros((n, 6))
+    f_ext[:, 2] = -force
+    if squeeze:
+        rn = np.linalg.norm(pos, axis=1, keepdims=True)
+        f_ext[:, :3] -= squeeze * force * pos / np.maximum(rn, 1e-300)
+    hyd = np.full(n, float(a))
+    delta = 0.3 * 2.0 * rc
+    margin = 2.0 * rc + delta
+    lo = np.full(3, -R - margin)
+    return Suspension(name or f"cluster_n{n}", pos, _isotropic_axes(rng, n), np.full(n, rc),
+                      np.zeros(n), sphere_mobility(hyd, mu), f_ext,
+                      np.full(3, 2.0 * (R + margin)), delta, 0.05 * mu * a * a / force, tol,
+                      lo=lo, periodic=0, hydro_radius=hyd)
 
 
 def rods(n, seed, density=None, phi=None, pairs_per_rod=6.0, kappa=None,
