@@ -124,6 +124,8 @@ typedef struct sc_contacts {
 #define SC_OP_AUTO   0      /* assembled M if c->mat_ready, else the matrix-free chain */
 #define SC_OP_CHAIN  1      /* matrix-free: gather D x, apply Mob, gather D^T U */
 #define SC_OP_MATRIX 2      /* assembled sparse M (requires c->mat_ready) */
+#define SC_OP_CALLBACK 3    /* reported by sc_solve_lcp_mob only: D x, the caller's
+                               mobility, D^T U */
 
 typedef struct sc_solve_opts {
     double tol;             /* absolute tolerance on ||min(gamma, g)||_2 (> 0) */
@@ -397,6 +399,86 @@ int sc_quat_from_axis(int32_t n, const double *axis, double *quat, void *stream)
  * [cur->count]. Enqueues only. */
 int sc_map_gamma(int32_t n, const sc_contacts *prev, const double *gamma_prev,
                  const sc_contacts *cur, double *gamma0, void *stream);
+
+/* ---- Algorithm 1 behind a general mobility --------------------------------
+ * Section 2 defines the mobility Mob as a dense SPD map from forces and
+ * torques to velocities; in section 3.3 each product M x = D^T Mob D x is one
+ * mobility problem for the force D x, and section 8 allows any mobility
+ * solver that keeps Mob SPD. The entry points below take the mobility as a
+ * function. */
+
+/* A mobility: enqueue u = Mob f on `stream` (no host synchronisation needed)
+ * for device arrays f, u of [n][6] in caller particle order (force xyz,
+ * torque xyz -> velocity xyz, angular velocity xyz). Mob must be symmetric
+ * positive definite. Returns SC_OK or an error code; an error ends the solve
+ * that called it with that code. f and u belong to the caller of the
+ * function and are valid until the enqueued work completes. */
+typedef int (*sc_mobility_fn)(void *ctx, int32_t n, const double *f, double *u,
+                              void *stream);
+
+/* The Rotne-Prager-Yamakawa mobility of n spheres in unbounded fluid (the
+ * approximation the abstract and section 1 name), in the form of Zuk,
+ * Wajnryb, Mizerski and Szymczak (J. Fluid Mech. 2014) for unequal radii a_i,
+ * a_j at centre distance r:
+ *   r > a_i + a_j:   (1/(8 pi mu r)) [(1 + (a_i^2 + a_j^2)/(3 r^2)) I
+ *                                     + (1 - (a_i^2 + a_j^2)/r^2) rr/r^2],
+ *   |a_i - a_j| < r <= a_i + a_j: the overlap form
+ *     (1/(6 pi mu a_i a_j)) [(16 r^3 (a_i + a_j) - ((a_i - a_j)^2 + 3 r^2)^2)/(32 r^3) I
+ *                            + 3 ((a_i - a_j)^2 - r^2)^2/(32 r^3) rr/r^2],
+ *   r <= |a_i - a_j|: I / (6 pi mu max(a_i, a_j)),
+ * with the self term I / (6 pi mu a_i). Rotations take the single-sphere
+ * mobility I / (8 pi mu a_i^3) and do not couple between spheres, which keeps
+ * Mob SPD. The pair sum is evaluated directly (O(n^2), FP64). */
+typedef struct sc_rpy {
+    int32_t n;              /* number of spheres */
+    int32_t reserved;
+    const double *pos;      /* [n][3] device: centres */
+    const double *radius;   /* [n] device: hydrodynamic radii > 0 (may differ from the
+                               collision radii of sc_particles) */
+    double mu;              /* viscosity > 0 */
+    void *work;             /* device, 256-byte aligned, >= sc_rpy_work_bytes(n) bytes */
+    size_t work_bytes;
+} sc_rpy;
+
+/* Device bytes of sc_rpy.work for n spheres. */
+size_t sc_rpy_work_bytes(int32_t n);
+
+/* sc_mobility_fn for ctx = const sc_rpy *: u = Mob f. n must equal ctx->n.
+ * Enqueues only. Returns SC_OK, SC_ERR_INVALID (n mismatch, NULL pointer,
+ * mu <= 0), SC_ERR_WORKSPACE or SC_ERR_HIP. Calls that overlap on one
+ * stream's work buffer race. */
+int sc_rpy_apply(void *ctx, int32_t n, const double *f, double *u, void *stream);
+
+/* sc_mobility_fn for ctx = const sc_particles *: the dry block-diagonal
+ * mobility of sc_apply_mobility. */
+int sc_dry_apply(void *ctx, int32_t n, const double *f, double *u, void *stream);
+
+/* Device bytes of the workspace of sc_solve_lcp_mob. */
+size_t sc_solve_mob_work_bytes(int32_t n, int32_t capacity);
+
+/* Algorithm 1 (section 3.3.1) as sc_solve_lcp computes it, with every
+ * product M x = D^T Mob D x taking Mob from `mob(mob_ctx, ...)`: gamma_0,
+ * g_0 = M gamma_0 + q, alpha_0 = g0^T g0 / g0^T M g0 (if that denominator is
+ * <= 0: 1 / max_l of D_l^T Mob_self D_l from the particles' own `mob`
+ * blocks), then projected BB steps until ||min(gamma, g)||_2 < opts->tol
+ * (Eq. mmapnorm) or opts->max_iter steps. Uses opts->tol, max_iter, bb and
+ * warm_start; the launch-shape fields are ignored. c: contacts from
+ * sc_build_contacts (the plan is used; M need not be assembled).
+ * The iterations are enqueued in chunks of `check_every` (0 = 4) and the
+ * host reads the stop decision one chunk behind, so up to about two chunks
+ * of mobility calls run after the decision to stop (their results are
+ * ignored, and they are not counted in mvops). gamma, g: [c->count] device,
+ * OUT (gamma holds gamma_0 on entry if warm_start). f_c, u_c: [n][6] device
+ * or NULL: D gamma and Mob D gamma of the result. st: host, OUT (kernel_ms:
+ * GPU time from the first product to the stop decision; op =
+ * SC_OP_CALLBACK). work: device, 256-byte aligned, >=
+ * sc_solve_mob_work_bytes(n, c->capacity). Returns SC_OK, SC_NOT_CONVERGED,
+ * SC_ERR_NONFINITE, SC_ERR_INVALID, SC_ERR_WORKSPACE, SC_ERR_HIP or the
+ * mobility's own error code. Synchronises `stream` before returning. */
+int sc_solve_lcp_mob(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *opts,
+                     sc_mobility_fn mob, void *mob_ctx, int32_t check_every, double *gamma,
+                     double *g, double *f_c, double *u_c, sc_stats *st, void *work,
+                     size_t work_bytes, void *stream);
 
 /* Static string describing a return code. */
 const char *sc_strerror(int code);

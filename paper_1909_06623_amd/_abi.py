@@ -22,6 +22,7 @@ SC_ERR_TIMEOUT = -7
 SC_OP_AUTO = 0
 SC_OP_CHAIN = 1
 SC_OP_MATRIX = 2
+SC_OP_CALLBACK = 3
 
 c_dp = ctypes.c_void_p  # device pointers travel as plain addresses
 
@@ -98,6 +99,16 @@ class sc_batch_info(ctypes.Structure):
                 ("tune_ms", ctypes.c_float * 6)]
 
 
+class sc_rpy(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("pos", c_dp),
+                ("radius", c_dp), ("mu", ctypes.c_double), ("work", c_dp),
+                ("work_bytes", ctypes.c_size_t)]
+
+
+# int (*)(void *ctx, int32_t n, const double *f, double *u, void *stream)
+MOBILITY_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p)
+
 P = ctypes.POINTER
 SIGNATURES = {
     "sc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
@@ -132,6 +143,13 @@ SIGNATURES = {
     "sc_quat_from_axis": (ctypes.c_int, [ctypes.c_int32, c_dp, c_dp, c_dp]),
     "sc_map_gamma": (ctypes.c_int, [ctypes.c_int32, P(sc_contacts), c_dp, P(sc_contacts),
                                     c_dp, c_dp]),
+    "sc_rpy_work_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "sc_rpy_apply": (ctypes.c_int, [c_dp, ctypes.c_int32, c_dp, c_dp, c_dp]),
+    "sc_dry_apply": (ctypes.c_int, [c_dp, ctypes.c_int32, c_dp, c_dp, c_dp]),
+    "sc_solve_mob_work_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "sc_solve_lcp_mob": (ctypes.c_int, [P(sc_particles), P(sc_contacts), P(sc_solve_opts),
+                                        c_dp, c_dp, ctypes.c_int32, c_dp, c_dp, c_dp, c_dp,
+                                        P(sc_stats), c_dp, ctypes.c_size_t, c_dp]),
     "sc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sc_version": (ctypes.c_int, []),
 }

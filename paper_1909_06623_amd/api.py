@@ -330,6 +330,96 @@ def solve_lcp_adjoint(particles: Particles, box: Box, contacts: Contacts,
     return dq[:nc], dpos, st.as_dict()
 
 
+class RPY:
+    """Rotne-Prager-Yamakawa mobility of spheres in unbounded fluid
+    (``sc_rpy``): translational pair couplings for unequal radii with the
+    overlap forms, single-sphere rotational mobility, evaluated directly on
+    the GPU. ``pos`` is read at every product, so it may be updated in
+    place between solves; ``radius`` are hydrodynamic radii."""
+
+    def __init__(self, pos: torch.Tensor, radius: torch.Tensor, mu: float = 1.0):
+        self.pos = _dev(pos)
+        self.radius = _dev(radius)
+        self.mu = float(mu)
+        n = int(self.pos.shape[0])
+        wb = int(A.lib().sc_rpy_work_bytes(n))
+        self._work = torch.empty(wb + 256, dtype=torch.uint8, device="cuda")
+        addr = self._work.data_ptr()
+        self._wp = (addr + 255) // 256 * 256
+        self._ctx = A.sc_rpy(n, 0, self.pos.data_ptr(), self.radius.data_ptr(), self.mu,
+                             self._wp, wb + 256 - (self._wp - addr))
+
+    @property
+    def n(self):
+        return int(self._ctx.n)
+
+    def fn_ctx(self):
+        """(function address, context address) for sc_solve_lcp_mob."""
+        return (ctypes.cast(A.lib().sc_rpy_apply, ctypes.c_void_p).value,
+                ctypes.addressof(self._ctx))
+
+    def apply(self, f: torch.Tensor) -> torch.Tensor:
+        """u = Mob f for f [n][6]."""
+        f = _dev(f)
+        u = torch.empty_like(f)
+        _check("sc_rpy_apply", A.lib().sc_rpy_apply(ctypes.addressof(self._ctx), self.n,
+                                                    _ptr(f), _ptr(u), _stream()))
+        return u
+
+
+class DryMobility:
+    """The dry block-diagonal mobility of ``particles`` as a mobility
+    function (``sc_dry_apply``)."""
+
+    def __init__(self, particles: Particles):
+        self.P = particles
+        self._ctx = particles.c()
+
+    def fn_ctx(self):
+        return (ctypes.cast(A.lib().sc_dry_apply, ctypes.c_void_p).value,
+                ctypes.addressof(self._ctx))
+
+    def apply(self, f: torch.Tensor) -> torch.Tensor:
+        return apply_mobility(self.P, f)
+
+
+def solve_lcp_mob(particles: Particles, contacts: Contacts, mobility, tol: float = 1e-6,
+                  max_iter: int = 100000, bb: int = 1, gamma0: Optional[torch.Tensor] = None,
+                  want_fc: bool = False, check_every: int = 0,
+                  raise_on_nonconverged: bool = False):
+    """Algorithm 1 with every product D^T Mob D x taking Mob from
+    ``mobility`` (an RPY or DryMobility object, or anything with
+    ``fn_ctx()`` returning an sc_mobility_fn address and its context).
+    Returns (gamma, g, stats dict, f_c, u_c) like solve_lcp."""
+    nc = contacts.count
+    n = particles.n
+    gamma = torch.zeros(max(1, nc), dtype=torch.float64, device="cuda")
+    if gamma0 is not None and nc:
+        gamma[:nc] = _dev(gamma0)
+    g = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
+    f_c = u_c = None
+    if want_fc:
+        f_c = torch.empty((n, 6), dtype=torch.float64, device="cuda")
+        u_c = torch.empty((n, 6), dtype=torch.float64, device="cuda")
+    opts = A.sc_solve_opts(float(tol), int(max_iter), int(bb), 1 if gamma0 is not None else 0,
+                           0, 0, 0, 0, 0, 0, 0)
+    st = A.sc_stats()
+    wb = int(A.lib().sc_solve_mob_work_bytes(n, contacts.capacity))
+    work = torch.empty(wb + 256, dtype=torch.uint8, device="cuda")
+    wp = (work.data_ptr() + 255) // 256 * 256
+    fn, ctx = mobility.fn_ctx()
+    pc, cc = particles.c(), contacts.c()
+    rc = A.lib().sc_solve_lcp_mob(ctypes.byref(pc), ctypes.byref(cc), ctypes.byref(opts),
+                                  ctypes.c_void_p(fn), ctypes.c_void_p(ctx), int(check_every),
+                                  _ptr(gamma), _ptr(g), _ptr(f_c), _ptr(u_c), ctypes.byref(st),
+                                  ctypes.c_void_p(wp), wb + 256 - (wp - work.data_ptr()),
+                                  _stream())
+    allow = (A.SC_OK,) if raise_on_nonconverged else (A.SC_OK, A.SC_NOT_CONVERGED,
+                                                      A.SC_ERR_NONFINITE)
+    _check("sc_solve_lcp_mob", rc, allow)
+    return gamma[:nc], g[:nc], st.as_dict(), f_c, u_c
+
+
 class Batch:
     """Many independent LCPs solved in one persistent launch (one team of
     workgroups per instance at a time, instances taken largest first).

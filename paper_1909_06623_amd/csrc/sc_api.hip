@@ -26,4 +26,4 @@ extern "C" const char *sc_strerror(int code) {
     }
 }
 
-extern "C" int sc_version(void) { return 310; }
+extern "C" int sc_version(void) { return 320; }

@@ -1,0 +1,619 @@
+// sc_mobsolve.hip -- BBPGD (Algorithm 1, section 3.3.1) behind a general
+// mobility, and the Rotne-Prager-Yamakawa mobility of spheres.
+//
+// Section 2 defines the mobility as a dense SPD map from forces and torques to
+// velocities, and in section 3.3 each product M x = D^T Mob D x is one
+// mobility problem for the force D x. Here the mobility is a caller-supplied
+// function (sc_mobility_fn) that enqueues u = Mob f on the solver's stream, so
+// one iteration is a sequence of launches:
+//
+//   scatter: gamma_j = max(0, gamma_{j-1} - alpha g_{j-1}) formed on the fly
+//            for every incidence (the owning incidence stores it) and
+//            F = D gamma_j per particle, in caller order;
+//   mobility: U = Mob F (the callback);
+//   gather:  g_j = D^T U + q per contact, with block partials of
+//            ||min(gamma_j, g_j)||^2, s^T s, s^T y, y^T y and |{gamma_j > 0}|;
+//   finish:  one workgroup folds the partials in a fixed order and decides:
+//            stop, or the next BB step size.
+//
+// The iteration index and the decision live on the device (MsCtrl), so the
+// host enqueues iterations in chunks without waiting; once the finish kernel
+// has set `done`, the remaining launches of the chunk return at once (the
+// callback still runs on stale data, and its results are ignored). The host
+// polls `done` one chunk behind, through pinned memory, so the GPU always has
+// the next chunk queued.
+//
+// RPY (Zuk, Wajnryb, Mizerski and Szymczak, J. Fluid Mech. 2014, unequal
+// radii with the overlap forms): translations couple pairwise, each sphere's
+// rotation has its single-sphere mobility 1/(8 pi mu a^3), and rotations do
+// not couple (this keeps Mob SPD). The pair sum is an O(n^2) tiled N-body
+// kernel on the FP64 vector units: targets one per thread, sources staged
+// through LDS, the source range split over a second grid dimension so that
+// small systems still fill the chip; the splits' partial sums are added in
+// a fixed order, so the result is deterministic.
+#include <cmath>
+
+#include "sc_common.hpp"
+#include "sc_plan.hpp"
+
+namespace sc {
+
+namespace {
+
+struct MsCtrl {
+    double alpha, res;
+    int iters;      // descent steps taken
+    int mvops;      // products M x evaluated before the decision to stop
+    int status;     // SC_OK, SC_NOT_CONVERGED, SC_ERR_NONFINITE
+    int ndegen;
+    int done;       // set once the solve has stopped
+    int n_active;
+    int final_buf;  // buffer (0/1) holding the last iterate
+    int pad;
+};
+
+constexpr int kMsLanes = 4;     // lanes sharing one particle's incidence list
+constexpr int kNV = 5;          // partial sums per gather block
+
+struct MsView {
+    int n, nc;
+    const int *order;       // rank -> caller index
+    const int *inc_ptr;     // [n+1] by rank
+    const int *inc;         // incidence codes 2 l + owner
+    const double *dpm;      // [2 cap][6] signed column entries
+    const int *ci, *cj;     // caller indices (cj < 0: wall)
+    const int *cs;          // [nc][2] ranks
+    const double *pdat;     // [n][8] per rank
+    const double *frame;    // [nc][9]
+    const double *q;
+};
+
+__device__ __forceinline__ double project(double v) { return v < 0.0 ? 0.0 : v; }
+
+// F = D w per particle (caller order). STEP: w_l = max(0, gc_l - alpha ggc_l),
+// stored by the owning incidence into gn; otherwise w = x.
+template <bool STEP>
+__global__ void __launch_bounds__(kBlock)
+k_ms_scatter(MsView V, const double *x, const double *gc, const double *ggc, double *gn,
+             const MsCtrl *ctrl, double *f) {
+    if (STEP && ctrl->done) return;
+    const double alpha = STEP ? ctrl->alpha : 0.0;
+    const int k = (blockIdx.x * kBlock + threadIdx.x) / kMsLanes;
+    const int lane = threadIdx.x % kMsLanes;
+    double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (k < V.n) {
+        const int e1 = V.inc_ptr[k + 1];
+        for (int e = V.inc_ptr[k] + lane; e < e1; e += kMsLanes) {
+            const int code = V.inc[e];
+            const int m = code >> 1;
+            double w;
+            if (STEP) {
+                w = project(gc[m] - alpha * ggc[m]);
+                if (code & 1) gn[m] = w;
+            } else {
+                w = x[m];
+            }
+            const double *d = V.dpm + 6 * static_cast<long long>(e);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) a[c] += w * d[c];
+        }
+    }
+#pragma unroll
+    for (int off = kMsLanes / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a[c] += __shfl_xor(a[c], off, kWave);
+    if (k < V.n && lane == 0) {
+        double *fk = f + 6 * static_cast<long long>(V.order[k]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) fk[c] = a[c];
+    }
+}
+
+// (D^T u)_l with u in caller order.
+__device__ __forceinline__ double dt_u_caller(const MsView &V, const double *u, int l) {
+    const double *fr = V.frame + 9 * static_cast<long long>(l);
+    const double *ui = u + 6 * static_cast<long long>(V.ci[l]);
+    const double vi = -(fr[0] * ui[0] + fr[1] * ui[1] + fr[2] * ui[2]) -
+                      (fr[3] * ui[3] + fr[4] * ui[4] + fr[5] * ui[5]);
+    const int j = V.cj[l];
+    if (j < 0) return vi;  // wall contact: the particle's side only
+    const double *uj = u + 6 * static_cast<long long>(j);
+    return vi + (fr[0] * uj[0] + fr[1] * uj[1] + fr[2] * uj[2]) +
+           (fr[6] * uj[3] + fr[7] * uj[4] + fr[8] * uj[5]);
+}
+
+// D_l^T Mob_self D_l from the particles' own (dry) mobility blocks.
+__device__ __forceinline__ double self_diag(const MsView &V, int l) {
+    const double *fr = V.frame + 9 * static_cast<long long>(l);
+    const V3 nn = load3(fr);
+    V3 u, w;
+    plan_mobility(V.pdat + 8 * static_cast<long long>(V.cs[2 * l]), nn, load3(fr + 3), u, w);
+    double d = dot(nn, u) + dot(load3(fr + 3), w);
+    const int rj = V.cs[2 * l + 1];
+    if (rj >= 0) {
+        plan_mobility(V.pdat + 8 * static_cast<long long>(rj), nn, load3(fr + 6), u, w);
+        d += dot(nn, u) + dot(load3(fr + 6), w);
+    }
+    return d;
+}
+
+enum { kG0 = 0, kAlpha0 = 1, kIter = 2 };
+
+// Block partials of one gather, written to part[blockIdx.x][0..kNV).
+__device__ __forceinline__ void ms_partials(double (&v)[kNV], double *part, bool max4) {
+    __shared__ double red[kNV][kBlock / kWave];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int c = 0; c < kNV; ++c) v[c] = (max4 && c == 4) ? wave_max(v[c]) : wave_sum(v[c]);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < kNV; ++c) red[c][wid] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < kNV; ++c) {
+            double s = red[c][0];
+            for (int w = 1; w < kBlock / kWave; ++w)
+                s = (max4 && c == 4) ? fmax(s, red[c][w]) : s + red[c][w];
+            part[static_cast<long long>(blockIdx.x) * kNV + c] = s;
+        }
+    }
+}
+
+// kG0: out = D^T u + q for gamma = gam; partials (res2, -, -, -, active).
+// kAlpha0: t = D^T u for x = g (= ggc); partials (g.g, g.t, -, -, max self diag).
+// kIter: out = D^T u + q for gamma_j = gam (gamma_{j-1} = gc, g_{j-1} = ggc);
+//        partials (res2, ss, sy, yy, active).
+template <int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_ms_gather(MsView V, const double *u, const double *gam, const double *gc, const double *ggc,
+            double *out, const MsCtrl *ctrl, double *part) {
+    if (MODE != kG0 && ctrl->done) return;
+    double v[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int l = blockIdx.x * kBlock + threadIdx.x; l < V.nc; l += gridDim.x * kBlock) {
+        const double du = dt_u_caller(V, u, l);
+        if (MODE == kAlpha0) {
+            const double gl = ggc[l];
+            v[0] += gl * gl;
+            v[1] += gl * du;
+            v[4] = fmax(v[4], self_diag(V, l));
+        } else {
+            const double gn = du + V.q[l];
+            out[l] = gn;
+            const double gm = gam[l];
+            const double m = gm < gn ? gm : gn;
+            v[0] += m * m;
+            v[4] += gm > 0.0 ? 1.0 : 0.0;
+            if (MODE == kIter) {
+                const double s = gm - gc[l], y = gn - ggc[l];
+                v[1] += s * s;
+                v[2] += s * y;
+                v[3] += y * y;
+            }
+        }
+    }
+    ms_partials(v, part, MODE == kAlpha0);
+}
+
+// One workgroup: fold the gather partials in a fixed order, then decide.
+template <int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_ms_finish(const double *part, int nparts, MsCtrl *ctrl, double tol, int max_iter, int bb) {
+    if (MODE != kG0 && ctrl->done) return;
+    __shared__ double tot[kNV];
+    const int lane = threadIdx.x % kWave, c = threadIdx.x / kWave;
+    // waves 0-3 fold values 0-3, then wave 0 folds value 4
+    for (int pass = 0; pass < 2; ++pass) {
+        const int k = pass == 0 ? c : 4;
+        if (pass == 1 && c != 0) break;
+        if (k < kNV) {
+            const bool mx = MODE == kAlpha0 && k == 4;
+            double x = 0.0;   // the self diagonal is >= 0
+            for (int b = lane; b < nparts; b += kWave) {
+                const double y = part[static_cast<long long>(b) * kNV + k];
+                x = mx ? fmax(x, y) : x + y;
+            }
+            x = mx ? wave_max(x) : wave_sum(x);
+            if (lane == 0) tot[k] = x;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    MsCtrl C = *ctrl;
+    if (MODE == kG0) {
+        C.mvops = 1;
+        C.iters = 0;
+        C.res = sqrt(tot[0]);
+        C.n_active = static_cast<int>(tot[4]);
+        C.final_buf = 0;
+        if (!std::isfinite(C.res)) {
+            C.status = SC_ERR_NONFINITE;
+            C.done = 1;
+        } else if (C.res < tol) {
+            C.status = SC_OK;
+            C.done = 1;
+        } else {
+            C.status = SC_NOT_CONVERGED;
+        }
+    } else if (MODE == kAlpha0) {
+        C.mvops = 2;
+        const double num = tot[0], den = tot[1];
+        if (den > 0.0 && std::isfinite(den) && std::isfinite(num)) {
+            C.alpha = num / den;
+        } else {
+            C.alpha = tot[4] > 0.0 ? 1.0 / tot[4] : 1.0;
+            C.ndegen += 1;
+        }
+        if (max_iter == 0) C.done = 1;
+    } else {
+        const int j = C.iters + 1;
+        C.mvops += 1;
+        C.iters = j;
+        C.final_buf = j & 1;
+        C.res = sqrt(tot[0]);
+        C.n_active = static_cast<int>(tot[4]);
+        if (!std::isfinite(C.res)) {
+            C.status = SC_ERR_NONFINITE;
+            C.done = 1;
+        } else if (C.res < tol) {
+            C.status = SC_OK;
+            C.done = 1;
+        } else {
+            const bool bb2 = bb == 2 || (bb == 3 && (j % 2 == 0));
+            const double num = bb2 ? tot[2] : tot[1];
+            const double den = bb2 ? tot[3] : tot[2];
+            if (den > 0.0 && num > 0.0 && std::isfinite(num) && std::isfinite(den))
+                C.alpha = num / den;
+            else
+                C.ndegen += 1;
+            if (j >= max_iter) C.done = 1;
+        }
+    }
+    *ctrl = C;
+}
+
+// ------------------------------------------------------------------ RPY
+
+constexpr int kRpyBlock = 256;
+constexpr int kRpyMinSources = 64;   // smallest source range of one split
+constexpr int kRpyTargetBlocks = 2048;
+
+struct RpyConst {
+    double k8;      // 1 / (8 pi mu)
+    double k6;      // 1 / (6 pi mu)
+};
+
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// (each roughly squares the relative error of the estimate).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * (1.5 - hx * y * y);
+    y = y * (1.5 - hx * y * y);
+    return y;
+}
+
+// acc += RPY(x_i - x_j; a_i, a_j) F_j (translational coupling, i != j).
+__device__ __forceinline__ void rpy_pair(const RpyConst &K, double dx, double dy, double dz,
+                                         double ai, double aj, double fx, double fy, double fz,
+                                         double &ux, double &uy, double &uz) {
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double sa = ai + aj;
+    double A, B;   // U = A F + B (d.F) d, d unnormalised
+    if (r2 > sa * sa) {
+        const double ri = rsqrt_nr(r2);
+        const double ri2 = ri * ri;
+        const double s2 = (ai * ai + aj * aj) * ri2;
+        const double c = K.k8 * ri;
+        A = c * (1.0 + s2 * (1.0 / 3.0));
+        B = c * (1.0 - s2) * ri2;
+    } else {
+        const double da = ai - aj;
+        if (r2 > da * da) {
+            const double r = sqrt(r2);
+            const double pre = K.k6 / (ai * aj);
+            const double dd = da * da;
+            const double t = dd + 3.0 * r2;
+            const double r3 = r2 * r;
+            A = pre * (16.0 * r3 * sa - t * t) / (32.0 * r3);
+            const double w = dd - r2;
+            B = pre * 3.0 * w * w / (32.0 * r3) / r2;
+        } else {
+            A = K.k6 / (ai > aj ? ai : aj);
+            B = 0.0;
+        }
+    }
+    const double dF = dx * fx + dy * fy + dz * fz;
+    const double bd = B * dF;
+    ux += A * fx + bd * dx;
+    uy += A * fy + bd * dy;
+    uz += A * fz + bd * dz;
+}
+
+__global__ void __launch_bounds__(kRpyBlock)
+k_rpy_pairs(int n, const double *__restrict__ pos, const double *__restrict__ rad,
+            const double *__restrict__ f, RpyConst K, int splits, double *__restrict__ part) {
+    __shared__ double sx[kRpyBlock], sy[kRpyBlock], sz[kRpyBlock], sa[kRpyBlock];
+    __shared__ double sfx[kRpyBlock], sfy[kRpyBlock], sfz[kRpyBlock];
+    const int i = blockIdx.x * kRpyBlock + threadIdx.x;
+    const int s = blockIdx.y;
+    const int j0 = static_cast<int>(static_cast<long long>(s) * n / splits);
+    const int j1 = static_cast<int>(static_cast<long long>(s + 1) * n / splits);
+    const bool live = i < n;
+    const double xi = live ? pos[3 * i] : 0.0, yi = live ? pos[3 * i + 1] : 0.0,
+                 zi = live ? pos[3 * i + 2] : 0.0, ai = live ? rad[i] : 1.0;
+    double ux = 0.0, uy = 0.0, uz = 0.0;
+    for (int t = j0; t < j1; t += kRpyBlock) {
+        const int cnt = j1 - t < kRpyBlock ? j1 - t : kRpyBlock;
+        __syncthreads();
+        if (threadIdx.x < cnt) {
+            const int j = t + threadIdx.x;
+            sx[threadIdx.x] = pos[3 * j];
+            sy[threadIdx.x] = pos[3 * j + 1];
+            sz[threadIdx.x] = pos[3 * j + 2];
+            sa[threadIdx.x] = rad[j];
+            sfx[threadIdx.x] = f[6 * static_cast<long long>(j)];
+            sfy[threadIdx.x] = f[6 * static_cast<long long>(j) + 1];
+            sfz[threadIdx.x] = f[6 * static_cast<long long>(j) + 2];
+        }
+        __syncthreads();
+        for (int m = 0; m < cnt; ++m) {
+            if (t + m == i) continue;
+            rpy_pair(K, xi - sx[m], yi - sy[m], zi - sz[m], ai, sa[m], sfx[m], sfy[m], sfz[m],
+                     ux, uy, uz);
+        }
+    }
+    if (live) {
+        double *p = part + 3 * (static_cast<long long>(s) * n + i);
+        p[0] = ux;
+        p[1] = uy;
+        p[2] = uz;
+    }
+}
+
+__global__ void k_rpy_finish(int n, const double *rad, const double *f, RpyConst K, int splits,
+                             const double *part, double *u) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a = rad[i];
+    const double *fi = f + 6 * static_cast<long long>(i);
+    const double st = K.k6 / a, sr = 0.75 * K.k6 / (a * a * a);  // 1/(6 pi mu a), 1/(8 pi mu a^3)
+    double ux = st * fi[0], uy = st * fi[1], uz = st * fi[2];
+    for (int s = 0; s < splits; ++s) {
+        const double *p = part + 3 * (static_cast<long long>(s) * n + i);
+        ux += p[0];
+        uy += p[1];
+        uz += p[2];
+    }
+    double *ui = u + 6 * static_cast<long long>(i);
+    ui[0] = ux;
+    ui[1] = uy;
+    ui[2] = uz;
+    ui[3] = sr * fi[3];
+    ui[4] = sr * fi[4];
+    ui[5] = sr * fi[5];
+}
+
+int rpy_splits(int n) {
+    const int bx = grid_for(n, kRpyBlock);
+    int s = (kRpyTargetBlocks + bx - 1) / bx;
+    const int smax = (n + kRpyMinSources - 1) / kRpyMinSources;
+    if (s > smax) s = smax;
+    return s < 1 ? 1 : s;
+}
+
+// ------------------------------------------------------------------ host
+
+// Host copies of the control block, one per chunk parity, in pinned memory
+// (allocated once per host thread, kept for the life of the process).
+MsCtrl *pinned_ctrl() {
+    thread_local MsCtrl *p = nullptr;
+    if (!p && hipHostMalloc(reinterpret_cast<void **>(&p), 2 * sizeof(MsCtrl),
+                            hipHostMallocDefault) != hipSuccess)
+        p = nullptr;
+    return p;
+}
+
+struct Events {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};  // t0, t1, chunk parity 0, 1
+    bool ok = true;
+    Events() {
+        for (int k = 0; k < 4; ++k)
+            if (hipEventCreateWithFlags(&e[k], k < 2 ? hipEventDefault : hipEventDisableTiming) !=
+                hipSuccess) {
+                e[k] = nullptr;
+                ok = false;
+            }
+    }
+    ~Events() {
+        for (auto ev : e)
+            if (ev) (void)hipEventDestroy(ev);
+    }
+};
+
+size_t ms_ws_bytes(int32_t n, int32_t cap) {
+    const size_t nn = static_cast<size_t>(n), cc = static_cast<size_t>(cap);
+    size_t b = 0;
+    b += 2 * align_up(cc * sizeof(double), 256);       // second gamma / g buffers
+    b += 2 * align_up(6 * nn * sizeof(double), 256);   // F, U (caller order)
+    b += align_up(kNV * kMaxReduceBlocks * sizeof(double), 256);
+    b += align_up(sizeof(MsCtrl), 256);
+    return b + 1024;
+}
+
+}  // namespace
+
+}  // namespace sc
+
+using namespace sc;
+
+extern "C" size_t sc_rpy_work_bytes(int32_t n) {
+    if (n <= 0) return 256;
+    return align_up(3 * sizeof(double) * static_cast<size_t>(rpy_splits(n)) * n, 256) + 256;
+}
+
+extern "C" int sc_rpy_apply(void *ctx, int32_t n, const double *f, double *u, void *stream) {
+    const sc_rpy *R = static_cast<const sc_rpy *>(ctx);
+    if (!R || n < 0 || n != R->n || !(R->mu > 0.0) || !std::isfinite(R->mu)) return SC_ERR_INVALID;
+    if (n == 0) return SC_OK;
+    if (!R->pos || !R->radius || !f || !u) return SC_ERR_INVALID;
+    if (!R->work || (reinterpret_cast<uintptr_t>(R->work) & 255) != 0 ||
+        R->work_bytes < sc_rpy_work_bytes(n))
+        return SC_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int splits = rpy_splits(n);
+    const RpyConst K{1.0 / (8.0 * M_PI * R->mu), 1.0 / (6.0 * M_PI * R->mu)};
+    double *part = static_cast<double *>(R->work);
+    const dim3 grid(grid_for(n, kRpyBlock), splits);
+    k_rpy_pairs<<<grid, kRpyBlock, 0, s>>>(n, R->pos, R->radius, f, K, splits, part);
+    k_rpy_finish<<<grid_for(n), kBlock, 0, s>>>(n, R->radius, f, K, splits, part, u);
+    SC_HIP_TRY(hipGetLastError());
+    return SC_OK;
+}
+
+extern "C" int sc_dry_apply(void *ctx, int32_t n, const double *f, double *u, void *stream) {
+    const sc_particles *p = static_cast<const sc_particles *>(ctx);
+    if (!p || n != p->n) return SC_ERR_INVALID;
+    return sc_apply_mobility(p, f, u, stream);
+}
+
+extern "C" size_t sc_solve_mob_work_bytes(int32_t n, int32_t capacity) {
+    if (n < 0 || capacity < 0) return 0;
+    return ms_ws_bytes(n, capacity);
+}
+
+extern "C" int sc_solve_lcp_mob(const sc_particles *p, const sc_contacts *c,
+                                const sc_solve_opts *opts, sc_mobility_fn mob, void *mob_ctx,
+                                int32_t check_every, double *gamma, double *g, double *f_c,
+                                double *u_c, sc_stats *st, void *ws, size_t ws_bytes,
+                                void *stream_) {
+    if (!p || !c || !opts || !st || !mob || p->n < 0 || c->count < 0 || c->count > c->capacity)
+        return SC_ERR_INVALID;
+    if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->bb < 1 || opts->bb > 3 ||
+        check_every < 0 || check_every > 4096)
+        return SC_ERR_INVALID;
+    Plan pl;
+    if (!carve_plan(c->plan, c->plan_bytes, p->n, c->capacity, pl)) return SC_ERR_INVALID;
+    const int n = p->n, nc = c->count;
+    if (nc > 0 && (!c->ci || !c->cj || !c->frame || !c->q || !gamma || !g)) return SC_ERR_INVALID;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 ||
+        ws_bytes < ms_ws_bytes(n, c->capacity))
+        return SC_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream_);
+    *st = sc_stats{};
+    Carver cv{static_cast<char *>(ws), ws_bytes};
+    double *gam1 = cv.take<double>(static_cast<size_t>(c->capacity));
+    double *g1 = cv.take<double>(static_cast<size_t>(c->capacity));
+    double *F = cv.take<double>(6 * static_cast<size_t>(n));
+    double *U = cv.take<double>(6 * static_cast<size_t>(n));
+    double *part = cv.take<double>(kNV * static_cast<size_t>(kMaxReduceBlocks));
+    MsCtrl *ctrl = cv.take<MsCtrl>(1);
+    if (!cv.ok) return SC_ERR_WORKSPACE;
+
+    if (nc == 0) {
+        // no constraints: the zero force; U_c = Mob 0 = 0
+        if (f_c) SC_HIP_TRY(hipMemsetAsync(f_c, 0, 6 * sizeof(double) * n, s));
+        if (u_c) SC_HIP_TRY(hipMemsetAsync(u_c, 0, 6 * sizeof(double) * n, s));
+        SC_HIP_TRY(hipStreamSynchronize(s));
+        st->status = SC_OK;
+        st->mvops = 1;
+        return SC_OK;
+    }
+    MsCtrl *hctrl = pinned_ctrl();
+    Events ev;
+    if (!hctrl || !ev.ok) return SC_ERR_HIP;
+    hipEvent_t t0 = ev.e[0], t1 = ev.e[1];
+
+    const MsView V{n, nc, pl.order, pl.inc_ptr, pl.inc, pl.dpm, c->ci, c->cj, pl.cs, pl.pdat,
+                   c->frame, c->q};
+    double *gam[2] = {gamma, gam1};
+    double *gg[2] = {g, g1};
+    const int sb = grid_for(static_cast<long long>(n) * kMsLanes);
+    int gb = grid_for(nc);
+    if (gb > kMaxReduceBlocks) gb = kMaxReduceBlocks;
+    const double tol = opts->tol;
+    const int max_iter = opts->max_iter, bb = opts->bb;
+    const int K = check_every > 0 ? check_every : 4;
+
+    if (!opts->warm_start) SC_HIP_TRY(hipMemsetAsync(gamma, 0, sizeof(double) * nc, s));
+    SC_HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(MsCtrl), s));
+    SC_HIP_TRY(hipEventRecord(t0, s));
+    int rc = SC_OK;
+    // g0 = M gamma0 + q
+    k_ms_scatter<false><<<sb, kBlock, 0, s>>>(V, gamma, nullptr, nullptr, nullptr, ctrl, F);
+    rc = mob(mob_ctx, n, F, U, s);
+    if (rc) return rc;
+    k_ms_gather<kG0><<<gb, kBlock, 0, s>>>(V, U, gamma, nullptr, nullptr, g, ctrl, part);
+    k_ms_finish<kG0><<<1, kBlock, 0, s>>>(part, gb, ctrl, tol, max_iter, bb);
+    // alpha0 = g0^T g0 / g0^T M g0 (skipped on the device once done)
+    k_ms_scatter<false><<<sb, kBlock, 0, s>>>(V, g, nullptr, nullptr, nullptr, ctrl, F);
+    rc = mob(mob_ctx, n, F, U, s);
+    if (rc) return rc;
+    k_ms_gather<kAlpha0><<<gb, kBlock, 0, s>>>(V, U, nullptr, nullptr, g, nullptr, ctrl, part);
+    k_ms_finish<kAlpha0><<<1, kBlock, 0, s>>>(part, gb, ctrl, tol, max_iter, bb);
+    SC_HIP_TRY(hipGetLastError());
+    // a gamma0 that already meets the tolerance needs no iteration: wait once
+    SC_HIP_TRY(hipMemcpyAsync(&hctrl[1], ctrl, sizeof(MsCtrl), hipMemcpyDeviceToHost, s));
+    SC_HIP_TRY(hipEventRecord(ev.e[3], s));
+    SC_HIP_TRY(hipEventSynchronize(ev.e[3]));
+    bool stop = hctrl[1].done != 0;
+
+    // iterations in chunks of K; `done` is read one chunk behind, so the
+    // GPU always has the next chunk queued
+    int chunk = 0;
+    for (int j0 = 1; j0 <= max_iter && !stop; j0 += K, ++chunk) {
+        const int j1 = j0 + K - 1 < max_iter ? j0 + K - 1 : max_iter;
+        for (int j = j0; j <= j1; ++j) {
+            const int cur = (j - 1) & 1, nxt = j & 1;
+            k_ms_scatter<true><<<sb, kBlock, 0, s>>>(V, nullptr, gam[cur], gg[cur], gam[nxt],
+                                                     ctrl, F);
+            rc = mob(mob_ctx, n, F, U, s);
+            if (rc) return rc;
+            k_ms_gather<kIter><<<gb, kBlock, 0, s>>>(V, U, gam[nxt], gam[cur], gg[cur],
+                                                     gg[nxt], ctrl, part);
+            k_ms_finish<kIter><<<1, kBlock, 0, s>>>(part, gb, ctrl, tol, max_iter, bb);
+        }
+        SC_HIP_TRY(hipGetLastError());
+        const int slot = chunk & 1;
+        SC_HIP_TRY(hipMemcpyAsync(&hctrl[slot], ctrl, sizeof(MsCtrl), hipMemcpyDeviceToHost, s));
+        SC_HIP_TRY(hipEventRecord(ev.e[2 + slot], s));
+        if (chunk > 0) {
+            SC_HIP_TRY(hipEventSynchronize(ev.e[2 + (slot ^ 1)]));
+            if (hctrl[slot ^ 1].done) stop = true;
+        }
+    }
+    SC_HIP_TRY(hipEventRecord(t1, s));
+    MsCtrl hc;
+    SC_HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(MsCtrl), hipMemcpyDeviceToHost, s));
+    SC_HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0.0f;
+    SC_HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+    if (hc.final_buf == 1) {
+        SC_HIP_TRY(hipMemcpyAsync(gamma, gam1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+        SC_HIP_TRY(hipMemcpyAsync(g, g1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+    }
+    if (f_c || u_c) {
+        double *fo = f_c ? f_c : F;
+        k_ms_scatter<false><<<sb, kBlock, 0, s>>>(V, gamma, nullptr, nullptr, nullptr, ctrl, fo);
+        SC_HIP_TRY(hipGetLastError());
+        if (u_c) {
+            rc = mob(mob_ctx, n, fo, u_c, s);
+            if (rc) return rc;
+        }
+    }
+    SC_HIP_TRY(hipStreamSynchronize(s));
+    SC_HIP_TRY(hipGetLastError());
+    st->status = hc.status;
+    st->iters = hc.iters;
+    st->mvops = hc.mvops;
+    st->n_active = hc.n_active;
+    st->residual = hc.res;
+    st->alpha = hc.alpha;
+    st->n_degenerate = hc.ndegen;
+    st->kernel_ms = ms;
+    st->grid = gb;
+    st->block = kBlock;
+    st->lanes_per_particle = kMsLanes;
+    st->op = SC_OP_CALLBACK;
+    return hc.status;
+}

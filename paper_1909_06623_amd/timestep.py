@@ -13,8 +13,8 @@ from typing import Optional
 import torch
 
 from . import _abi as A
-from .api import (Box, Contacts, Particles, Workspace, _check, _dev, _ptr, _stream,
-                  apply_mobility, build_contacts, solve_lcp)
+from .api import (RPY, Box, Contacts, Particles, Workspace, _check, _dev, _ptr, _stream,
+                  apply_mobility, build_contacts, solve_lcp, solve_lcp_mob)
 
 
 def quat_from_axis(axis: torch.Tensor) -> torch.Tensor:
@@ -56,11 +56,14 @@ class TimeStepper:
     """Euler steps of ``particles`` (whose pos and axis tensors are updated in
     place) under external forces ``f_ext`` [n][6] with time step ``dt`` and
     pair threshold ``delta``. ``warm_start``: gamma_0 of each step from the
-    previous step's solution."""
+    previous step's solution. ``hydro_radius``: the mobility is the RPY
+    mobility of spheres of these hydrodynamic radii and viscosity ``mu``
+    (every product through ``solve_lcp_mob``) instead of the dry mobility."""
 
     def __init__(self, particles: Particles, box: Box, delta: float, dt: float,
                  f_ext: torch.Tensor, tol: float = 1e-6, warm_start: bool = True,
-                 max_iter: int = 100000):
+                 max_iter: int = 100000, hydro_radius: Optional[torch.Tensor] = None,
+                 mu: float = 1.0):
         self.P = particles
         self.box = box
         self.delta = float(delta)
@@ -73,16 +76,24 @@ class TimeStepper:
         self.ws = Workspace()
         self.prev: Optional[Contacts] = None
         self.prev_gamma: Optional[torch.Tensor] = None
+        # reads particles.pos at every product, which the steps update in place
+        self.rpy = None if hydro_radius is None else RPY(particles.pos, hydro_radius, mu)
 
     def step(self) -> StepInfo:
         P = self.P
-        u_nc = apply_mobility(P, self.f_ext)
-        con = build_contacts(P, self.box, self.delta, u_nc, self.dt, workspace=self.ws)
+        u_nc = apply_mobility(P, self.f_ext) if self.rpy is None else self.rpy.apply(self.f_ext)
+        con = build_contacts(P, self.box, self.delta, u_nc, self.dt, workspace=self.ws,
+                             assemble=self.rpy is None)
         gamma0 = None
         if self.warm and self.prev is not None and con.count:
             gamma0 = map_gamma(P.n, self.prev, self.prev_gamma, con)
-        gamma, g, st, f_c, u_c = solve_lcp(P, con, tol=self.tol, max_iter=self.max_iter,
-                                           gamma0=gamma0, want_fc=True, workspace=self.ws)
+        if self.rpy is None:
+            gamma, g, st, f_c, u_c = solve_lcp(P, con, tol=self.tol, max_iter=self.max_iter,
+                                               gamma0=gamma0, want_fc=True, workspace=self.ws)
+        else:
+            gamma, g, st, f_c, u_c = solve_lcp_mob(P, con, self.rpy, tol=self.tol,
+                                                   max_iter=self.max_iter, gamma0=gamma0,
+                                                   want_fc=True)
         advance(P, self.quat, u_nc, u_c, self.dt)
         self.prev, self.prev_gamma = con, gamma
         return StepInfo(con, gamma, st, u_c)

@@ -1,0 +1,197 @@
+"""Algorithm 1 behind a general mobility on the GPU (sc_solve_lcp_mob) and
+the RPY mobility (sc_rpy_apply), against the oracle: RPY products on
+several tiles with a ragged tail and on sampled rows of a 20000-sphere
+cluster, solves through the dry mobility against the persistent solver and
+the C oracle, solves through RPY against Algorithm 1 on the oracle's
+explicit M, edge cases, and time steps of the sedimenting cluster of
+section 6.3."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+import oracle.hydro as OM  # noqa: E402
+import oracle.timestep as T  # noqa: E402
+import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _free_spheres(n, seed, phi=0.3):
+    s = W.spheres(n, phi, seed)
+    s.periodic = 0
+    return s
+
+
+def _gpu(s):
+    import paper_1909_06623_amd as sc
+    P = sc.Particles.from_suspension(s)
+    box = sc.Box(tuple(s.box), periodic=bool(s.periodic), walls=s.walls, lo=tuple(s.lo))
+    return P, box
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 300, 1100])
+def test_rpy_products_match_oracle(n):
+    import paper_1909_06623_amd as sc
+    rng = np.random.default_rng(n)
+    pos = rng.uniform(0.0, 1.2 * max(1.0, n ** (1 / 3)), (n, 3))
+    rad = rng.uniform(0.2, 0.7, n)
+    if n >= 7:
+        pos[1] = pos[0] + [0.02, 0.0, 0.0]    # nearly contained
+        rad[0], rad[1] = 0.7, 0.2
+        pos[3] = pos[2]                        # a small sphere at a larger one's centre
+        rad[2], rad[3] = 0.6, 0.25
+        pos[5] = pos[4] + [0.9, 0.0, 0.0]      # overlapping
+        rad[4], rad[5] = 0.5, 0.5
+    F = rng.standard_normal((n, 6))
+    _say(f"rpy product n={n}")
+    R = sc.RPY(torch.from_numpy(pos).cuda(), torch.from_numpy(rad).cuda(), mu=1.7)
+    U = R.apply(torch.from_numpy(F).cuda()).cpu().numpy()
+    Uo = (OM.rpy_dense(pos, rad, 1.7) @ F.ravel()).reshape(n, 6)
+    np.testing.assert_allclose(U, Uo, rtol=0, atol=1e-13 * np.abs(Uo).max())
+
+
+def test_rpy_product_sampled_rows_of_a_large_cluster():
+    import paper_1909_06623_amd as sc
+    s = W.sphere_cluster(20000, W.SEED_BASE + 901)
+    rng = np.random.default_rng(5)
+    F = rng.standard_normal((s.n, 6))
+    _say("rpy product, 20000-sphere cluster, sampled rows")
+    R = sc.RPY(torch.from_numpy(s.pos).cuda(), torch.from_numpy(s.hydro_radius).cuda())
+    U = R.apply(torch.from_numpy(F).cuda()).cpu().numpy()
+    rows = rng.choice(s.n, 60, replace=False)
+    for i in rows:
+        acc = F[i, :3] / (6.0 * math.pi * s.hydro_radius[i])
+        for j in range(s.n):
+            if j != i:
+                acc = acc + OM.rpy_block(s.pos[i] - s.pos[j], s.hydro_radius[i],
+                                         s.hydro_radius[j]) @ F[j, :3]
+        np.testing.assert_allclose(U[i, :3], acc, rtol=0, atol=1e-12 * np.abs(acc).max())
+        np.testing.assert_allclose(U[i, 3:], F[i, 3:] / (8.0 * math.pi), rtol=1e-14)
+
+
+@pytest.mark.parametrize("bb", [1, 2, 3])
+def test_dry_callback_equals_persistent_solver(bb):
+    import paper_1909_06623_amd as sc
+    s = W.rods_and_spheres(1500, 300, seed=W.SEED_BASE + 905)
+    _say(f"dry mobility through the callback, bb={bb}")
+    P, box = _gpu(s)
+    u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt)
+    gam_p, g_p, st_p, f_p, _ = sc.solve_lcp(P, con, tol=1e-10, bb=bb, want_fc=True)
+    gam, g, st, f_c, u_c = sc.solve_lcp_mob(P, con, sc.DryMobility(P), tol=1e-10, bb=bb,
+                                            want_fc=True)
+    assert st["status"] == 0 and st_p["status"] == 0 and st["op"] == 3
+    assert abs(st["iters"] - st_p["iters"]) <= max(20, st_p["iters"] // 3)
+    assert st["mvops"] == st["iters"] + 2
+    sc_ = max(1.0, float(g_p.abs().max()))
+    assert float((g - g_p).abs().max()) < 1e-6 * sc_
+    np.testing.assert_allclose(f_c.cpu().numpy(), f_p.cpu().numpy(), rtol=0,
+                               atol=1e-6 * float(f_p.abs().max()))
+    np.testing.assert_allclose(u_c.cpu().numpy(), sc.apply_mobility(P, f_c).cpu().numpy(),
+                               rtol=1e-14, atol=0)
+    # and the C oracle
+    c, _, q = O.setup(s)
+    pm = con.canonical_order().cpu().numpy()
+    go, g_o, _ = O.bbpgd(s, c, q, tol=1e-10, bb=bb)
+    np.testing.assert_allclose(g.cpu().numpy()[pm], g_o, rtol=0,
+                               atol=1e-6 * max(1.0, np.abs(g_o).max()))
+
+
+@pytest.mark.parametrize("n", [300, 900])
+def test_rpy_solve_matches_oracle(n):
+    import paper_1909_06623_amd as sc
+    s = _free_spheres(n, W.SEED_BASE + 906 + n)
+    _say(f"rpy solve, {n} overlapping spheres in free space")
+    P, box = _gpu(s)
+    R = sc.RPY(P.pos, P.radius)
+    u_nc = R.apply(torch.from_numpy(s.f_ext).cuda())
+    Mob = OM.rpy_dense(s.pos, s.radius)
+    u_o = (Mob @ s.f_ext.ravel()).reshape(s.n, 6)
+    np.testing.assert_allclose(u_nc.cpu().numpy(), u_o, rtol=0, atol=1e-13 * np.abs(u_o).max())
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, assemble=False)
+    c = O.find_contacts(s)
+    q_o = O.build_q(c, u_o, s.dt)
+    pm = con.canonical_order().cpu().numpy()
+    assert con.count == c.nc
+    np.testing.assert_allclose(con.q[: con.count].cpu().numpy()[pm], q_o, rtol=0,
+                               atol=1e-11 * np.abs(q_o).max())
+    gam, g, st, f_c, u_c = sc.solve_lcp_mob(P, con, R, tol=1e-10, want_fc=True)
+    assert st["status"] == 0 and st["n_active"] > 30
+    M = OM.contact_matrix(O.D_matrix(s.n, c), Mob)
+    go, g_o, sto = OM.bbpgd_dense(M, q_o, O.M_diag(s, c), tol=1e-10)
+    assert sto.status == 0
+    sc_ = max(1.0, np.abs(go).max())
+    np.testing.assert_allclose(gam.cpu().numpy()[pm], go, rtol=0, atol=1e-6 * sc_)
+    np.testing.assert_allclose(g.cpu().numpy()[pm], g_o, rtol=0, atol=1e-6 * sc_)
+    gg = g.cpu().numpy()
+    assert float(gam.min()) >= 0.0 and gg.min() > -1e-9
+    F_o = O.D_apply(s.n, c, go)
+    np.testing.assert_allclose(f_c.cpu().numpy(), F_o, rtol=0, atol=1e-6 * np.abs(F_o).max())
+    U_o = (Mob @ F_o.ravel()).reshape(s.n, 6)
+    np.testing.assert_allclose(u_c.cpu().numpy(), U_o, rtol=0, atol=1e-6 * np.abs(U_o).max())
+
+
+def test_mob_solve_edge_cases():
+    import paper_1909_06623_amd as sc
+    import paper_1909_06623_amd._abi as A
+    s = _free_spheres(200, W.SEED_BASE + 907)
+    _say("mobility solve edge cases")
+    P, box = _gpu(s)
+    R = sc.RPY(P.pos, P.radius)
+    u_nc = R.apply(torch.from_numpy(s.f_ext).cuda())
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, assemble=False)
+    gam, g, st, _, _ = sc.solve_lcp_mob(P, con, R, tol=1e-10)
+    assert st["status"] == 0
+    # warm start at the solution: one product, no step
+    gam2, g2, st2, _, _ = sc.solve_lcp_mob(P, con, R, tol=1e-6, gamma0=gam)
+    assert (st2["status"], st2["iters"], st2["mvops"]) == (0, 0, 1)
+    assert torch.equal(gam2, gam)
+    # max_iter = 0: not converged after the two start-up products
+    _, _, st0, _, _ = sc.solve_lcp_mob(P, con, R, tol=1e-10, max_iter=0)
+    assert (st0["status"], st0["iters"], st0["mvops"]) == (A.SC_NOT_CONVERGED, 0, 2)
+    # a cap reached: status, iteration count and MVOPs agree with the cap
+    _, _, st3, _, _ = sc.solve_lcp_mob(P, con, R, tol=1e-14, max_iter=7, check_every=3)
+    assert (st3["status"], st3["iters"], st3["mvops"]) == (A.SC_NOT_CONVERGED, 7, 9)
+    # chunk sizes do not change the result
+    gam4, _, st4, _, _ = sc.solve_lcp_mob(P, con, R, tol=1e-10, check_every=1)
+    gam5, _, st5, _, _ = sc.solve_lcp_mob(P, con, R, tol=1e-10, check_every=64)
+    assert torch.equal(gam4, gam) and torch.equal(gam5, gam)
+    assert st4["iters"] == st5["iters"] == st["iters"]
+    # no contacts
+    far = W.Suspension("far", np.array([[0.0, 0, 0], [5.0, 0, 0]]), np.tile([0, 0, 1.0], (2, 1)),
+                       np.full(2, 0.5), np.zeros(2), W.sphere_mobility(np.full(2, 0.5)),
+                       np.ones((2, 6)), np.full(3, 10.0), 0.1, 0.01, 1e-6, periodic=0)
+    P2, box2 = _gpu(far)
+    R2 = sc.RPY(P2.pos, P2.radius)
+    con2 = sc.build_contacts(P2, box2, far.delta, R2.apply(torch.ones(2, 6).cuda()), far.dt)
+    assert con2.count == 0
+    _, _, st6, f6, u6 = sc.solve_lcp_mob(P2, con2, R2, want_fc=True)
+    assert st6["status"] == 0 and float(f6.abs().max()) == 0.0 and float(u6.abs().max()) == 0.0
+
+
+def test_cluster_steps_match_oracle():
+    """Five steps of the section 6.3 cluster (squeezed, so that contacts
+    carry force) with the RPY mobility: GPU positions follow the oracle's."""
+    from paper_1909_06623_amd import timestep as ts
+    import paper_1909_06623_amd as sc
+    s = W.sphere_cluster(1000, W.SEED_BASE + 908, squeeze=3.0, tol=1e-10)
+    _say("cluster time steps with RPY, GPU vs oracle")
+    P, box = _gpu(s)
+    stp = ts.TimeStepper(P, box, s.delta, s.dt, torch.from_numpy(s.f_ext).cuda(), tol=1e-10,
+                         hydro_radius=torch.from_numpy(s.hydro_radius).cuda())
+    quat, rec = T.quat_from_axis(s.axis), None
+    for k in range(5):
+        info = stp.step()
+        s, quat, rec = T.step(s, quat, rec, hydro="rpy")
+        assert info.stats["status"] == 0 and rec.status == 0
+        assert info.contacts.count == rec.i.size
+        np.testing.assert_allclose(P.pos.cpu().numpy(), s.pos, rtol=0, atol=1e-9)
+    assert float(-P.pos[:, 2].mean()) > 0.0
