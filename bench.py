@@ -95,6 +95,107 @@ def timestepping(sc, W, torch, np, steps):
     return out
 
 
+# FP64 operations of one ordered pair of the RPY sum as the kernel evaluates
+# the far-field branch (every add, multiply and the square-root estimate
+# counted once, a fused multiply-add as two): difference 3, r^2 5, radius
+# test 2, 1/r with two Newton steps 10, coefficients 12, d.F 5, update 13.
+RPY_FLOPS_PER_PAIR = 50
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def hydro(sc, W, torch, np, steps):
+    """The solve behind a non-diagonal mobility (RPY): the RPY product on a
+    20,000-sphere cluster (ALU roofline of the pair kernel), a solve through
+    RPY of 20,000 overlapping spheres in free space, and time steps of the
+    1000-sphere sedimenting cluster of section 6.3 (and of a 20,000-sphere
+    one)."""
+    from paper_1909_06623_amd import timestep as ts
+    out = {}
+    s = W.sphere_cluster(20000, W.SEED_BASE + 901)
+    R = sc.RPY(torch.from_numpy(s.pos).cuda(), torch.from_numpy(s.hydro_radius).cuda())
+    F = torch.from_numpy(np.random.default_rng(1).standard_normal((s.n, 6))).cuda()
+    # one product captured in a HIP graph (its two kernels, no memset) and
+    # replayed, so that host-side call overhead stays out of the timing
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            R.apply(F)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        U_g = R.apply(F)
+    U_e = R.apply(F)
+    graph.replay()
+    torch.cuda.synchronize()
+    if not torch.equal(U_g, U_e):
+        raise RuntimeError("graph replay of the RPY product differs from the eager call")
+    # warm replays first (about 20 ms of FP64 work: the first products after
+    # the memory-bound legs run at lower clocks), then the timed ones
+    for _ in range(40):
+        graph.replay()
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = RPY_FLOPS_PER_PAIR * s.n * (s.n - 1)
+    tf = flops / (ms * 1e-3) / 1e12
+    out["rpy_product"] = {
+        "workload": "20000-sphere cluster (section 6.3 recipe), random forces",
+        "n": s.n, "ms": ms, "pairs_per_s": s.n * (s.n - 1) / (ms * 1e-3),
+        "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_rpy_pairs + k_rpy_finish (one sc_rpy_apply, HIP graph "
+                               "replays)",
+                     "flops_model": f"{RPY_FLOPS_PER_PAIR} FP64 flops per ordered pair"}}
+
+    s = W.spheres(20000, 0.3, W.SEED_BASE + 909)
+    s.periodic = 0
+    P = sc.Particles.from_suspension(s)
+    box = sc.Box(tuple(s.box), periodic=False)
+    R = sc.RPY(P.pos, P.radius)
+    u_nc = R.apply(torch.from_numpy(s.f_ext).cuda())
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, assemble=False)
+    sc.solve_lcp_mob(P, con, R, tol=s.tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gam, g, st, _, _ = sc.solve_lcp_mob(P, con, R, tol=s.tol)
+    wall = 1e3 * (time.perf_counter() - t0)
+    out["solve_rpy"] = {
+        "workload": "20000 overlapping spheres (phi 0.3, uniform centres) in free space, "
+                    "RPY mobility, BB1 to 1e-6",
+        "n": s.n, "n_contacts": con.count, "status": st["status"], "iters": st["iters"],
+        "mvops": st["mvops"], "n_active": st["n_active"], "solve_ms": wall,
+        "gpu_ms": st["kernel_ms"], "ms_per_product": st["kernel_ms"] / max(1, st["mvops"]),
+        "rpy_share": min(1.0, ms * st["mvops"] / max(1e-9, st["kernel_ms"]))}
+
+    for n, nsteps in ((1000, steps), (20000, max(2, steps // 4))):
+        s = W.sphere_cluster(n, W.SEED_BASE + 900 + (n == 20000))
+        P = sc.Particles.from_suspension(s)
+        box = sc.Box(tuple(s.box), lo=tuple(s.lo), periodic=False)
+        stp = ts.TimeStepper(P, box, s.delta, s.dt, torch.from_numpy(s.f_ext).cuda(), tol=s.tol,
+                             hydro_radius=torch.from_numpy(s.hydro_radius).cuda())
+        stp.step()
+        z0 = float(P.pos[:, 2].mean())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [stp.step() for _ in range(nsteps)]
+        torch.cuda.synchronize()
+        z1 = float(P.pos[:, 2].mean())
+        out[f"cluster{n}_steps"] = {
+            "steps": nsteps, "ms_per_step": 1e3 * (time.perf_counter() - t0) / nsteps,
+            "iters": [x.stats["iters"] for x in infos],
+            "contacts": [x.contacts.count for x in infos],
+            "active": [x.stats["n_active"] for x in infos],
+            "mean_fall_speed": (z0 - z1) / (nsteps * s.dt),
+            "all_converged": all(x.stats["status"] == 0 for x in infos)}
+    return out
+
+
 def operator_bytes(nc, nnz):
     """Bytes the assembled-M product itself streams per iteration: each
     nonzero's column and value (12), and per row its length (4), q (8) and
@@ -226,6 +327,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--no-timestep", action="store_true")
+    ap.add_argument("--no-hydro", action="store_true",
+                    help="skip the RPY-mobility leg")
+    ap.add_argument("--hydro-steps", type=int, default=20)
     ap.add_argument("--timestep-steps", type=int, default=8)
     ap.add_argument("--large", action="store_true",
                     help="also time the 1.1M-particle forward solve")
@@ -325,6 +429,7 @@ def main():
     batch = None if args.no_batch else batched(sc, W, torch, np, args.batch_count)
     big = large(sc, W, torch, np) if args.large else None
     tsl = None if args.no_timestep else timestepping(sc, W, torch, np, args.timestep_steps)
+    hyd = None if args.no_hydro else hydro(sc, W, torch, np, args.hydro_steps)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -387,6 +492,7 @@ def main():
         "batched": batch,
         "large": big,
         "timestep": tsl,
+        "hydro": hyd,
     }
     print(json.dumps(line), flush=True)
 

@@ -195,3 +195,34 @@ def test_cluster_steps_match_oracle():
         assert info.contacts.count == rec.i.size
         np.testing.assert_allclose(P.pos.cpu().numpy(), s.pos, rtol=0, atol=1e-9)
     assert float(-P.pos[:, 2].mean()) > 0.0
+
+
+def test_rpy_product_in_a_hip_graph():
+    """One RPY product captured in a HIP graph: every replay, with eager work
+    and synchronisations between them, equals the eager product bitwise, and
+    replays follow positions updated in place."""
+    import paper_1909_06623_amd as sc
+    s = W.sphere_cluster(3000, W.SEED_BASE + 910)
+    _say("rpy product graph replays")
+    pos = torch.from_numpy(s.pos).cuda()
+    R = sc.RPY(pos, torch.from_numpy(s.hydro_radius).cuda())
+    F = torch.from_numpy(np.random.default_rng(2).standard_normal((s.n, 6))).cuda()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        R.apply(F)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        U_g = R.apply(F)
+    for k in range(4):
+        if k == 2:
+            pos.add_(0.01)                      # every centre moves: couplings unchanged
+            pos[0, 0] += 0.5                    # one centre moves alone
+        U_e = R.apply(F)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(U_g, U_e), k
+    Uo = (OM.rpy_dense(pos.cpu().numpy(), s.hydro_radius) @ F.cpu().numpy().ravel()).reshape(s.n, 6)
+    np.testing.assert_allclose(U_g.cpu().numpy(), Uo, rtol=0, atol=1e-13 * np.abs(Uo).max())
