@@ -333,7 +333,7 @@ typedef struct sc_batch sc_batch;   /* opaque plan (host memory) */
 size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *items,
                                 const sc_batch_opts *opts);
 
-/* Plans a batch of `count` LCPs (Algorithm 1 per instance, section 4): checks
+/* Plans a batch of `count` LCPs (Algorithm 1 per instance, section 3.3.1): checks
  * every item, writes the instance table and the work order (by nonzeros,
  * largest first) into ws, and picks the team size (autotuning if
  * opts->team == 0). *out receives a plan to free with sc_batch_destroy.
