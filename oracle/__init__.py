@@ -400,16 +400,28 @@ def adjoint(s, c, q, u_nc, gamma, dL_dgamma=None, dL_dF=None, method="direct"):
     Uc = mobility(axis, mob, D_apply(n, c, gamma))
     Vw = mobility(axis, mob, D_apply(n, c, w))
     Utot = _f64(u_nc) + Uc
+    out = adjoint_positions(s, c, gamma, w, dL_dF, Vw, Utot)
+    return -w, out, w
+
+
+def adjoint_positions(s, c, gamma, w, dL_dF, Vw, Utot):
+    """The per-contact geometric part of the adjoint's centre gradient:
+    sum_l dD_l^T [gamma_l (dL/dF - V_w) - w_l U] - sum_l w_l dPhi_l/dt over
+    the centres, for given V_w = Mob D w and U = U_nc + U_c (any symmetric
+    mobility; the mobility itself held fixed)."""
+    lib = _load()
+    n = s.n
+    gamma, w, Vw, Utot = map(_f64, (gamma, w, Vw, Utot))
     dLdF = None if dL_dF is None else _f64(dL_dF)
     ci, cj = _i32(c.i), _i32(c.j)
     out = np.zeros((n, 3))
-    pos, rad, hl, box = map(_f64, (s.pos, s.radius, s.half_len, s.box))
+    pos, axis, rad, hl, box = map(_f64, (s.pos, s.axis, s.radius, s.half_len, s.box))
     lib.orc_adjoint_positions(
         n, c.nc, _d(pos), _d(axis), _d(rad), _d(hl), _d(box), int(s.periodic),
         ci.ctypes.data_as(_ip), cj.ctypes.data_as(_ip), _d(gamma), _d(w),
         None if dLdF is None else _d(dLdF), _d(Vw), _d(Utot), float(s.dt),
         _d(out))
-    return -w, out, w
+    return out
 
 
 def contact_grad(ci, pi, Ri, hi, cj, pj, Rj, hj, Ei, Ej, c_phi,

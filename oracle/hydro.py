@@ -18,6 +18,10 @@ allows any mobility solver that keeps Mob SPD). This module holds:
   spheres (a reading: this keeps the matrix SPD, being block diagonal in
   translations and rotations with an SPD translational block);
   ``rpy_dense`` evaluates the same formulas on arrays of all pairs;
+* ``rpy_grad``: the centre gradient of a^T Mob(c) f for the RPY mobility,
+  from the derivatives of the coefficient functions of each branch;
+* ``adjoint_rpy``: the implicit adjoint of the converged LCP behind the RPY
+  mobility (not in the paper), on the explicit M;
 * ``bbpgd_dense``: Algorithm 1 on an explicit M, step for step as the C
   oracle's ``orc_bbpgd`` (BB1/BB2/alternating step sizes, a non-positive
   denominator keeps the previous step, a non-positive g0^T M g0 falls back
@@ -26,8 +30,11 @@ allows any mobility solver that keeps Mob SPD). This module holds:
 Pins (tests/test_oracle_hydro.py): the equal-radius Rotne-Prager closed
 form (both branches), continuity at r = a_i + a_j and r = |a_i - a_j|, the
 Oseen far field, positive definiteness, the two-sphere sedimentation
-velocities, ``bbpgd_dense`` against the C oracle on the dry mobility, and
-KKT plus brute-force active sets with the RPY mobility.
+velocities, ``bbpgd_dense`` against the C oracle on the dry mobility,
+KKT plus brute-force active sets with the RPY mobility, ``rpy_grad``
+against central differences, and ``adjoint_rpy`` against central
+differences of polished solves (parity unpinned by the paper: the adjoint
+is not in it).
 """
 from __future__ import annotations
 
@@ -130,6 +137,100 @@ def rpy_apply(pos, radius, F, mu=1.0):
     return U
 
 
+def _rpy_coefficients(r, ai, aj, mu):
+    """A, Bt and their derivatives in r for M = A I + Bt d d^T (d the
+    unnormalised separation, r = |d|), per branch; arrays of pairs."""
+    k8 = 1.0 / (8.0 * math.pi * mu)
+    k6 = 1.0 / (6.0 * math.pi * mu)
+    S = ai * ai + aj * aj
+    far = r > ai + aj
+    inside = r <= np.abs(ai - aj)
+    rs = np.where(r > 0.0, r, 1.0)
+    # separated: A = k8 (1/r + S/(3 r^3)), Bt = k8 (1/r^3 - S/r^5)
+    A_f = k8 * (1.0 / rs + S / (3.0 * rs ** 3))
+    dA_f = k8 * (-1.0 / rs ** 2 - S / rs ** 4)
+    B_f = k8 * (1.0 / rs ** 3 - S / rs ** 5)
+    dB_f = k8 * (-3.0 / rs ** 4 + 5.0 * S / rs ** 6)
+    # overlapping: A = pre (sigma/2 - T^2/(32 r^3)), T = delta^2 + 3 r^2,
+    # Bt = 3 pre (delta^2 - r^2)^2 / (32 r^5)
+    pre = k6 / (ai * aj)
+    d2 = (ai - aj) ** 2
+    T = d2 + 3.0 * rs * rs
+    A_o = pre * ((ai + aj) / 2.0 - T * T / (32.0 * rs ** 3))
+    dA_o = -pre * 3.0 * T * (rs * rs - d2) / (32.0 * rs ** 4)
+    B_o = pre * 3.0 * (d2 - rs * rs) ** 2 / (32.0 * rs ** 5)
+    dB_o = pre * 3.0 * (d2 - rs * rs) * (rs * rs - 5.0 * d2) / (32.0 * rs ** 6)
+    A = np.where(far, A_f, np.where(inside, k6 / np.maximum(ai, aj), A_o))
+    dA = np.where(far, dA_f, np.where(inside, 0.0, dA_o))
+    Bt = np.where(far, B_f, np.where(inside, 0.0, B_o))
+    dB = np.where(far, dB_f, np.where(inside, 0.0, dB_o))
+    return A, dA, Bt, dB
+
+
+def rpy_grad(pos, radius, a, f, mu=1.0):
+    """g[k] = d/dc_k of a^T Mob(c) f for the RPY mobility (a, f: [n][6];
+    only the translational couplings depend on the centres). Each ordered
+    pair (k, j), d = c_k - c_j, contributes the gradient in d of
+    a_k^T M(d) f_j + a_j^T M(d) f_k."""
+    pos = np.asarray(pos, dtype=np.float64)
+    radius = np.asarray(radius, dtype=np.float64)
+    at = np.asarray(a, dtype=np.float64)[:, :3]
+    ft = np.asarray(f, dtype=np.float64)[:, :3]
+    n = pos.shape[0]
+    d = pos[:, None, :] - pos[None, :, :]
+    r = np.sqrt(np.einsum("kjc,kjc->kj", d, d))
+    ai = radius[:, None] * np.ones((1, n))
+    aj = radius[None, :] * np.ones((n, 1))
+    A, dA, Bt, dB = _rpy_coefficients(r, ai, aj, mu)
+    rs = np.where(r > 0.0, r, 1.0)
+    e = np.where((r > 0.0)[..., None], d / rs[..., None], 0.0)
+    ak, fk = at[:, None, :], ft[:, None, :]
+    aj_, fj = at[None, :, :], ft[None, :, :]
+    P = np.einsum("kjc,kjc->kj", ak * np.ones_like(d), fj * np.ones_like(d)) + \
+        np.einsum("kjc,kjc->kj", aj_ * np.ones_like(d), fk * np.ones_like(d))
+    akd = np.einsum("kjc,kjc->kj", ak * np.ones_like(d), d)
+    ajd = np.einsum("kjc,kjc->kj", aj_ * np.ones_like(d), d)
+    fkd = np.einsum("kjc,kjc->kj", fk * np.ones_like(d), d)
+    fjd = np.einsum("kjc,kjc->kj", fj * np.ones_like(d), d)
+    Q = akd * fjd + ajd * fkd
+    g = (dA * P + dB * Q)[..., None] * e + Bt[..., None] * (
+        fjd[..., None] * ak + akd[..., None] * fj + fkd[..., None] * aj_ + ajd[..., None] * fk)
+    idx = np.arange(n)
+    g[idx, idx] = 0.0
+    return g.sum(axis=1)
+
+
+def adjoint_rpy(s, c, gamma, dL_dgamma=None, dL_dF=None, mu=1.0):
+    """Implicit adjoint of the converged LCP with the RPY mobility (not in
+    the paper; the dry-mobility derivation with Mob a function of the
+    centres). With b = dL/dgamma + D^T dL/dF, M_AA w_A = b_A on A = {gamma >
+    0}; dL/dq = -w; the centre gradient is the per-contact geometric part
+    with V_w = Mob D w and U = Mob (F_ext + D gamma), minus
+    d/dc [(D w)^T Mob(c) (D gamma + F_ext)]. Returns (dL_dq, dL_dpos, w)."""
+    from . import D_apply, D_matrix, DT_apply, adjoint_positions
+    n = s.n
+    rad = s.radius if s.hydro_radius is None else s.hydro_radius
+    gamma = np.asarray(gamma, dtype=np.float64)
+    Mob = rpy_dense(s.pos, rad, mu)
+    M = contact_matrix(D_matrix(n, c), Mob)
+    b = np.zeros(c.nc) if dL_dgamma is None else np.asarray(dL_dgamma, dtype=np.float64).copy()
+    if dL_dF is not None:
+        b = b + DT_apply(c, dL_dF)
+    act = gamma > 0.0
+    idx = np.flatnonzero(act)
+    w = np.zeros(c.nc)
+    if idx.size:
+        w[idx] = np.linalg.solve(M[np.ix_(idx, idx)], b[idx])
+    Fc = D_apply(n, c, gamma)
+    Fw = D_apply(n, c, w)
+    Ftot = Fc + s.f_ext
+    Vw = (Mob @ Fw.ravel()).reshape(n, 6)
+    U = (Mob @ Ftot.ravel()).reshape(n, 6)
+    out = adjoint_positions(s, c, gamma, w, dL_dF, Vw, U)
+    out = out - rpy_grad(s.pos, rad, Fw, Ftot, mu)
+    return -w, out, w
+
+
 def contact_matrix(D, Mob):
     """M = D^T Mob D, dense (D: 6N x nc, sparse or dense)."""
     if hasattr(D, "toarray"):
@@ -211,6 +312,27 @@ def bbpgd_dense(M, q, diag, gamma0=None, tol=1e-6, max_iter=100000, bb=1):
                 ndegen += 1
     st = DenseStats(status, iters, mvops, res, int(np.count_nonzero(gamma > 0.0)), ndegen, alpha)
     return gamma, g, st
+
+
+def polish_dense(M, q, gamma, max_pass=50):
+    """Exact LCP solution near ``gamma`` on the explicit M: solve the active
+    block, move violators, repeat. Returns (gamma, g, passes), passes = -1 if
+    it did not settle."""
+    act = np.asarray(gamma) > 0.0
+    q = np.asarray(q, dtype=np.float64)
+    gam = np.zeros(q.size)
+    for p in range(max_pass):
+        gam = np.zeros(q.size)
+        idx = np.flatnonzero(act)
+        if idx.size:
+            gam[idx] = np.linalg.solve(M[np.ix_(idx, idx)], -q[idx])
+        g = M @ gam + q
+        leave = act & (gam < 0.0)
+        join = (~act) & (g < 0.0)
+        if not leave.any() and not join.any():
+            return gam, g, p + 1
+        act = (act & ~leave) | join
+    return gam, M @ gam + q, -1
 
 
 def self_diag(s, c):

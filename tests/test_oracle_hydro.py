@@ -222,3 +222,100 @@ def test_cluster_sediments_like_a_point_force_cloud():
     # the core falls faster than the surface
     rr = np.linalg.norm(s.pos, axis=1)
     assert uz[rr < 0.5 * R].mean() > uz[rr > 0.8 * R].mean()
+
+
+def test_rpy_gradient_against_central_differences():
+    rng = np.random.default_rng(3)
+    for trial in range(3):
+        n = 12
+        pos = rng.uniform(0.0, 2.0, (n, 3))
+        rad = rng.uniform(0.2, 0.6, n)
+        if trial == 2:
+            pos[1] = pos[0] + [0.05, 0.02, 0.0]      # one sphere inside another
+            rad[0], rad[1] = 0.6, 0.2
+        a = rng.standard_normal((n, 6))
+        f = rng.standard_normal((n, 6))
+        g = OM.rpy_grad(pos, rad, a, f, 1.3)
+        h = 1e-6
+        fd = np.zeros((n, 3))
+        for k in range(n):
+            for c in range(3):
+                pp, pm = pos.copy(), pos.copy()
+                pp[k, c] += h
+                pm[k, c] -= h
+                fd[k, c] = (a.ravel() @ OM.rpy_dense(pp, rad, 1.3) @ f.ravel()
+                            - a.ravel() @ OM.rpy_dense(pm, rad, 1.3) @ f.ravel()) / (2 * h)
+        np.testing.assert_allclose(g, fd, rtol=0, atol=1e-7 * np.abs(g).max())
+
+
+def _rpy_solve(s):
+    c = O.find_contacts(s)
+    Mob = OM.rpy_dense(s.pos, s.radius)
+    u_nc = (Mob @ s.f_ext.ravel()).reshape(s.n, 6)
+    q = O.build_q(c, u_nc, s.dt)
+    M = OM.contact_matrix(O.D_matrix(s.n, c), Mob)
+    g, _, st = OM.bbpgd_dense(M, q, O.M_diag(s, c), tol=1e-11)
+    gp, _, passes = OM.polish_dense(M, q, g)
+    assert passes > 0
+    return c, gp
+
+
+@pytest.mark.parametrize("loss", ["force", "linear"])
+def test_rpy_adjoint_against_central_differences(loss):
+    """dL/dc from adjoint_rpy against central differences of polished RPY
+    solves (contacts, U_nc = Mob(c) F_ext, q and M all rebuilt), for
+    L = 1/2 ||D gamma||^2 and L = wts . gamma."""
+    s = W.spheres(40, 0.35, W.SEED_BASE + 911)
+    s.periodic = 0
+    s.dt = 0.01
+    rng = np.random.default_rng(12)
+    c, gam = _rpy_solve(s)
+    act = gam > 0.0
+    assert act.sum() >= 5
+    wts = rng.standard_normal(c.nc)
+    if loss == "force":
+        F = O.D_apply(s.n, c, gam)
+        _, dpos, _ = OM.adjoint_rpy(s, c, gam, dL_dF=F)
+    else:
+        _, dpos, _ = OM.adjoint_rpy(s, c, gam, dL_dgamma=wts)
+    hp = 1e-7
+    done = 0
+    for _ in range(20):
+        if done >= 4:
+            break
+        V = rng.standard_normal((s.n, 3))
+        V /= np.linalg.norm(V)
+        L = []
+        for sg in (1, -1):
+            sp = W.Suspension(**{**s.__dict__, "pos": s.pos + sg * hp * V})
+            cp, gp = _rpy_solve(sp)
+            if not np.array_equal(cp.keys(), c.keys()) or not np.array_equal(gp > 0, act):
+                break
+            if loss == "force":
+                Fp = O.D_apply(s.n, cp, gp)
+                L.append(0.5 * float(np.sum(Fp * Fp)))
+            else:
+                L.append(float(wts @ gp))
+        if len(L) < 2:
+            continue
+        fd = (L[0] - L[1]) / (2 * hp)
+        assert abs(float(np.sum(dpos * V)) - fd) <= 1e-5 * np.linalg.norm(dpos), (fd, np.sum(dpos * V))
+        done += 1
+    assert done >= 3
+
+
+def test_rpy_adjoint_is_translation_invariant():
+    """In unbounded fluid the loss depends on relative positions only, so
+    the centre gradient sums to zero (a sign slip between the two ends of a
+    pair term, in the contacts or in the mobility's gradient, breaks it)."""
+    s = W.spheres(60, 0.35, W.SEED_BASE + 912)
+    s.periodic = 0
+    s.dt = 0.01
+    c, gam = _rpy_solve(s)
+    assert (gam > 0).sum() >= 5
+    for kw in ({"dL_dF": O.D_apply(s.n, c, gam)},
+               {"dL_dgamma": np.random.default_rng(4).standard_normal(c.nc)}):
+        _, dpos, _ = OM.adjoint_rpy(s, c, gam, **kw)
+        assert np.abs(dpos.sum(axis=0)).max() < 1e-10 * np.abs(dpos).max()
+        g = OM.rpy_grad(s.pos, s.radius, O.D_apply(s.n, c, gam), s.f_ext)
+        assert np.abs(g.sum(axis=0)).max() < 1e-11 * np.abs(g).max()
