@@ -453,6 +453,21 @@ int sc_rpy_apply(void *ctx, int32_t n, const double *f, double *u, void *stream)
  * mobility of sc_apply_mobility. */
 int sc_dry_apply(void *ctx, int32_t n, const double *f, double *u, void *stream);
 
+/* The centre gradient of a mobility: enqueue g[k] = d/dc_k (a^T Mob(c) f)
+ * for device arrays a, f of [n][6] (caller order) into g of [n][3]. Used by
+ * the adjoint behind a mobility that depends on the centres; returns SC_OK
+ * or an error code. */
+typedef int (*sc_mobility_grad_fn)(void *ctx, int32_t n, const double *a, const double *f,
+                                   double *g, void *stream);
+
+/* sc_mobility_grad_fn for ctx = const sc_rpy *: the gradient of the RPY
+ * translational couplings (from the r-derivatives of each branch's
+ * coefficient functions; rotations and self terms do not depend on the
+ * centres). Uses ctx->work like sc_rpy_apply (calls on one work buffer must
+ * not overlap). Enqueues only. */
+int sc_rpy_grad(void *ctx, int32_t n, const double *a, const double *f, double *g,
+                void *stream);
+
 /* Device bytes of the workspace of sc_solve_lcp_mob. */
 size_t sc_solve_mob_work_bytes(int32_t n, int32_t capacity);
 
@@ -479,6 +494,34 @@ int sc_solve_lcp_mob(const sc_particles *p, const sc_contacts *c, const sc_solve
                      sc_mobility_fn mob, void *mob_ctx, int32_t check_every, double *gamma,
                      double *g, double *f_c, double *u_c, sc_stats *st, void *work,
                      size_t work_bytes, void *stream);
+
+/* Device bytes of the workspace of sc_solve_lcp_adjoint_mob. */
+size_t sc_adjoint_mob_work_bytes(int32_t n, int32_t capacity);
+
+/* Implicit adjoint of a converged solve behind a general mobility (not in the
+ * paper; sc_solve_lcp_adjoint's derivation, which holds for any symmetric
+ * mobility, plus the mobility's own dependence on the centres). With A =
+ * {gamma > 0} and b = dL/dgamma + D^T dL/dF_c: M_AA w_A = b_A by conjugate
+ * gradients with every product through `mob` (to ||r|| <= opts->tol ||b_A||
+ * or opts->max_iter iterations, enqueued in chunks of `check_every` (0 = 4)
+ * like sc_solve_lcp_mob); dL/dq = -w on A, 0 elsewhere; dL/dc = the
+ * per-contact geometric terms of sc_solve_lcp_adjoint with V_w = Mob D w and
+ * U = u_nc + Mob D gamma, minus d/dc [(D w)^T Mob(c) (D gamma + f_ext)] from
+ * `mob_grad` (NULL: the mobility does not depend on the centres, f_ext may
+ * be NULL). u_nc, f_ext: [n][6] device, u_nc = Mob f_ext at these centres.
+ * gamma, dL_dgamma: [c->count]; dL_df: [n][6] or NULL; dL_dq: [c->count];
+ * dL_dpos: [n][3]; all device. st: host, OUT (mvops = CG iterations; the
+ * two products for V_w and U_c are extra). work: device, 256-byte aligned,
+ * >= sc_adjoint_mob_work_bytes(n, c->capacity). Returns SC_OK,
+ * SC_NOT_CONVERGED, SC_ERR_NONFINITE, SC_ERR_INVALID, SC_ERR_WORKSPACE,
+ * SC_ERR_HIP or a mobility function's error code. Synchronises `stream`. */
+int sc_solve_lcp_adjoint_mob(const sc_particles *p, const sc_box *box, const sc_contacts *c,
+                             const double *u_nc, const double *f_ext, double dt,
+                             const double *gamma, const double *dL_dgamma, const double *dL_df,
+                             sc_mobility_fn mob, void *mob_ctx, sc_mobility_grad_fn mob_grad,
+                             void *mob_grad_ctx, const sc_adjoint_opts *opts,
+                             int32_t check_every, double *dL_dq, double *dL_dpos, sc_stats *st,
+                             void *work, size_t work_bytes, void *stream);
 
 /* Static string describing a return code. */
 const char *sc_strerror(int code);

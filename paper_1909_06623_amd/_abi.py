@@ -150,6 +150,13 @@ SIGNATURES = {
     "sc_solve_lcp_mob": (ctypes.c_int, [P(sc_particles), P(sc_contacts), P(sc_solve_opts),
                                         c_dp, c_dp, ctypes.c_int32, c_dp, c_dp, c_dp, c_dp,
                                         P(sc_stats), c_dp, ctypes.c_size_t, c_dp]),
+    "sc_rpy_grad": (ctypes.c_int, [c_dp, ctypes.c_int32, c_dp, c_dp, c_dp, c_dp]),
+    "sc_adjoint_mob_work_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "sc_solve_lcp_adjoint_mob": (ctypes.c_int, [P(sc_particles), P(sc_box), P(sc_contacts),
+                                                c_dp, c_dp, ctypes.c_double, c_dp, c_dp, c_dp,
+                                                c_dp, c_dp, c_dp, c_dp, P(sc_adjoint_opts),
+                                                ctypes.c_int32, c_dp, c_dp, P(sc_stats), c_dp,
+                                                ctypes.c_size_t, c_dp]),
     "sc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sc_version": (ctypes.c_int, []),
 }

@@ -366,6 +366,19 @@ class RPY:
                                                     _ptr(f), _ptr(u), _stream()))
         return u
 
+    def grad_fn_ctx(self):
+        """(gradient function address, context address) for the adjoint."""
+        return (ctypes.cast(A.lib().sc_rpy_grad, ctypes.c_void_p).value,
+                ctypes.addressof(self._ctx))
+
+    def grad(self, a: torch.Tensor, f: torch.Tensor) -> torch.Tensor:
+        """g[k] = d/dc_k (a^T Mob f) for a, f [n][6]."""
+        a, f = _dev(a), _dev(f)
+        g = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
+        _check("sc_rpy_grad", A.lib().sc_rpy_grad(ctypes.addressof(self._ctx), self.n, _ptr(a),
+                                                  _ptr(f), _ptr(g), _stream()))
+        return g
+
 
 class DryMobility:
     """The dry block-diagonal mobility of ``particles`` as a mobility
@@ -378,6 +391,10 @@ class DryMobility:
     def fn_ctx(self):
         return (ctypes.cast(A.lib().sc_dry_apply, ctypes.c_void_p).value,
                 ctypes.addressof(self._ctx))
+
+    def grad_fn_ctx(self):
+        """The dry mobility does not depend on the centres."""
+        return None
 
     def apply(self, f: torch.Tensor) -> torch.Tensor:
         return apply_mobility(self.P, f)
@@ -418,6 +435,43 @@ def solve_lcp_mob(particles: Particles, contacts: Contacts, mobility, tol: float
                                                       A.SC_ERR_NONFINITE)
     _check("sc_solve_lcp_mob", rc, allow)
     return gamma[:nc], g[:nc], st.as_dict(), f_c, u_c
+
+
+def solve_lcp_adjoint_mob(particles: Particles, box: Box, contacts: Contacts,
+                          u_nc: torch.Tensor, dt: float, gamma: torch.Tensor, mobility,
+                          f_ext: Optional[torch.Tensor] = None,
+                          dL_dgamma: Optional[torch.Tensor] = None,
+                          dL_df: Optional[torch.Tensor] = None, tol: float = 1e-10,
+                          max_iter: int = 100000, check_every: int = 0):
+    """Implicit adjoint of a solve behind ``mobility`` (see solve_lcp_mob):
+    returns (dL_dq, dL_dpos, stats). A mobility that depends on the centres
+    (``grad_fn_ctx()`` not None, e.g. RPY) needs ``f_ext``."""
+    nc, n = contacts.count, particles.n
+    u_nc = _dev(u_nc)
+    gamma = _dev(gamma)
+    fe = None if f_ext is None else _dev(f_ext)
+    dLg = None if dL_dgamma is None else _dev(dL_dgamma)
+    dLf = None if dL_df is None else _dev(dL_df)
+    dq = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
+    dpos = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    opts = A.sc_adjoint_opts(float(tol), int(max_iter), 0, 0, 0, 0, 0, 0)
+    st = A.sc_stats()
+    wb = int(A.lib().sc_adjoint_mob_work_bytes(n, contacts.capacity))
+    work = torch.empty(wb + 256, dtype=torch.uint8, device="cuda")
+    wp = (work.data_ptr() + 255) // 256 * 256
+    fn, ctx = mobility.fn_ctx()
+    gfc = mobility.grad_fn_ctx()
+    gfn, gctx = (None, None) if gfc is None else gfc
+    pc, bc, cc = particles.c(), box.c(), contacts.c()
+    rc = A.lib().sc_solve_lcp_adjoint_mob(
+        ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(cc), _ptr(u_nc), _ptr(fe), float(dt),
+        _ptr(gamma), _ptr(dLg), _ptr(dLf), ctypes.c_void_p(fn), ctypes.c_void_p(ctx),
+        None if gfn is None else ctypes.c_void_p(gfn),
+        None if gctx is None else ctypes.c_void_p(gctx), ctypes.byref(opts), int(check_every),
+        _ptr(dq), _ptr(dpos), ctypes.byref(st), ctypes.c_void_p(wp),
+        wb + 256 - (wp - work.data_ptr()), _stream())
+    _check("sc_solve_lcp_adjoint_mob", rc, (A.SC_OK, A.SC_NOT_CONVERGED))
+    return dq[:nc], dpos, st.as_dict()
 
 
 class Batch:

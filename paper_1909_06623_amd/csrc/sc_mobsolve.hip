@@ -34,6 +34,7 @@
 // order, so the result is deterministic.
 #include <cmath>
 
+#include "sc_adjoint_dev.hpp"
 #include "sc_common.hpp"
 #include "sc_plan.hpp"
 
@@ -273,6 +274,205 @@ k_ms_finish(const double *part, int nparts, MsCtrl *ctrl, double tol, int max_it
     *ctrl = C;
 }
 
+// ---------------------------------------------------------- adjoint CG
+//
+// The masked system M_AA w_A = b_A of the implicit adjoint (not in the paper;
+// the derivation is the dry solver's, which holds for any symmetric
+// mobility) by conjugate gradients, one mobility call per iteration:
+//   scatter: p = r + beta p_prev per incidence (owner stores), F = D p;
+//   mobility: U = Mob F;
+//   gather: t = mask(D^T U), partial p.t;   finish: alpha = rr / p.t;
+//   update: x += alpha p, r -= alpha t, partial r.r;   finish: beta, stop.
+
+struct CgMobCtrl {
+    double alpha, beta, rr, rr0, res;
+    int iters, status, done, n_active;
+};
+
+__global__ void __launch_bounds__(kBlock)
+k_am_rhs(MsView V, const double *gamma, const double *dLdg, const double *dLdF, double *r,
+         double *x, double *p0, double *part) {
+    double v[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int l = blockIdx.x * kBlock + threadIdx.x; l < V.nc; l += gridDim.x * kBlock) {
+        const double b = cg_rhs_one(l, V.ci, V.cj, V.frame, gamma, dLdg, dLdF);
+        r[l] = b;
+        x[l] = 0.0;
+        p0[l] = 0.0;
+        v[0] += b * b;
+        v[4] += gamma[l] > 0.0 ? 1.0 : 0.0;
+    }
+    ms_partials(v, part, false);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_am_scatter(MsView V, const double *r, const double *pc, double *pn, const CgMobCtrl *ctrl,
+             double *f) {
+    if (ctrl->done) return;
+    const double beta = ctrl->beta;
+    const int k = (blockIdx.x * kBlock + threadIdx.x) / kMsLanes;
+    const int lane = threadIdx.x % kMsLanes;
+    double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (k < V.n) {
+        const int e1 = V.inc_ptr[k + 1];
+        for (int e = V.inc_ptr[k] + lane; e < e1; e += kMsLanes) {
+            const int code = V.inc[e];
+            const int m = code >> 1;
+            const double w = r[m] + beta * pc[m];
+            if (code & 1) pn[m] = w;
+            const double *d = V.dpm + 6 * static_cast<long long>(e);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) a[c] += w * d[c];
+        }
+    }
+#pragma unroll
+    for (int off = kMsLanes / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a[c] += __shfl_xor(a[c], off, kWave);
+    if (k < V.n && lane == 0) {
+        double *fk = f + 6 * static_cast<long long>(V.order[k]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) fk[c] = a[c];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_am_gather(MsView V, const double *u, const double *gamma, const double *p, double *tv,
+            const CgMobCtrl *ctrl, double *part) {
+    if (ctrl->done) return;
+    double v[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int l = blockIdx.x * kBlock + threadIdx.x; l < V.nc; l += gridDim.x * kBlock) {
+        const double tl = gamma[l] > 0.0 ? dt_u_caller(V, u, l) : 0.0;
+        tv[l] = tl;
+        v[0] += p[l] * tl;
+    }
+    ms_partials(v, part, false);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_am_update(int nc, const double *p, const double *tv, double *x, double *r,
+            const CgMobCtrl *ctrl, double *part) {
+    if (ctrl->done) return;
+    const double alpha = ctrl->alpha;
+    double v[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int l = blockIdx.x * kBlock + threadIdx.x; l < nc; l += gridDim.x * kBlock) {
+        x[l] = x[l] + alpha * p[l];
+        const double rl = r[l] - alpha * tv[l];
+        r[l] = rl;
+        v[0] += rl * rl;
+    }
+    ms_partials(v, part, false);
+}
+
+// STAGE 0: rr0 after the right-hand side; 1: alpha; 2: beta and the stop test.
+template <int STAGE>
+__global__ void __launch_bounds__(kBlock)
+k_am_finish(const double *part, int nparts, CgMobCtrl *ctrl, double tol, int max_iter) {
+    if (STAGE != 0 && ctrl->done) return;
+    __shared__ double tot[2];
+    const int lane = threadIdx.x % kWave, c = threadIdx.x / kWave;
+    if (c < 2) {
+        const int k = c == 0 ? 0 : 4;
+        double x = 0.0;
+        for (int b = lane; b < nparts; b += kWave) x += part[static_cast<long long>(b) * kNV + k];
+        x = wave_sum(x);
+        if (lane == 0) tot[c] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    CgMobCtrl C = *ctrl;
+    if (STAGE == 0) {
+        C.rr = C.rr0 = tot[0];
+        C.beta = 0.0;
+        C.res = tot[0] > 0.0 ? 1.0 : 0.0;
+        C.n_active = static_cast<int>(tot[1]);
+        if (!std::isfinite(tot[0])) {
+            C.status = SC_ERR_NONFINITE;
+            C.done = 1;
+        } else if (tot[0] == 0.0) {
+            C.status = SC_OK;
+            C.done = 1;
+        } else {
+            C.status = SC_NOT_CONVERGED;
+            if (max_iter == 0) C.done = 1;
+        }
+    } else if (STAGE == 1) {
+        const double pt = tot[0];
+        if (!std::isfinite(pt)) {
+            C.status = SC_ERR_NONFINITE;
+            C.done = 1;
+        } else if (!(pt > 0.0)) {
+            C.done = 1;   // M_AA not positive on p (numerically)
+        } else {
+            C.alpha = C.rr / pt;
+        }
+    } else {
+        const double rr = tot[0];
+        C.iters += 1;
+        C.res = sqrt(rr / C.rr0);
+        if (!std::isfinite(rr)) {
+            C.status = SC_ERR_NONFINITE;
+            C.done = 1;
+        } else if (rr <= tol * tol * C.rr0) {
+            C.status = SC_OK;
+            C.done = 1;
+        } else {
+            C.beta = rr / C.rr;
+            C.rr = rr;
+            if (C.iters >= max_iter) C.done = 1;
+        }
+    }
+    *ctrl = C;
+}
+
+__global__ void k_am_post(int nc, const double *gamma, const double *x, double *dLdq) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < nc) dLdq[l] = gamma[l] > 0.0 ? -x[l] : 0.0;
+}
+
+// Caller-order [n][6] -> rank-order [n][8] (the layout of the geometric
+// gradient's velocity reads).
+__global__ void k_am_rank8(int n, const int *order, const double *src, double *dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double *s = src + 6 * static_cast<long long>(order[k]);
+    double *d = dst + 8 * static_cast<long long>(k);
+    for (int c = 0; c < 6; ++c) d[c] = s[c];
+    d[6] = 0.0;
+    d[7] = 0.0;
+}
+
+__global__ void k_am_contact_grad(int nc, const int *ci, const int *cj, const int *cs,
+                                  const double *pos, const double *axis, const double *half_len,
+                                  PBox box, const double *gamma, const double *w,
+                                  const double *dLdF, const double *Vw8, const double *Unc,
+                                  const double *Uc8, double inv_dt, double *grad) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nc) return;
+    const V3 g = contact_grad_one(l, ci, cj, cs, pos, axis, half_len, box, gamma, w, dLdF, Vw8,
+                                  Unc, Uc8, inv_dt);
+    double *o = grad + 3 * static_cast<long long>(l);
+    o[0] = g.x;
+    o[1] = g.y;
+    o[2] = g.z;
+}
+
+__global__ void k_am_gather_pos(int n, Plan pl, const double *grad, double *out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) gather_pos_one(k, pl, grad, out);
+}
+
+// a += b (elementwise, m entries)
+__global__ void k_am_add(long long m, double *a, const double *b) {
+    const long long k = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < m) a[k] += b[k];
+}
+
+// a -= b (elementwise, m entries)
+__global__ void k_am_sub(long long m, double *a, const double *b) {
+    const long long k = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < m) a[k] -= b[k];
+}
+
 // ------------------------------------------------------------------ RPY
 
 constexpr int kRpyBlock = 256;
@@ -424,6 +624,122 @@ __global__ void k_rpy_finish(int n, const double *rad, const double *f, RpyConst
     u[k] = acc;
 }
 
+// Gradient of s(d) = a_k^T M(d) f_j + a_j^T M(d) f_k in d = c_k - c_j, with
+// M = A(r) I + Bt(r) d d^T per branch (A, Bt and their r-derivatives), added
+// to (gx, gy, gz); the self pair and one sphere inside the other add nothing.
+__device__ __forceinline__ void rpy_grad_pair(const RpyConst &K, double dx, double dy, double dz,
+                                              double ai, double aj, const double (&ak)[3],
+                                              const double (&fk)[3], double ajx, double ajy,
+                                              double ajz, double fjx, double fjy, double fjz,
+                                              bool self, double &gx, double &gy, double &gz) {
+#pragma clang fp contract(fast)
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double sa = ai + aj;
+    double dA, Bt, dB, ri;
+    if (r2 > sa * sa) {
+        ri = rsqrt_nr(r2);
+        const double ri2 = ri * ri;
+        const double S = ai * ai + aj * aj;
+        dA = K.k8 * ri2 * (-1.0 - S * ri2);
+        Bt = K.k8 * ri2 * ri * (1.0 - S * ri2);
+        dB = K.k8 * ri2 * ri2 * (-3.0 + 5.0 * S * ri2);
+    } else {
+        const double da = ai - aj;
+        const double d2 = da * da;
+        if (self || !(r2 > d2)) return;
+        const double r = sqrt(r2);
+        ri = 1.0 / r;
+        const double pre = K.k6 / (ai * aj) * (3.0 / 32.0);
+        const double T = d2 + 3.0 * r2;
+        const double ri4 = ri * ri * ri * ri;
+        const double w = d2 - r2;
+        dA = -pre * T * (r2 - d2) * ri4;
+        Bt = pre * w * w * ri4 * ri;
+        dB = pre * w * (r2 - 5.0 * d2) * ri4 * ri * ri;
+    }
+    const double P = ak[0] * fjx + ak[1] * fjy + ak[2] * fjz + ajx * fk[0] + ajy * fk[1] +
+                     ajz * fk[2];
+    const double akd = ak[0] * dx + ak[1] * dy + ak[2] * dz;
+    const double ajd = ajx * dx + ajy * dy + ajz * dz;
+    const double fkd = fk[0] * dx + fk[1] * dy + fk[2] * dz;
+    const double fjd = fjx * dx + fjy * dy + fjz * dz;
+    const double Q = akd * fjd + ajd * fkd;
+    const double cd = (dA * P + dB * Q) * ri;
+    gx += cd * dx + Bt * (fjd * ak[0] + akd * fjx + fkd * ajx + ajd * fk[0]);
+    gy += cd * dy + Bt * (fjd * ak[1] + akd * fjy + fkd * ajy + ajd * fk[1]);
+    gz += cd * dz + Bt * (fjd * ak[2] + akd * fjz + fkd * ajz + ajd * fk[2]);
+}
+
+// g_k = sum_j of the pair gradients, laid out like k_rpy_pairs (64 targets
+// per workgroup, the waves sharing each LDS tile of sources, source splits
+// over the second grid dimension, fixed-order sums).
+__global__ void __launch_bounds__(kRpyBlock)
+k_rpy_grad_pairs(int n, const double *__restrict__ pos, const double *__restrict__ rad,
+                 const double *__restrict__ a, const double *__restrict__ f, RpyConst K,
+                 int splits, double *__restrict__ part) {
+    constexpr int NW = kRpyBlock / kWave;
+    __shared__ double sx[kRpyBlock], sy[kRpyBlock], sz[kRpyBlock], sr[kRpyBlock];
+    __shared__ double sa[3][kRpyBlock], sf[3][kRpyBlock];
+    __shared__ double red[3][kRpyBlock];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int i = blockIdx.x * kRpyTargets + lane;
+    const int s = blockIdx.y;
+    const int j0 = static_cast<int>(static_cast<long long>(s) * n / splits);
+    const int j1 = static_cast<int>(static_cast<long long>(s + 1) * n / splits);
+    const bool live = i < n;
+    const double xi = live ? pos[3 * i] : 0.0, yi = live ? pos[3 * i + 1] : 0.0,
+                 zi = live ? pos[3 * i + 2] : 0.0, ai = live ? rad[i] : 1.0;
+    double ak[3], fk[3];
+    for (int c = 0; c < 3; ++c) {
+        ak[c] = live ? a[6 * static_cast<long long>(i) + c] : 0.0;
+        fk[c] = live ? f[6 * static_cast<long long>(i) + c] : 0.0;
+    }
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int t = j0; t < j1; t += kRpyBlock) {
+        const int cnt = j1 - t < kRpyBlock ? j1 - t : kRpyBlock;
+        __syncthreads();
+        if (threadIdx.x < cnt) {
+            const int j = t + threadIdx.x;
+            sx[threadIdx.x] = pos[3 * j];
+            sy[threadIdx.x] = pos[3 * j + 1];
+            sz[threadIdx.x] = pos[3 * j + 2];
+            sr[threadIdx.x] = rad[j];
+            for (int c = 0; c < 3; ++c) {
+                sa[c][threadIdx.x] = a[6 * static_cast<long long>(j) + c];
+                sf[c][threadIdx.x] = f[6 * static_cast<long long>(j) + c];
+            }
+        }
+        __syncthreads();
+        const int me = i - t;
+        for (int m = w; m < cnt; m += NW)
+            rpy_grad_pair(K, xi - sx[m], yi - sy[m], zi - sz[m], ai, sr[m], ak, fk, sa[0][m],
+                          sa[1][m], sa[2][m], sf[0][m], sf[1][m], sf[2][m], m == me, gx, gy, gz);
+    }
+    red[0][threadIdx.x] = gx;
+    red[1][threadIdx.x] = gy;
+    red[2][threadIdx.x] = gz;
+    __syncthreads();
+    if (w == 0 && live) {
+        double *p = part + 3 * (static_cast<long long>(s) * n + i);
+        for (int c = 0; c < 3; ++c) {
+            double acc = red[c][lane];
+            for (int q = 1; q < NW; ++q) acc += red[c][q * kWave + lane];
+            p[c] = acc;
+        }
+    }
+}
+
+// g = sum of the splits' partial gradients, in split order.
+__global__ void k_rpy_grad_finish(int n, int splits, const double *part, double *g) {
+    const long long k = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= 3LL * n) return;
+    double acc = 0.0;
+    const long long stride = 3LL * n;
+#pragma unroll 8
+    for (int s = 0; s < splits; ++s) acc += part[k + s * stride];
+    g[k] = acc;
+}
+
 int rpy_splits(int n) {
     const int bx = grid_for(n, kRpyTargets);
     int s = (kRpyTargetBlocks + bx - 1) / bx;
@@ -435,11 +751,14 @@ int rpy_splits(int n) {
 
 // ------------------------------------------------------------------ host
 
-// Host copies of the control block, one per chunk parity, in pinned memory
+// Host copies of a control block, one per chunk parity, in pinned memory
 // (allocated once per host thread, kept for the life of the process).
-MsCtrl *pinned_ctrl() {
-    thread_local MsCtrl *p = nullptr;
-    if (!p && hipHostMalloc(reinterpret_cast<void **>(&p), 2 * sizeof(MsCtrl),
+constexpr size_t kPinnedSlot = 128;
+static_assert(sizeof(MsCtrl) <= kPinnedSlot && sizeof(CgMobCtrl) <= kPinnedSlot, "pinned slot");
+
+char *pinned_slots() {
+    thread_local char *p = nullptr;
+    if (!p && hipHostMalloc(reinterpret_cast<void **>(&p), 2 * kPinnedSlot,
                             hipHostMallocDefault) != hipSuccess)
         p = nullptr;
     return p;
@@ -461,6 +780,19 @@ struct Events {
             if (ev) (void)hipEventDestroy(ev);
     }
 };
+
+size_t am_ws_bytes(int32_t n, int32_t cap) {
+    const size_t nn = static_cast<size_t>(n), cc = static_cast<size_t>(cap);
+    size_t b = 0;
+    b += 5 * align_up(cc * sizeof(double), 256);       // r, t, x, p (two buffers)
+    b += align_up(3 * cc * sizeof(double), 256);       // per-contact gradient
+    b += 7 * align_up(6 * nn * sizeof(double), 256);   // F, U, F_w, V_w, F_c, U_c, F_tot
+    b += 2 * align_up(8 * nn * sizeof(double), 256);   // V_w, U_c in rank order
+    b += align_up(3 * nn * sizeof(double), 256);       // mobility gradient
+    b += align_up(kNV * kMaxReduceBlocks * sizeof(double), 256);
+    b += align_up(sizeof(CgMobCtrl), 256);
+    return b + 2048;
+}
 
 size_t ms_ws_bytes(int32_t n, int32_t cap) {
     const size_t nn = static_cast<size_t>(n), cc = static_cast<size_t>(cap);
@@ -498,6 +830,26 @@ extern "C" int sc_rpy_apply(void *ctx, int32_t n, const double *f, double *u, vo
     const dim3 grid(grid_for(n, kRpyTargets), splits);
     k_rpy_pairs<<<grid, kRpyBlock, 0, s>>>(n, R->pos, R->radius, f, K, splits, part);
     k_rpy_finish<<<grid_for(6LL * n), kBlock, 0, s>>>(n, R->radius, f, K, splits, part, u);
+    SC_HIP_TRY(hipGetLastError());
+    return SC_OK;
+}
+
+extern "C" int sc_rpy_grad(void *ctx, int32_t n, const double *a, const double *f, double *g,
+                           void *stream) {
+    const sc_rpy *R = static_cast<const sc_rpy *>(ctx);
+    if (!R || n < 0 || n != R->n || !(R->mu > 0.0) || !std::isfinite(R->mu)) return SC_ERR_INVALID;
+    if (n == 0) return SC_OK;
+    if (!R->pos || !R->radius || !a || !f || !g) return SC_ERR_INVALID;
+    if (!R->work || (reinterpret_cast<uintptr_t>(R->work) & 255) != 0 ||
+        R->work_bytes < sc_rpy_work_bytes(n))
+        return SC_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int splits = rpy_splits(n);
+    const RpyConst K{1.0 / (8.0 * M_PI * R->mu), 1.0 / (6.0 * M_PI * R->mu)};
+    double *part = static_cast<double *>(R->work);
+    const dim3 grid(grid_for(n, kRpyTargets), splits);
+    k_rpy_grad_pairs<<<grid, kRpyBlock, 0, s>>>(n, R->pos, R->radius, a, f, K, splits, part);
+    k_rpy_grad_finish<<<grid_for(3LL * n), kBlock, 0, s>>>(n, splits, part, g);
     SC_HIP_TRY(hipGetLastError());
     return SC_OK;
 }
@@ -550,9 +902,12 @@ extern "C" int sc_solve_lcp_mob(const sc_particles *p, const sc_contacts *c,
         st->mvops = 1;
         return SC_OK;
     }
-    MsCtrl *hctrl = pinned_ctrl();
+    char *slots = pinned_slots();
     Events ev;
-    if (!hctrl || !ev.ok) return SC_ERR_HIP;
+    if (!slots || !ev.ok) return SC_ERR_HIP;
+    MsCtrl *hc0 = reinterpret_cast<MsCtrl *>(slots);
+    MsCtrl *hc1 = reinterpret_cast<MsCtrl *>(slots + kPinnedSlot);
+    MsCtrl *hctrl[2] = {hc0, hc1};
     hipEvent_t t0 = ev.e[0], t1 = ev.e[1];
 
     const MsView V{n, nc, pl.order, pl.inc_ptr, pl.inc, pl.dpm, c->ci, c->cj, pl.cs, pl.pdat,
@@ -584,10 +939,10 @@ extern "C" int sc_solve_lcp_mob(const sc_particles *p, const sc_contacts *c,
     k_ms_finish<kAlpha0><<<1, kBlock, 0, s>>>(part, gb, ctrl, tol, max_iter, bb);
     SC_HIP_TRY(hipGetLastError());
     // a gamma0 that already meets the tolerance needs no iteration: wait once
-    SC_HIP_TRY(hipMemcpyAsync(&hctrl[1], ctrl, sizeof(MsCtrl), hipMemcpyDeviceToHost, s));
+    SC_HIP_TRY(hipMemcpyAsync(hctrl[1], ctrl, sizeof(MsCtrl), hipMemcpyDeviceToHost, s));
     SC_HIP_TRY(hipEventRecord(ev.e[3], s));
     SC_HIP_TRY(hipEventSynchronize(ev.e[3]));
-    bool stop = hctrl[1].done != 0;
+    bool stop = hctrl[1]->done != 0;
 
     // iterations in chunks of K; `done` is read one chunk behind, so the
     // GPU always has the next chunk queued
@@ -606,11 +961,11 @@ extern "C" int sc_solve_lcp_mob(const sc_particles *p, const sc_contacts *c,
         }
         SC_HIP_TRY(hipGetLastError());
         const int slot = chunk & 1;
-        SC_HIP_TRY(hipMemcpyAsync(&hctrl[slot], ctrl, sizeof(MsCtrl), hipMemcpyDeviceToHost, s));
+        SC_HIP_TRY(hipMemcpyAsync(hctrl[slot], ctrl, sizeof(MsCtrl), hipMemcpyDeviceToHost, s));
         SC_HIP_TRY(hipEventRecord(ev.e[2 + slot], s));
         if (chunk > 0) {
             SC_HIP_TRY(hipEventSynchronize(ev.e[2 + (slot ^ 1)]));
-            if (hctrl[slot ^ 1].done) stop = true;
+            if (hctrl[slot ^ 1]->done) stop = true;
         }
     }
     SC_HIP_TRY(hipEventRecord(t1, s));
@@ -641,6 +996,151 @@ extern "C" int sc_solve_lcp_mob(const sc_particles *p, const sc_contacts *c,
     st->residual = hc.res;
     st->alpha = hc.alpha;
     st->n_degenerate = hc.ndegen;
+    st->kernel_ms = ms;
+    st->grid = gb;
+    st->block = kBlock;
+    st->lanes_per_particle = kMsLanes;
+    st->op = SC_OP_CALLBACK;
+    return hc.status;
+}
+
+extern "C" size_t sc_adjoint_mob_work_bytes(int32_t n, int32_t capacity) {
+    if (n < 0 || capacity < 0) return 0;
+    return am_ws_bytes(n, capacity);
+}
+
+extern "C" int sc_solve_lcp_adjoint_mob(const sc_particles *p, const sc_box *box,
+                                        const sc_contacts *c, const double *u_nc,
+                                        const double *f_ext, double dt, const double *gamma,
+                                        const double *dL_dgamma, const double *dL_df,
+                                        sc_mobility_fn mob, void *mob_ctx,
+                                        sc_mobility_grad_fn mob_grad, void *mob_grad_ctx,
+                                        const sc_adjoint_opts *opts, int32_t check_every,
+                                        double *dL_dq, double *dL_dpos, sc_stats *st, void *ws,
+                                        size_t ws_bytes, void *stream_) {
+    if (!p || !box || !c || !opts || !st || !mob || p->n < 0 || c->count < 0 ||
+        c->count > c->capacity)
+        return SC_ERR_INVALID;
+    if (!(dt > 0.0) || !std::isfinite(dt) || !(opts->tol > 0.0) || opts->max_iter < 0 ||
+        check_every < 0 || check_every > 4096)
+        return SC_ERR_INVALID;
+    Plan pl;
+    if (!carve_plan(c->plan, c->plan_bytes, p->n, c->capacity, pl)) return SC_ERR_INVALID;
+    const int n = p->n, nc = c->count;
+    if (n > 0 && (!dL_dpos || !p->pos || !p->axis || !p->half_len || !p->mob || !u_nc ||
+                  (mob_grad && !f_ext)))
+        return SC_ERR_INVALID;
+    if (nc > 0 && (!gamma || !dL_dq || !c->ci || !c->cj || !c->frame)) return SC_ERR_INVALID;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 ||
+        ws_bytes < am_ws_bytes(n, c->capacity))
+        return SC_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream_);
+    *st = sc_stats{};
+    if (nc == 0) {
+        // no constraints: gamma and w are empty, every term vanishes
+        if (n > 0) SC_HIP_TRY(hipMemsetAsync(dL_dpos, 0, 3 * sizeof(double) * n, s));
+        SC_HIP_TRY(hipStreamSynchronize(s));
+        st->status = SC_OK;
+        return SC_OK;
+    }
+    const size_t cap = static_cast<size_t>(c->capacity), nn = static_cast<size_t>(n);
+    Carver cv{static_cast<char *>(ws), ws_bytes};
+    double *r = cv.take<double>(cap), *tv = cv.take<double>(cap), *x = cv.take<double>(cap);
+    double *pv[2] = {cv.take<double>(cap), cv.take<double>(cap)};
+    double *grad = cv.take<double>(3 * cap);
+    double *F = cv.take<double>(6 * nn), *U = cv.take<double>(6 * nn);
+    double *Fw = cv.take<double>(6 * nn), *Vw = cv.take<double>(6 * nn);
+    double *Fc = cv.take<double>(6 * nn), *Uc = cv.take<double>(6 * nn);
+    double *Ftot = cv.take<double>(6 * nn);
+    double *Vw8 = cv.take<double>(8 * nn), *Uc8 = cv.take<double>(8 * nn);
+    double *gm = cv.take<double>(3 * nn);
+    double *part = cv.take<double>(kNV * static_cast<size_t>(kMaxReduceBlocks));
+    CgMobCtrl *ctrl = cv.take<CgMobCtrl>(1);
+    if (!cv.ok) return SC_ERR_WORKSPACE;
+    char *slots = pinned_slots();
+    Events ev;
+    if (!slots || !ev.ok) return SC_ERR_HIP;
+    CgMobCtrl *hctrl[2] = {reinterpret_cast<CgMobCtrl *>(slots),
+                           reinterpret_cast<CgMobCtrl *>(slots + kPinnedSlot)};
+
+    const MsView V{n, nc, pl.order, pl.inc_ptr, pl.inc, pl.dpm, c->ci, c->cj, pl.cs, pl.pdat,
+                   c->frame, c->q};
+    const int sb = grid_for(static_cast<long long>(n) * kMsLanes);
+    int gb = grid_for(nc);
+    if (gb > kMaxReduceBlocks) gb = kMaxReduceBlocks;
+    const double tol = opts->tol;
+    const int max_iter = opts->max_iter;
+    const int K = check_every > 0 ? check_every : 4;
+    int rc = SC_OK;
+
+    SC_HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(CgMobCtrl), s));
+    SC_HIP_TRY(hipEventRecord(ev.e[0], s));
+    k_am_rhs<<<gb, kBlock, 0, s>>>(V, gamma, dL_dgamma, dL_df, r, x, pv[0], part);
+    k_am_finish<0><<<1, kBlock, 0, s>>>(part, gb, ctrl, tol, max_iter);
+    SC_HIP_TRY(hipGetLastError());
+    SC_HIP_TRY(hipMemcpyAsync(hctrl[1], ctrl, sizeof(CgMobCtrl), hipMemcpyDeviceToHost, s));
+    SC_HIP_TRY(hipEventRecord(ev.e[3], s));
+    SC_HIP_TRY(hipEventSynchronize(ev.e[3]));
+    bool stop = hctrl[1]->done != 0;
+    int chunk = 0;
+    for (int i0 = 1; i0 <= max_iter && !stop; i0 += K, ++chunk) {
+        const int i1 = i0 + K - 1 < max_iter ? i0 + K - 1 : max_iter;
+        for (int i = i0; i <= i1; ++i) {
+            const int cur = (i - 1) & 1, nxt = i & 1;
+            k_am_scatter<<<sb, kBlock, 0, s>>>(V, r, pv[cur], pv[nxt], ctrl, F);
+            rc = mob(mob_ctx, n, F, U, s);
+            if (rc) return rc;
+            k_am_gather<<<gb, kBlock, 0, s>>>(V, U, gamma, pv[nxt], tv, ctrl, part);
+            k_am_finish<1><<<1, kBlock, 0, s>>>(part, gb, ctrl, tol, max_iter);
+            k_am_update<<<gb, kBlock, 0, s>>>(nc, pv[nxt], tv, x, r, ctrl, part);
+            k_am_finish<2><<<1, kBlock, 0, s>>>(part, gb, ctrl, tol, max_iter);
+        }
+        SC_HIP_TRY(hipGetLastError());
+        const int slot = chunk & 1;
+        SC_HIP_TRY(hipMemcpyAsync(hctrl[slot], ctrl, sizeof(CgMobCtrl), hipMemcpyDeviceToHost, s));
+        SC_HIP_TRY(hipEventRecord(ev.e[2 + slot], s));
+        if (chunk > 0) {
+            SC_HIP_TRY(hipEventSynchronize(ev.e[2 + (slot ^ 1)]));
+            if (hctrl[slot ^ 1]->done) stop = true;
+        }
+    }
+    SC_HIP_TRY(hipEventRecord(ev.e[1], s));
+    // dL/dq = -w on A; F_w = D w, V_w = Mob F_w; F_c = D gamma, U_c = Mob F_c
+    k_am_post<<<grid_for(nc), kBlock, 0, s>>>(nc, gamma, x, dL_dq);
+    k_ms_scatter<false><<<sb, kBlock, 0, s>>>(V, x, nullptr, nullptr, nullptr, nullptr, Fw);
+    rc = mob(mob_ctx, n, Fw, Vw, s);
+    if (rc) return rc;
+    k_ms_scatter<false><<<sb, kBlock, 0, s>>>(V, gamma, nullptr, nullptr, nullptr, nullptr, Fc);
+    rc = mob(mob_ctx, n, Fc, Uc, s);
+    if (rc) return rc;
+    // the per-contact geometric part, with the velocities of this mobility
+    k_am_rank8<<<grid_for(n), kBlock, 0, s>>>(n, pl.order, Vw, Vw8);
+    k_am_rank8<<<grid_for(n), kBlock, 0, s>>>(n, pl.order, Uc, Uc8);
+    const PBox pb{{box->len[0], box->len[1], box->len[2]}, box->periodic ? 1 : 0};
+    k_am_contact_grad<<<grid_for(nc), kBlock, 0, s>>>(nc, c->ci, c->cj, pl.cs, p->pos, p->axis,
+                                                      p->half_len, pb, gamma, x, dL_df, Vw8, u_nc,
+                                                      Uc8, 1.0 / dt, grad);
+    k_am_gather_pos<<<grid_for(n), kBlock, 0, s>>>(n, pl, grad, dL_dpos);
+    // the mobility's own dependence on the centres: -d/dc [F_w^T Mob(c) (F_c + F_ext)]
+    if (mob_grad) {
+        SC_HIP_TRY(hipMemcpyAsync(Ftot, Fc, 6 * sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+        k_am_add<<<grid_for(6LL * n), kBlock, 0, s>>>(6LL * n, Ftot, f_ext);
+        rc = mob_grad(mob_grad_ctx, n, Fw, Ftot, gm, s);
+        if (rc) return rc;
+        k_am_sub<<<grid_for(3LL * n), kBlock, 0, s>>>(3LL * n, dL_dpos, gm);
+    }
+    SC_HIP_TRY(hipGetLastError());
+    CgMobCtrl hc;
+    SC_HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(CgMobCtrl), hipMemcpyDeviceToHost, s));
+    SC_HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0.0f;
+    SC_HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+    st->status = hc.status;
+    st->iters = hc.iters;
+    st->mvops = hc.iters;
+    st->n_active = hc.n_active;
+    st->residual = hc.res;
+    st->alpha = hc.alpha;
     st->kernel_ms = ms;
     st->grid = gb;
     st->block = kBlock;

@@ -226,3 +226,111 @@ def test_rpy_product_in_a_hip_graph():
         assert torch.equal(U_g, U_e), k
     Uo = (OM.rpy_dense(pos.cpu().numpy(), s.hydro_radius) @ F.cpu().numpy().ravel()).reshape(s.n, 6)
     np.testing.assert_allclose(U_g.cpu().numpy(), Uo, rtol=0, atol=1e-13 * np.abs(Uo).max())
+
+
+@pytest.mark.parametrize("n", [7, 300, 1100])
+def test_rpy_gradient_matches_oracle(n):
+    import paper_1909_06623_amd as sc
+    rng = np.random.default_rng(50 + n)
+    pos = rng.uniform(0.0, 1.2 * max(1.0, n ** (1 / 3)), (n, 3))
+    rad = rng.uniform(0.2, 0.7, n)
+    pos[1] = pos[0] + [0.02, 0.0, 0.0]          # contained
+    rad[0], rad[1] = 0.7, 0.2
+    pos[3] = pos[2] + [0.5, 0.3, 0.0]          # overlapping
+    rad[2], rad[3] = 0.5, 0.45
+    a = rng.standard_normal((n, 6))
+    f = rng.standard_normal((n, 6))
+    _say(f"rpy gradient n={n}")
+    R = sc.RPY(torch.from_numpy(pos).cuda(), torch.from_numpy(rad).cuda(), mu=0.8)
+    g = R.grad(torch.from_numpy(a).cuda(), torch.from_numpy(f).cuda()).cpu().numpy()
+    go = OM.rpy_grad(pos, rad, a, f, 0.8)
+    np.testing.assert_allclose(g, go, rtol=0, atol=1e-12 * np.abs(go).max())
+
+
+@pytest.mark.parametrize("loss", ["force", "linear"])
+def test_rpy_adjoint_matches_oracle(loss):
+    import paper_1909_06623_amd as sc
+    s = _free_spheres(300, W.SEED_BASE + 913, phi=0.35)
+    s.dt = 0.01
+    _say(f"rpy adjoint, {loss} loss")
+    P, box = _gpu(s)
+    R = sc.RPY(P.pos, P.radius)
+    fe = torch.from_numpy(s.f_ext).cuda()
+    u_nc = R.apply(fe)
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, assemble=False)
+    gam, g, st, f_c, _ = sc.solve_lcp_mob(P, con, R, tol=1e-10, want_fc=True)
+    assert st["status"] == 0
+    c = O.find_contacts(s)
+    Mob = OM.rpy_dense(s.pos, s.radius)
+    q_o = O.build_q(c, (Mob @ s.f_ext.ravel()).reshape(s.n, 6), s.dt)
+    M = OM.contact_matrix(O.D_matrix(s.n, c), Mob)
+    go, _, _ = OM.bbpgd_dense(M, q_o, O.M_diag(s, c), tol=1e-10)
+    gp, _, passes = OM.polish_dense(M, q_o, go)
+    pm = con.canonical_order().cpu().numpy()
+    assert passes > 0 and np.array_equal(gam.cpu().numpy()[pm] > 0, gp > 0)
+    if loss == "force":
+        dq, dpos, sta = sc.solve_lcp_adjoint_mob(P, box, con, u_nc, s.dt, gam, R, f_ext=fe,
+                                                 dL_df=f_c, tol=1e-13)
+        rq, rpos, _ = OM.adjoint_rpy(s, c, gp, dL_dF=O.D_apply(s.n, c, gp))
+    else:
+        wts = np.random.default_rng(3).standard_normal(c.nc)
+        wg = np.empty_like(wts)
+        wg[pm] = wts
+        dq, dpos, sta = sc.solve_lcp_adjoint_mob(P, box, con, u_nc, s.dt, gam, R, f_ext=fe,
+                                                 dL_dgamma=torch.from_numpy(wg).cuda(),
+                                                 tol=1e-13)
+        rq, rpos, _ = OM.adjoint_rpy(s, c, gp, dL_dgamma=wts)
+    assert sta["status"] == 0 and sta["op"] == 3
+    np.testing.assert_allclose(dq.cpu().numpy()[pm], rq, rtol=0, atol=1e-7 * np.abs(rq).max())
+    np.testing.assert_allclose(dpos.cpu().numpy(), rpos, rtol=0, atol=1e-7 * np.abs(rpos).max())
+    assert np.abs(dpos.cpu().numpy().sum(axis=0)).max() < 1e-9 * np.abs(rpos).max()
+
+
+def test_dry_callback_adjoint_equals_persistent_adjoint():
+    import paper_1909_06623_amd as sc
+    s = W.rods_and_spheres(1000, 200, seed=W.SEED_BASE + 914)
+    _say("dry adjoint through the callback")
+    P, box = _gpu(s)
+    u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt)
+    gam, _, st, f_c, _ = sc.solve_lcp(P, con, tol=1e-10, want_fc=True)
+    assert st["status"] == 0
+    dq_p, dpos_p, sp = sc.solve_lcp_adjoint(P, box, con, u_nc, s.dt, gam, dL_df=f_c, tol=1e-13)
+    dq, dpos, sm = sc.solve_lcp_adjoint_mob(P, box, con, u_nc, s.dt, gam, sc.DryMobility(P),
+                                            dL_df=f_c, tol=1e-13)
+    assert sp["status"] == 0 and sm["status"] == 0
+    np.testing.assert_allclose(dq.cpu().numpy(), dq_p.cpu().numpy(), rtol=0,
+                               atol=1e-8 * float(dq_p.abs().max()))
+    np.testing.assert_allclose(dpos.cpu().numpy(), dpos_p.cpu().numpy(), rtol=0,
+                               atol=1e-8 * float(dpos_p.abs().max()))
+
+
+def test_mob_adjoint_edge_cases():
+    import paper_1909_06623_amd as sc
+    import paper_1909_06623_amd._abi as A
+    s = _free_spheres(200, W.SEED_BASE + 915)
+    _say("mobility adjoint edge cases")
+    P, box = _gpu(s)
+    R = sc.RPY(P.pos, P.radius)
+    fe = torch.from_numpy(s.f_ext).cuda()
+    u_nc = R.apply(fe)
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, assemble=False)
+    gam, _, st, f_c, _ = sc.solve_lcp_mob(P, con, R, tol=1e-10, want_fc=True)
+    # max_iter = 0: not converged, dL/dq = 0
+    dq, dpos, st0 = sc.solve_lcp_adjoint_mob(P, box, con, u_nc, s.dt, gam, R, f_ext=fe,
+                                             dL_df=f_c, max_iter=0)
+    assert st0["status"] == A.SC_NOT_CONVERGED and float(dq.abs().max()) == 0.0
+    # a zero loss: converged at once, zero gradients
+    dq, dpos, stz = sc.solve_lcp_adjoint_mob(P, box, con, u_nc, s.dt, gam, R, f_ext=fe,
+                                             dL_dgamma=torch.zeros_like(gam))
+    assert stz["status"] == 0 and stz["iters"] == 0
+    assert float(dq.abs().max()) == 0.0 and float(dpos.abs().max()) == 0.0
+    # chunk sizes do not change the result
+    a1 = sc.solve_lcp_adjoint_mob(P, box, con, u_nc, s.dt, gam, R, f_ext=fe, dL_df=f_c,
+                                  check_every=1)
+    a2 = sc.solve_lcp_adjoint_mob(P, box, con, u_nc, s.dt, gam, R, f_ext=fe, dL_df=f_c,
+                                  check_every=64)
+    assert torch.equal(a1[0], a2[0]) and torch.equal(a1[1], a2[1])
+    # the RPY mobility needs f_ext
+    with pytest.raises(sc.ScError):
+        sc.solve_lcp_adjoint_mob(P, box, con, u_nc, s.dt, gam, R, dL_df=f_c)
