@@ -172,6 +172,18 @@ def hydro(sc, W, torch, np, steps):
         "mvops": st["mvops"], "n_active": st["n_active"], "solve_ms": wall,
         "gpu_ms": st["kernel_ms"], "ms_per_product": st["kernel_ms"] / max(1, st["mvops"]),
         "rpy_share": min(1.0, ms * st["mvops"] / max(1e-9, st["kernel_ms"]))}
+    # the adjoint of L = 1/2 ||D gamma||^2 through RPY (CG, geometric terms and
+    # the RPY centre gradient)
+    fe = torch.from_numpy(s.f_ext).cuda()
+    gam, _, _, f_c, _ = sc.solve_lcp_mob(P, con, R, tol=s.tol, want_fc=True)
+    sc.solve_lcp_adjoint_mob(P, box, con, u_nc, s.dt, gam, R, f_ext=fe, dL_df=f_c, tol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, sta = sc.solve_lcp_adjoint_mob(P, box, con, u_nc, s.dt, gam, R, f_ext=fe, dL_df=f_c,
+                                         tol=1e-10)
+    adj_ms = 1e3 * (time.perf_counter() - t0)
+    out["solve_rpy"]["adjoint"] = {"ms": adj_ms, "status": sta["status"], "cg_iters": sta["iters"],
+                                   "adjoint_forward_ratio": adj_ms / wall}
 
     for n, nsteps in ((1000, steps), (20000, max(2, steps // 4))):
         s = W.sphere_cluster(n, W.SEED_BASE + 900 + (n == 20000))

@@ -11,10 +11,15 @@ library):
   it returns dL/d(centres) and stores dL/dq in the ``SolveInfo``.
 * ``lcp_solve(q, ...)``: the solve on a fixed contact set as a function of q,
   returning gamma; its backward returns dL/dq = -w with M_AA w_A = dL/dgamma_A.
+* ``hydro_collision_solve(pos, ...)``: as ``collision_solve`` with the RPY
+  mobility of spheres: U_nc = Mob(c) F_ext and every product of the solve go
+  through it, and the backward includes the mobility's dependence on the
+  centres (``sc_solve_lcp_adjoint_mob``).
 
-Orientations, radii, mobility coefficients and U_nc receive no gradient. The
-contact set is piecewise constant in the centres; the gradient is that of the
-active branch.
+Orientations, radii and mobility coefficients receive no gradient, and U_nc
+none in ``collision_solve`` (the dry mobility does not depend on the
+centres). The contact set is piecewise constant in the centres; the
+gradient is that of the active branch.
 """
 from __future__ import annotations
 
@@ -25,7 +30,8 @@ from typing import Optional
 import torch
 from torch.autograd.function import once_differentiable
 
-from .api import Box, Contacts, Particles, build_contacts, solve_lcp, solve_lcp_adjoint
+from .api import (RPY, Box, Contacts, Particles, build_contacts, solve_lcp, solve_lcp_adjoint,
+                  solve_lcp_adjoint_mob, solve_lcp_mob)
 
 
 @dataclasses.dataclass
@@ -83,6 +89,32 @@ class _LcpSolve(torch.autograd.Function):
         return dq, None, None, None, None, None, None, None, None, None
 
 
+class _HydroCollisionSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, pos, particles, box, f_ext, hydro_radius, mu, dt, delta, tol, adjoint_tol,
+                info):
+        P = dataclasses.replace(particles, pos=pos.detach().to(torch.float64).contiguous())
+        R = RPY(P.pos, hydro_radius, mu)
+        u_nc = R.apply(f_ext)
+        con = build_contacts(P, box, delta, u_nc, dt, assemble=False)
+        gamma, g, st, f_c, u_c = solve_lcp_mob(P, con, R, tol=tol, want_fc=True)
+        info.contacts, info.stats = con, st
+        ctx.state = (P, box, con, R, f_ext, u_nc, dt, adjoint_tol, info)
+        ctx.save_for_backward(gamma)
+        return gamma, f_c
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, dL_dgamma, dL_df):
+        (gamma,) = ctx.saved_tensors
+        P, box, con, R, f_ext, u_nc, dt, adjoint_tol, info = ctx.state
+        dq, dpos, sta = solve_lcp_adjoint_mob(P, box, con, u_nc, dt, gamma, R, f_ext=f_ext,
+                                              dL_dgamma=dL_dgamma, dL_df=dL_df,
+                                              tol=adjoint_tol)
+        info.dL_dq, info.adjoint_stats = dq, sta
+        return dpos, None, None, None, None, None, None, None, None, None, None
+
+
 def _adjoint_kw(kw):
     keep = ("lanes_per_particle", "grid", "block", "op", "slices_per_wave",
             "lds_entries_per_wave", "workspace")
@@ -110,3 +142,20 @@ def lcp_solve(q: torch.Tensor, particles: Particles, box: Box, contacts: Contact
     gamma = _LcpSolve.apply(q, particles, box, contacts, u_nc, float(dt), float(tol),
                             float(adjoint_tol), info, solve_kw)
     return gamma, info
+
+
+def hydro_collision_solve(pos: torch.Tensor, particles: Particles, box: Box,
+                          f_ext: torch.Tensor, dt: float, delta: float,
+                          hydro_radius: Optional[torch.Tensor] = None, mu: float = 1.0,
+                          tol: float = 1e-6, adjoint_tol: float = 1e-10,
+                          info: Optional[SolveInfo] = None):
+    """(gamma, F_c, info) for sphere centres ``pos`` [n, 3] with the RPY
+    mobility (hydrodynamic radii default to the collision radii), external
+    forces and torques ``f_ext`` [n, 6]; differentiable in ``pos``."""
+    info = SolveInfo() if info is None else info
+    hr = particles.radius if hydro_radius is None else hydro_radius
+    f_ext = f_ext.to(device="cuda", dtype=torch.float64).contiguous()
+    hr = hr.to(device="cuda", dtype=torch.float64).contiguous()
+    gamma, f_c = _HydroCollisionSolve.apply(pos, particles, box, f_ext, hr, float(mu), float(dt),
+                                            float(delta), float(tol), float(adjoint_tol), info)
+    return gamma, f_c, info
