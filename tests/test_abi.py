@@ -110,3 +110,56 @@ def test_product_path_has_no_cpu_fallback():
             A.lib()
     finally:
         A._lib, A.LIB_PATH = saved
+
+
+def test_mobility_entry_points_reject_bad_arguments_without_device_work():
+    """The solve and adjoint behind a mobility function, and the RPY
+    functions, validate their arguments before touching the device."""
+    from paper_1909_06623_amd import _abi as A
+    L = A.lib()
+    rpy_fn = ctypes.cast(L.sc_rpy_apply, ctypes.c_void_p)
+    p0 = A.sc_particles(0, 0, 0, 0, 0, 0, 0)
+    c = A.sc_contacts()
+    c.capacity, c.count = 0, 0
+    st = A.sc_stats()
+    opts = A.sc_solve_opts(1e-6, 100, 1, 0, 0)
+    # no mobility function; bad options; count beyond capacity
+    assert L.sc_solve_lcp_mob(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(opts), None,
+                              None, 0, None, None, None, None, ctypes.byref(st), None, 0,
+                              None) == A.SC_ERR_INVALID
+    for bad in (A.sc_solve_opts(0.0, 100, 1, 0, 0), A.sc_solve_opts(1e-6, -1, 1, 0, 0),
+                A.sc_solve_opts(1e-6, 100, 4, 0, 0)):
+        assert L.sc_solve_lcp_mob(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(bad), rpy_fn,
+                                  None, 0, None, None, None, None, ctypes.byref(st), None, 0,
+                                  None) == A.SC_ERR_INVALID
+    assert L.sc_solve_lcp_mob(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(opts), rpy_fn,
+                              None, -1, None, None, None, None, ctypes.byref(st), None, 0,
+                              None) == A.SC_ERR_INVALID
+    c.capacity, c.count = 2, 3
+    assert L.sc_solve_lcp_mob(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(opts), rpy_fn,
+                              None, 0, None, None, None, None, ctypes.byref(st), None, 0,
+                              None) == A.SC_ERR_INVALID
+    c.capacity, c.count = 0, 0
+    # the adjoint: no mobility, dt <= 0, tol <= 0
+    box = A.sc_box()
+    aopts = A.sc_adjoint_opts(1e-10, 100)
+    args = lambda dt, o, fn: (ctypes.byref(p0), ctypes.byref(box), ctypes.byref(c), None, None,
+                              dt, None, None, None, fn, None, None, None, ctypes.byref(o), 0,
+                              None, None, ctypes.byref(st), None, 0, None)
+    assert L.sc_solve_lcp_adjoint_mob(*args(1e-3, aopts, None)) == A.SC_ERR_INVALID
+    assert L.sc_solve_lcp_adjoint_mob(*args(0.0, aopts, rpy_fn)) == A.SC_ERR_INVALID
+    assert L.sc_solve_lcp_adjoint_mob(*args(1e-3, A.sc_adjoint_opts(0.0, 100), rpy_fn)) == \
+        A.SC_ERR_INVALID
+    # RPY: n mismatch, mu <= 0, no work buffer; n = 0 is a no-op
+    R = A.sc_rpy(4, 0, 0, 0, 1.0, 0, 0)
+    assert L.sc_rpy_apply(ctypes.addressof(R), 3, None, None, None) == A.SC_ERR_INVALID
+    assert L.sc_rpy_grad(ctypes.addressof(R), 3, None, None, None, None) == A.SC_ERR_INVALID
+    R.mu = 0.0
+    assert L.sc_rpy_apply(ctypes.addressof(R), 4, None, None, None) == A.SC_ERR_INVALID
+    R.mu = 1.0
+    R.pos, R.radius = 256, 256
+    assert L.sc_rpy_apply(ctypes.addressof(R), 4, 256, 256, None) == A.SC_ERR_WORKSPACE
+    R0 = A.sc_rpy(0, 0, 0, 0, 1.0, 0, 0)
+    assert L.sc_rpy_apply(ctypes.addressof(R0), 0, None, None, None) == A.SC_OK
+    assert L.sc_rpy_work_bytes(1000) >= 3 * 8 * 1000
+    assert L.sc_solve_mob_work_bytes(-1, 10) == 0 and L.sc_adjoint_mob_work_bytes(10, -1) == 0
