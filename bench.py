@@ -456,6 +456,19 @@ def main():
                "sample": f"the full workload once: cell-list contacts {tc:.1f} s + "
                          f"BBPGD {ts:.1f} s ({sto.iters} iterations), serial FP64 C",
                "solve_only_rods_per_s": s.n / ts, "iters": sto.iters}
+        if not args.no_hydro:
+            # the oracle's time step behind the RPY mobility (dense NumPy on one
+            # thread) on the 1000-sphere cluster, beside the GPU's in `hydro`
+            import oracle.timestep as OT
+            from threadpoolctl import threadpool_limits
+            cl = W.sphere_cluster(1000, W.SEED_BASE + 900)
+            with threadpool_limits(1):
+                t1 = time.perf_counter()
+                OT.step(cl, OT.quat_from_axis(cl.axis), None, hydro="rpy")
+                tr = time.perf_counter() - t1
+            cpu["rpy_cluster1000_step_ms"] = 1e3 * tr
+            cpu["rpy_sample"] = ("one time step of the 1000-sphere cluster with the RPY mobility: "
+                                 "contacts, dense Mob and M, Algorithm 1, update; one thread")
 
     line = {
         "metric": "BBPGD solve time to res 1e-6 (rods/s), HBM GB/s; adjoint/forward time ratio",
