@@ -370,3 +370,62 @@ def test_hydro_collision_solve_autograd():
     _, rpos, _ = OM.adjoint_rpy(s, c, gp, dL_dF=O.D_apply(s.n, c, gp))
     np.testing.assert_allclose(pos.grad.cpu().numpy(), rpos, rtol=0,
                                atol=1e-7 * np.abs(rpos).max())
+
+
+def _rpy_rows(pos, rad, F, rows, mu=1.0):
+    """Rows of the RPY product computed by the oracle's pair formula, one
+    target at a time (vectorised over the sources only through rpy_block)."""
+    out = np.zeros((len(rows), 3))
+    for r, i in enumerate(rows):
+        acc = F[i, :3] / (6.0 * math.pi * mu * rad[i])
+        for j in range(pos.shape[0]):
+            if j != i:
+                acc = acc + OM.rpy_block(pos[i] - pos[j], rad[i], rad[j], mu) @ F[j, :3]
+        out[r] = acc
+    return out
+
+
+def test_rpy_product_at_100k_sampled_rows():
+    """100,000 spheres (few source splits, many target blocks): sampled rows
+    against the oracle's pair formula."""
+    import paper_1909_06623_amd as sc
+    rng = np.random.default_rng(17)
+    n = 100_000
+    side = (n * 4.18879 / 0.2) ** (1 / 3)
+    pos = rng.uniform(0.0, side, (n, 3))
+    rad = rng.uniform(0.8, 1.2, n)
+    F = rng.standard_normal((n, 6))
+    _say("rpy product, 100000 spheres, sampled rows")
+    R = sc.RPY(torch.from_numpy(pos).cuda(), torch.from_numpy(rad).cuda())
+    U = R.apply(torch.from_numpy(F).cuda()).cpu().numpy()
+    rows = rng.choice(n, 4, replace=False)
+    ref = _rpy_rows(pos, rad, F, rows)
+    np.testing.assert_allclose(U[rows, :3], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_rpy_solve_at_bench_size_properties():
+    """The benchmark's RPY solve (20,000 overlapping spheres): KKT, F_c = D
+    gamma against the oracle's D on the oracle's contact list, U_c on sampled
+    rows against the oracle's pair formula."""
+    import paper_1909_06623_amd as sc
+    s = W.spheres(20000, 0.3, W.SEED_BASE + 909)
+    s.periodic = 0
+    _say("rpy solve at 20000 spheres, properties")
+    P, box = _gpu(s)
+    R = sc.RPY(P.pos, P.radius)
+    u_nc = R.apply(torch.from_numpy(s.f_ext).cuda())
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, assemble=False)
+    gam, g, st, f_c, u_c = sc.solve_lcp_mob(P, con, R, tol=s.tol, want_fc=True)
+    assert st["status"] == 0 and st["n_active"] > 10000
+    ga, gg = gam.cpu().numpy(), g.cpu().numpy()
+    assert ga.min() >= 0.0 and gg.min() > -s.tol
+    assert np.linalg.norm(np.minimum(ga, gg)) < s.tol
+    c = O.find_contacts(s)
+    pm = con.canonical_order().cpu().numpy()
+    assert con.count == c.nc
+    F_o = O.D_apply(s.n, c, ga[pm])
+    np.testing.assert_allclose(f_c.cpu().numpy(), F_o, rtol=0, atol=1e-12 * np.abs(F_o).max())
+    rows = np.random.default_rng(9).choice(s.n, 3, replace=False)
+    ref = _rpy_rows(s.pos, s.radius, f_c.cpu().numpy(), rows)
+    np.testing.assert_allclose(u_c.cpu().numpy()[rows, :3], ref, rtol=0,
+                               atol=1e-11 * max(1.0, np.abs(ref).max()))
