@@ -429,3 +429,48 @@ def test_rpy_solve_at_bench_size_properties():
     ref = _rpy_rows(s.pos, s.radius, f_c.cpu().numpy(), rows)
     np.testing.assert_allclose(u_c.cpu().numpy()[rows, :3], ref, rtol=0,
                                atol=1e-11 * max(1.0, np.abs(ref).max()))
+
+
+def test_rpy_solve_with_walls_matches_oracle():
+    """Spheres pushed onto the floor of a closed box, with the RPY mobility
+    (the walls enter through their D columns only): GPU solve, forces and
+    adjoint against the oracle."""
+    import paper_1909_06623_amd as sc
+    rng = np.random.default_rng(21)
+    n = 120
+    pos = np.column_stack([rng.uniform(0.6, 7.4, n), rng.uniform(0.6, 7.4, n),
+                           rng.uniform(0.45, 1.6, n)])
+    rad = np.full(n, 0.5)
+    f = np.zeros((n, 6))
+    f[:, 2] = -5.0
+    f[:, :3] += rng.standard_normal((n, 3))
+    s = W.Suspension("floor_rpy", pos, np.tile([0.0, 0.0, 1.0], (n, 1)), rad, np.zeros(n),
+                     W.sphere_mobility(rad), f, np.full(3, 8.0), 0.1, 0.01, 1e-10, periodic=0,
+                     walls=63)
+    _say("rpy solve with walls")
+    P, box = _gpu(s)
+    R = sc.RPY(P.pos, P.radius)
+    fe = torch.from_numpy(f).cuda()
+    u_nc = R.apply(fe)
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, assemble=False)
+    c = O.find_contacts(s)
+    assert con.count == c.nc and np.count_nonzero(c.j < 0) >= 10
+    gam, g, st, f_c, _ = sc.solve_lcp_mob(P, con, R, tol=1e-10, want_fc=True)
+    assert st["status"] == 0
+    Mob = OM.rpy_dense(s.pos, rad)
+    q_o = O.build_q(c, (Mob @ f.ravel()).reshape(n, 6), s.dt)
+    M = OM.contact_matrix(O.D_matrix(n, c), Mob)
+    go, _, sto = OM.bbpgd_dense(M, q_o, O.M_diag(s, c), tol=1e-10)
+    gp, _, _ = OM.polish_dense(M, q_o, go)
+    pm = con.canonical_order().cpu().numpy()
+    np.testing.assert_allclose(gam.cpu().numpy()[pm], go, rtol=0,
+                               atol=1e-6 * max(1.0, np.abs(go).max()))
+    assert np.count_nonzero((c.j < 0) & (gp > 0)) > 5
+    if not np.array_equal(gam.cpu().numpy()[pm] > 0, gp > 0):
+        pytest.skip("active sets differ at tol 1e-10 (weakly active contacts)")
+    dq, dpos, sta = sc.solve_lcp_adjoint_mob(P, box, con, u_nc, s.dt, gam, R, f_ext=fe,
+                                             dL_df=f_c, tol=1e-13)
+    rq, rpos, _ = OM.adjoint_rpy(s, c, gp, dL_dF=O.D_apply(n, c, gp))
+    assert sta["status"] == 0
+    np.testing.assert_allclose(dq.cpu().numpy()[pm], rq, rtol=0, atol=1e-7 * np.abs(rq).max())
+    np.testing.assert_allclose(dpos.cpu().numpy(), rpos, rtol=0, atol=1e-7 * np.abs(rpos).max())
