@@ -474,3 +474,32 @@ def test_rpy_solve_with_walls_matches_oracle():
     assert sta["status"] == 0
     np.testing.assert_allclose(dq.cpu().numpy()[pm], rq, rtol=0, atol=1e-7 * np.abs(rq).max())
     np.testing.assert_allclose(dpos.cpu().numpy(), rpos, rtol=0, atol=1e-7 * np.abs(rpos).max())
+
+
+def test_rpy_nonfinite_inputs_are_reported():
+    """A NaN in the external forces reaches U_nc = Mob F_ext, and the
+    contact build rejects it (SC_ERR_NONFINITE); a NaN in a warm start
+    reaches g_0, and the solve through RPY reports SC_ERR_NONFINITE after its
+    first product. The next solve with finite data is unaffected."""
+    import paper_1909_06623_amd as sc
+    import paper_1909_06623_amd._abi as A
+    s = _free_spheres(150, W.SEED_BASE + 917)
+    _say("rpy path with NaN inputs")
+    P, box = _gpu(s)
+    R = sc.RPY(P.pos, P.radius)
+    f = s.f_ext.copy()
+    u_ok = R.apply(torch.from_numpy(f).cuda())
+    con = sc.build_contacts(P, box, s.delta, u_ok, s.dt, assemble=False)
+    assert con.count > 0
+    f[7, 1] = np.nan
+    u_bad = R.apply(torch.from_numpy(f).cuda())
+    assert not torch.isfinite(u_bad).all()
+    with pytest.raises(sc.ScError) as e:
+        sc.build_contacts(P, box, s.delta, u_bad, s.dt, assemble=False)
+    assert e.value.code == A.SC_ERR_NONFINITE
+    g0 = torch.zeros(con.count, dtype=torch.float64, device="cuda")
+    g0[3] = float("nan")
+    _, _, st, _, _ = sc.solve_lcp_mob(P, con, R, tol=1e-8, gamma0=g0)
+    assert st["status"] == A.SC_ERR_NONFINITE and st["mvops"] == 1
+    _, _, st2, _, _ = sc.solve_lcp_mob(P, con, R, tol=1e-8)
+    assert st2["status"] == 0
