@@ -6,12 +6,12 @@ kernels for gfx950 behind a C ABI (include/sc_api.h). This package is the thin
 Python binding: PyTorch provides device memory and streams only.
 """
 from ._abi import ScError, LIB_PATH  # noqa: F401
-from .api import (RPY, Batch, Box, Contacts, DryMobility, Particles, Workspace,  # noqa: F401
-                  apply_mobility, build_contacts, mvop, solve_lcp, solve_lcp_adjoint,
-                  solve_lcp_adjoint_mob, solve_lcp_mob)
+from .api import (RPY, Batch, Box, Contacts, DryMobility, FnMobility, Particles,  # noqa: F401
+                  Workspace, apply_mobility, build_contacts, mvop, solve_lcp,
+                  solve_lcp_adjoint, solve_lcp_adjoint_mob, solve_lcp_mob)
 from .autograd import SolveInfo, collision_solve, hydro_collision_solve, lcp_solve  # noqa: F401
 
-__all__ = ["Batch", "Box", "Contacts", "DryMobility", "Particles", "RPY", "Workspace",
-           "apply_mobility", "build_contacts", "mvop", "solve_lcp", "solve_lcp_adjoint",
+__all__ = ["Batch", "Box", "Contacts", "DryMobility", "FnMobility", "Particles", "RPY",
+           "Workspace", "apply_mobility", "build_contacts", "mvop", "solve_lcp", "solve_lcp_adjoint",
            "solve_lcp_adjoint_mob", "solve_lcp_mob", "ScError",
            "SolveInfo", "collision_solve", "hydro_collision_solve", "lcp_solve"]

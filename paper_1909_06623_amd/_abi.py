@@ -109,6 +109,11 @@ class sc_rpy(ctypes.Structure):
 MOBILITY_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p)
 
+# int (*)(void *ctx, int32_t n, const double *a, const double *f, double *g, void *stream)
+MOBILITY_GRAD_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p)
+
 P = ctypes.POINTER
 SIGNATURES = {
     "sc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),

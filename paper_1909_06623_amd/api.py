@@ -400,6 +400,71 @@ class DryMobility:
         return apply_mobility(self.P, f)
 
 
+class _DevView:
+    """A [shape] float64 view of device memory the library hands to a
+    mobility function (no copy; valid during the call)."""
+
+    def __init__(self, ptr, shape):
+        self.__cuda_array_interface__ = {"shape": shape, "typestr": "<f8", "data": (ptr, False),
+                                         "version": 2, "strides": None}
+
+
+def _view(ptr, shape):
+    return torch.as_tensor(_DevView(ptr, shape), device="cuda")
+
+
+class FnMobility:
+    """A mobility written in Python, for solve_lcp_mob and
+    solve_lcp_adjoint_mob: ``apply(f, u)`` writes u = Mob f into the [n, 6]
+    tensor u (f and u are views of the solver's buffers; the work goes on
+    the current stream), and the optional ``grad(a, f, g)`` writes
+    g = d/dc (a^T Mob f) into the [n, 3] tensor g. Mob must be symmetric
+    positive definite. The solver calls them through ctypes from the calling
+    thread; an exception raised inside is re-raised by the solve."""
+
+    def __init__(self, apply, grad=None):
+        self._apply, self._grad = apply, grad
+        self._error = None
+
+        def cb(ctx, n, f, u, stream):
+            try:
+                self._apply(_view(f, (n, 6)), _view(u, (n, 6)))
+                return A.SC_OK
+            except BaseException as e:  # handed back to the caller of the solve
+                self._error = e
+                return A.SC_ERR_INVALID
+
+        def gcb(ctx, n, a, f, g, stream):
+            try:
+                self._grad(_view(a, (n, 6)), _view(f, (n, 6)), _view(g, (n, 3)))
+                return A.SC_OK
+            except BaseException as e:
+                self._error = e
+                return A.SC_ERR_INVALID
+
+        self._cb = A.MOBILITY_FN(cb)
+        self._gcb = A.MOBILITY_GRAD_FN(gcb) if grad is not None else None
+
+    def fn_ctx(self):
+        return (ctypes.cast(self._cb, ctypes.c_void_p).value, None)
+
+    def grad_fn_ctx(self):
+        if self._gcb is None:
+            return None
+        return (ctypes.cast(self._gcb, ctypes.c_void_p).value, None)
+
+    def take_error(self):
+        e, self._error = self._error, None
+        return e
+
+
+def _raise_mobility_error(mobility):
+    take = getattr(mobility, "take_error", None)
+    e = take() if take is not None else None
+    if e is not None:
+        raise e
+
+
 def solve_lcp_mob(particles: Particles, contacts: Contacts, mobility, tol: float = 1e-6,
                   max_iter: int = 100000, bb: int = 1, gamma0: Optional[torch.Tensor] = None,
                   want_fc: bool = False, check_every: int = 0,
@@ -426,11 +491,13 @@ def solve_lcp_mob(particles: Particles, contacts: Contacts, mobility, tol: float
     wp = (work.data_ptr() + 255) // 256 * 256
     fn, ctx = mobility.fn_ctx()
     pc, cc = particles.c(), contacts.c()
+    ctx = None if ctx is None else ctypes.c_void_p(ctx)
     rc = A.lib().sc_solve_lcp_mob(ctypes.byref(pc), ctypes.byref(cc), ctypes.byref(opts),
-                                  ctypes.c_void_p(fn), ctypes.c_void_p(ctx), int(check_every),
+                                  ctypes.c_void_p(fn), ctx, int(check_every),
                                   _ptr(gamma), _ptr(g), _ptr(f_c), _ptr(u_c), ctypes.byref(st),
                                   ctypes.c_void_p(wp), wb + 256 - (wp - work.data_ptr()),
                                   _stream())
+    _raise_mobility_error(mobility)
     allow = (A.SC_OK,) if raise_on_nonconverged else (A.SC_OK, A.SC_NOT_CONVERGED,
                                                       A.SC_ERR_NONFINITE)
     _check("sc_solve_lcp_mob", rc, allow)
@@ -460,16 +527,18 @@ def solve_lcp_adjoint_mob(particles: Particles, box: Box, contacts: Contacts,
     work = torch.empty(wb + 256, dtype=torch.uint8, device="cuda")
     wp = (work.data_ptr() + 255) // 256 * 256
     fn, ctx = mobility.fn_ctx()
+    ctx = None if ctx is None else ctypes.c_void_p(ctx)
     gfc = mobility.grad_fn_ctx()
     gfn, gctx = (None, None) if gfc is None else gfc
     pc, bc, cc = particles.c(), box.c(), contacts.c()
     rc = A.lib().sc_solve_lcp_adjoint_mob(
         ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(cc), _ptr(u_nc), _ptr(fe), float(dt),
-        _ptr(gamma), _ptr(dLg), _ptr(dLf), ctypes.c_void_p(fn), ctypes.c_void_p(ctx),
+        _ptr(gamma), _ptr(dLg), _ptr(dLf), ctypes.c_void_p(fn), ctx,
         None if gfn is None else ctypes.c_void_p(gfn),
         None if gctx is None else ctypes.c_void_p(gctx), ctypes.byref(opts), int(check_every),
         _ptr(dq), _ptr(dpos), ctypes.byref(st), ctypes.c_void_p(wp),
         wb + 256 - (wp - work.data_ptr()), _stream())
+    _raise_mobility_error(mobility)
     _check("sc_solve_lcp_adjoint_mob", rc, (A.SC_OK, A.SC_NOT_CONVERGED))
     return dq[:nc], dpos, st.as_dict()
 

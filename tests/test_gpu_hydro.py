@@ -503,3 +503,51 @@ def test_rpy_nonfinite_inputs_are_reported():
     assert st["status"] == A.SC_ERR_NONFINITE and st["mvops"] == 1
     _, _, st2, _, _ = sc.solve_lcp_mob(P, con, R, tol=1e-8)
     assert st2["status"] == 0
+
+
+def test_python_mobility_functions():
+    """FnMobility: mobilities written with torch ops and called by the solver
+    through ctypes. The dry sphere mobility as an elementwise scaling gives
+    the dry callback's solve; the oracle's dense RPY matrix applied by a
+    torch matrix-vector product gives the built-in RPY solve and adjoint (with
+    the library's RPY gradient as the gradient function); an exception raised
+    inside the function comes back out of the solve."""
+    import paper_1909_06623_amd as sc
+    s = _free_spheres(300, W.SEED_BASE + 918)
+    _say("python mobility functions")
+    P, box = _gpu(s)
+    fe = torch.from_numpy(s.f_ext).cuda()
+    # dry sphere mobility: per particle (a_perp, a_perp, a_perp, b_perp, b_perp, b_perp)
+    scale = torch.cat([P.mob[:, 1:2].expand(-1, 3), P.mob[:, 3:4].expand(-1, 3)], dim=1)
+    dry = sc.FnMobility(lambda f, u: torch.mul(f, scale, out=u))
+    u_nc = sc.apply_mobility(P, fe)
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, assemble=False)
+    g1, _, s1, _, _ = sc.solve_lcp_mob(P, con, dry, tol=1e-10)
+    g2, _, s2, _, _ = sc.solve_lcp_mob(P, con, sc.DryMobility(P), tol=1e-10)
+    assert s1["status"] == 0 and s2["status"] == 0
+    assert torch.equal(g1, g2) and s1["iters"] == s2["iters"]
+    # the dense RPY matrix through torch
+    R = sc.RPY(P.pos, P.radius)
+    Mob = torch.from_numpy(OM.rpy_dense(s.pos, s.radius)).cuda()
+    dense = sc.FnMobility(
+        lambda f, u: u.copy_((Mob @ f.reshape(-1)).reshape(-1, 6)),
+        grad=lambda a, f, g: g.copy_(R.grad(a, f)))
+    u_r = R.apply(fe)
+    con_r = sc.build_contacts(P, box, s.delta, u_r, s.dt, assemble=False)
+    ga, _, sa, fa, _ = sc.solve_lcp_mob(P, con_r, dense, tol=1e-10, want_fc=True)
+    gb, _, sb, fb, _ = sc.solve_lcp_mob(P, con_r, R, tol=1e-10, want_fc=True)
+    assert sa["status"] == 0 and sb["status"] == 0
+    np.testing.assert_allclose(ga.cpu().numpy(), gb.cpu().numpy(), rtol=0,
+                               atol=1e-6 * max(1.0, float(gb.abs().max())))
+    da = sc.solve_lcp_adjoint_mob(P, box, con_r, u_r, s.dt, gb, dense, f_ext=fe, dL_df=fb,
+                                  tol=1e-13)
+    db = sc.solve_lcp_adjoint_mob(P, box, con_r, u_r, s.dt, gb, R, f_ext=fe, dL_df=fb,
+                                  tol=1e-13)
+    np.testing.assert_allclose(da[1].cpu().numpy(), db[1].cpu().numpy(), rtol=0,
+                               atol=1e-8 * float(db[1].abs().max()))
+
+    def broken(f, u):
+        raise ValueError("mobility failed")
+
+    with pytest.raises(ValueError, match="mobility failed"):
+        sc.solve_lcp_mob(P, con, sc.FnMobility(broken), tol=1e-10)
