@@ -445,6 +445,13 @@ class FnMobility:
         self._cb = A.MOBILITY_FN(cb)
         self._gcb = A.MOBILITY_GRAD_FN(gcb) if grad is not None else None
 
+    def apply(self, f: torch.Tensor) -> torch.Tensor:
+        """u = Mob f for f [n][6] (the Python function called directly)."""
+        f = _dev(f)
+        u = torch.empty_like(f)
+        self._apply(f, u)
+        return u
+
     def fn_ctx(self):
         return (ctypes.cast(self._cb, ctypes.c_void_p).value, None)
 

@@ -58,12 +58,15 @@ class TimeStepper:
     pair threshold ``delta``. ``warm_start``: gamma_0 of each step from the
     previous step's solution. ``hydro_radius``: the mobility is the RPY
     mobility of spheres of these hydrodynamic radii and viscosity ``mu``
-    (every product through ``solve_lcp_mob``) instead of the dry mobility."""
+    (every product through ``solve_lcp_mob``) instead of the dry mobility.
+    ``mobility``: any mobility object with ``apply(f)`` and ``fn_ctx()``
+    (RPY, DryMobility, FnMobility); it must follow the particles' centres,
+    which the steps update in place."""
 
     def __init__(self, particles: Particles, box: Box, delta: float, dt: float,
                  f_ext: torch.Tensor, tol: float = 1e-6, warm_start: bool = True,
                  max_iter: int = 100000, hydro_radius: Optional[torch.Tensor] = None,
-                 mu: float = 1.0):
+                 mu: float = 1.0, mobility=None):
         self.P = particles
         self.box = box
         self.delta = float(delta)
@@ -77,7 +80,10 @@ class TimeStepper:
         self.prev: Optional[Contacts] = None
         self.prev_gamma: Optional[torch.Tensor] = None
         # reads particles.pos at every product, which the steps update in place
-        self.rpy = None if hydro_radius is None else RPY(particles.pos, hydro_radius, mu)
+        if mobility is not None and hydro_radius is not None:
+            raise ValueError("give either hydro_radius or mobility")
+        self.rpy = mobility if mobility is not None else (
+            None if hydro_radius is None else RPY(particles.pos, hydro_radius, mu))
 
     def step(self) -> StepInfo:
         P = self.P
