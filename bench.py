@@ -204,7 +204,22 @@ def hydro(sc, W, torch, np, steps):
             "contacts": [x.contacts.count for x in infos],
             "active": [x.stats["n_active"] for x in infos],
             "mean_fall_speed": (z0 - z1) / (nsteps * s.dt),
-            "all_converged": all(x.stats["status"] == 0 for x in infos)}
+            "all_converged": all(x.stats["status"] == 0 for x in infos),
+            "solver": "per-phase"}
+        if n <= 2000:
+            # the same steps with the solve in one persistent launch
+            P2 = sc.Particles.from_suspension(s)
+            stp2 = ts.TimeStepper(P2, box, s.delta, s.dt, torch.from_numpy(s.f_ext).cuda(),
+                                  tol=s.tol, hydro_radius=torch.from_numpy(s.hydro_radius).cuda(),
+                                  persistent=True)
+            stp2.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(nsteps):
+                stp2.step()
+            torch.cuda.synchronize()
+            out[f"cluster{n}_steps"]["ms_per_step_persistent"] = \
+                1e3 * (time.perf_counter() - t0) / nsteps
     return out
 
 

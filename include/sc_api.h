@@ -126,6 +126,8 @@ typedef struct sc_contacts {
 #define SC_OP_MATRIX 2      /* assembled sparse M (requires c->mat_ready) */
 #define SC_OP_CALLBACK 3    /* reported by sc_solve_lcp_mob only: D x, the caller's
                                mobility, D^T U */
+#define SC_OP_RPY 4         /* reported by sc_solve_lcp_rpy only: one persistent launch
+                               with the RPY mobility inside */
 
 typedef struct sc_solve_opts {
     double tol;             /* absolute tolerance on ||min(gamma, g)||_2 (> 0) */
@@ -494,6 +496,30 @@ int sc_solve_lcp_mob(const sc_particles *p, const sc_contacts *c, const sc_solve
                      sc_mobility_fn mob, void *mob_ctx, int32_t check_every, double *gamma,
                      double *g, double *f_c, double *u_c, sc_stats *st, void *work,
                      size_t work_bytes, void *stream);
+
+/* Device bytes of the workspace of sc_solve_lcp_rpy. */
+size_t sc_solve_rpy_work_bytes(int32_t n, int32_t capacity);
+
+/* Algorithm 1 with the RPY mobility of `rpy` (same arithmetic definition as
+ * sc_solve_lcp_mob with sc_rpy_apply) in one persistent cooperative launch
+ * (one 1024-thread workgroup per CU, three grid barriers per iteration:
+ * after the projected step and F = D gamma, after the RPY pair sum, after
+ * g = D^T U + q and its partial sums). For systems small enough that the
+ * launches of the function-based solve dominate (measured faster for cold
+ * solves up to about 2000 spheres, slower beyond). Sums run in fixed orders:
+ * a given grid gives bitwise repeatable iterates, which differ from
+ * sc_solve_lcp_mob's by rounding only. Uses opts->tol, max_iter,
+ * bb, warm_start, grid (0 = one workgroup per CU) and spin_limit (as
+ * sc_solve_lcp: a grid barrier that times out ends the solve with
+ * SC_ERR_TIMEOUT). rpy->work holds the pair sums' split partials. gamma, g,
+ * f_c, u_c, st as sc_solve_lcp_mob (st->op = SC_OP_RPY; mvops counts only
+ * the products evaluated). work: device, 256-byte aligned, >=
+ * sc_solve_rpy_work_bytes(n, c->capacity). Returns SC_OK, SC_NOT_CONVERGED,
+ * SC_ERR_NONFINITE, SC_ERR_TIMEOUT, SC_ERR_INVALID, SC_ERR_WORKSPACE or
+ * SC_ERR_HIP. Synchronises `stream`. */
+int sc_solve_lcp_rpy(const sc_particles *p, const sc_contacts *c, const sc_rpy *rpy,
+                     const sc_solve_opts *opts, double *gamma, double *g, double *f_c,
+                     double *u_c, sc_stats *st, void *work, size_t work_bytes, void *stream);
 
 /* Device bytes of the workspace of sc_solve_lcp_adjoint_mob. */
 size_t sc_adjoint_mob_work_bytes(int32_t n, int32_t capacity);

@@ -23,6 +23,7 @@ SC_OP_AUTO = 0
 SC_OP_CHAIN = 1
 SC_OP_MATRIX = 2
 SC_OP_CALLBACK = 3
+SC_OP_RPY = 4
 
 c_dp = ctypes.c_void_p  # device pointers travel as plain addresses
 
@@ -162,6 +163,10 @@ SIGNATURES = {
                                                 c_dp, c_dp, c_dp, c_dp, P(sc_adjoint_opts),
                                                 ctypes.c_int32, c_dp, c_dp, P(sc_stats), c_dp,
                                                 ctypes.c_size_t, c_dp]),
+    "sc_solve_rpy_work_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "sc_solve_lcp_rpy": (ctypes.c_int, [P(sc_particles), P(sc_contacts), c_dp,
+                                        P(sc_solve_opts), c_dp, c_dp, c_dp, c_dp, P(sc_stats),
+                                        c_dp, ctypes.c_size_t, c_dp]),
     "sc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sc_version": (ctypes.c_int, []),
 }

@@ -511,6 +511,41 @@ def solve_lcp_mob(particles: Particles, contacts: Contacts, mobility, tol: float
     return gamma[:nc], g[:nc], st.as_dict(), f_c, u_c
 
 
+def solve_lcp_rpy(particles: Particles, contacts: Contacts, rpy: RPY, tol: float = 1e-6,
+                  max_iter: int = 100000, bb: int = 1, gamma0: Optional[torch.Tensor] = None,
+                  want_fc: bool = False, grid: int = 0, spin_limit: int = 0,
+                  raise_on_nonconverged: bool = False):
+    """Algorithm 1 with the RPY mobility ``rpy`` in one persistent launch
+    (sc_solve_lcp_rpy): the same arithmetic definition as solve_lcp_mob(...,
+    rpy), without a launch per phase; for small systems. Returns (gamma, g,
+    stats dict, f_c, u_c)."""
+    nc, n = contacts.count, particles.n
+    gamma = torch.zeros(max(1, nc), dtype=torch.float64, device="cuda")
+    if gamma0 is not None and nc:
+        gamma[:nc] = _dev(gamma0)
+    g = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
+    f_c = u_c = None
+    if want_fc:
+        f_c = torch.empty((n, 6), dtype=torch.float64, device="cuda")
+        u_c = torch.empty((n, 6), dtype=torch.float64, device="cuda")
+    opts = A.sc_solve_opts(float(tol), int(max_iter), int(bb), 1 if gamma0 is not None else 0,
+                           0, int(grid), 0, 0, 0, 0, int(spin_limit))
+    st = A.sc_stats()
+    wb = int(A.lib().sc_solve_rpy_work_bytes(n, contacts.capacity))
+    work = torch.empty(wb + 256, dtype=torch.uint8, device="cuda")
+    wp = (work.data_ptr() + 255) // 256 * 256
+    pc, cc = particles.c(), contacts.c()
+    rc = A.lib().sc_solve_lcp_rpy(ctypes.byref(pc), ctypes.byref(cc),
+                                  ctypes.c_void_p(ctypes.addressof(rpy._ctx)), ctypes.byref(opts),
+                                  _ptr(gamma), _ptr(g), _ptr(f_c), _ptr(u_c), ctypes.byref(st),
+                                  ctypes.c_void_p(wp), wb + 256 - (wp - work.data_ptr()),
+                                  _stream())
+    allow = (A.SC_OK,) if raise_on_nonconverged else (A.SC_OK, A.SC_NOT_CONVERGED,
+                                                      A.SC_ERR_NONFINITE, A.SC_ERR_TIMEOUT)
+    _check("sc_solve_lcp_rpy", rc, allow)
+    return gamma[:nc], g[:nc], st.as_dict(), f_c, u_c
+
+
 def solve_lcp_adjoint_mob(particles: Particles, box: Box, contacts: Contacts,
                           u_nc: torch.Tensor, dt: float, gamma: torch.Tensor, mobility,
                           f_ext: Optional[torch.Tensor] = None,

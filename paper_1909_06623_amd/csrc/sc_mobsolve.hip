@@ -37,6 +37,7 @@
 #include "sc_adjoint_dev.hpp"
 #include "sc_common.hpp"
 #include "sc_plan.hpp"
+#include "sc_sync.hpp"
 
 namespace sc {
 
@@ -749,6 +750,354 @@ int rpy_splits(int n) {
     return s < 1 ? 1 : s;
 }
 
+// ------------------------------------------------- persistent RPY solve
+//
+// Algorithm 1 with the RPY mobility in one cooperative launch (one 1024-thread
+// workgroup per CU), for systems small enough that launch gaps would
+// dominate the callback path. One iteration is three phases separated by grid
+// barriers: scatter (projected step, F = D gamma), pairs (the RPY sum in
+// units of 64 targets x one source split, the 16 waves of a workgroup taking
+// every 16th source of each LDS tile, partial sums per split), gather (U
+// from the self terms and the splits' partial sums, g = D^T U + q, partial
+// sums of the iteration), then a fixed-order grid reduction after which
+// every workgroup takes the same decision. All sums are in fixed orders, so
+// the iterates are reproducible for a given grid.
+
+constexpr int kPB = 1024;                 // threads per workgroup
+constexpr int kPW = kPB / kWave;          // waves per workgroup
+constexpr int kPTile = 512;               // sources per LDS tile
+
+struct RpyPersArgs {
+    MsView V;
+    const double *pos, *rad;
+    RpyConst K;
+    int splits;
+    double *F;            // [n][6] caller order
+    double *part;         // [splits][n][3]
+    double *gam[2], *gg[2];
+    double *red;          // [grid][kNV]
+    GridSync *sync;
+    MsCtrl *ctrl;
+    double tol;
+    int max_iter, bb;
+};
+
+// F = D w per particle over this workgroup's ranks; STEP as in k_ms_scatter.
+template <bool STEP>
+__device__ void p_scatter(const RpyPersArgs &A, const double *x, const double *gc,
+                          const double *ggc, double *gn, double alpha) {
+    const MsView &V = A.V;
+    int k0, k1;
+    chunk(V.n, k0, k1);
+    constexpr int PER = kPB / kMsLanes;
+    const int sub = threadIdx.x / kMsLanes, lane = threadIdx.x % kMsLanes;
+    for (int base = k0; base < k1; base += PER) {
+        const int k = base + sub;
+        double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (k < k1) {
+            const int e1 = V.inc_ptr[k + 1];
+            for (int e = V.inc_ptr[k] + lane; e < e1; e += kMsLanes) {
+                const int code = V.inc[e];
+                const int m = code >> 1;
+                double w;
+                if (STEP) {
+                    w = project(gc[m] - alpha * ggc[m]);
+                    if (code & 1) gn[m] = w;
+                } else {
+                    w = x[m];
+                }
+                const double *d = V.dpm + 6 * static_cast<long long>(e);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) a[c] += w * d[c];
+            }
+        }
+#pragma unroll
+        for (int off = kMsLanes / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) a[c] += __shfl_xor(a[c], off, kWave);
+        if (k < k1 && lane == 0) {
+            double *fk = A.F + 6 * static_cast<long long>(V.order[k]);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) fk[c] = a[c];
+        }
+    }
+}
+
+// The RPY pair sum: units (64-target block, source split), dealt to the
+// workgroups in logical order; part[s][i] = sum over split s of the pairs.
+__device__ void p_pairs(const RpyPersArgs &A) {
+    __shared__ double sx[kPTile], sy[kPTile], sz[kPTile], sa[kPTile];
+    __shared__ double sfx[kPTile], sfy[kPTile], sfz[kPTile];
+    __shared__ double red3[3][kPB];
+    const int n = A.V.n, S = A.splits;
+    const int bx = (n + kRpyTargets - 1) / kRpyTargets;
+    const int units = bx * S;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    for (int u = logical_block(); u < units; u += gridDim.x) {
+        const int tx = u % bx, s = u / bx;
+        const int i = tx * kRpyTargets + lane;
+        const int j0 = static_cast<int>(static_cast<long long>(s) * n / S);
+        const int j1 = static_cast<int>(static_cast<long long>(s + 1) * n / S);
+        const bool live = i < n;
+        const double xi = live ? A.pos[3 * i] : 0.0, yi = live ? A.pos[3 * i + 1] : 0.0,
+                     zi = live ? A.pos[3 * i + 2] : 0.0, ai = live ? A.rad[i] : 1.0;
+        double ux = 0.0, uy = 0.0, uz = 0.0;
+        // the next tile's source is loaded into registers while the current
+        // tile is summed
+        double nx = 0.0, ny = 0.0, nz = 0.0, na = 0.0, nfx = 0.0, nfy = 0.0, nfz = 0.0;
+        if (threadIdx.x < kPTile && j0 + static_cast<int>(threadIdx.x) < j1) {
+            const int j = j0 + threadIdx.x;
+            nx = A.pos[3 * j];
+            ny = A.pos[3 * j + 1];
+            nz = A.pos[3 * j + 2];
+            na = A.rad[j];
+            nfx = A.F[6 * static_cast<long long>(j)];
+            nfy = A.F[6 * static_cast<long long>(j) + 1];
+            nfz = A.F[6 * static_cast<long long>(j) + 2];
+        }
+        for (int t = j0; t < j1; t += kPTile) {
+            const int cnt = j1 - t < kPTile ? j1 - t : kPTile;
+            __syncthreads();
+            if (threadIdx.x < cnt) {
+                sx[threadIdx.x] = nx;
+                sy[threadIdx.x] = ny;
+                sz[threadIdx.x] = nz;
+                sa[threadIdx.x] = na;
+                sfx[threadIdx.x] = nfx;
+                sfy[threadIdx.x] = nfy;
+                sfz[threadIdx.x] = nfz;
+            }
+            __syncthreads();
+            const int tn = t + kPTile;
+            if (threadIdx.x < kPTile && tn + static_cast<int>(threadIdx.x) < j1) {
+                const int j = tn + threadIdx.x;
+                nx = A.pos[3 * j];
+                ny = A.pos[3 * j + 1];
+                nz = A.pos[3 * j + 2];
+                na = A.rad[j];
+                nfx = A.F[6 * static_cast<long long>(j)];
+                nfy = A.F[6 * static_cast<long long>(j) + 1];
+                nfz = A.F[6 * static_cast<long long>(j) + 2];
+            }
+            const int me = i - t;
+            for (int m = w; m < cnt; m += kPW)
+                rpy_pair(A.K, xi - sx[m], yi - sy[m], zi - sz[m], ai, sa[m], sfx[m], sfy[m],
+                         sfz[m], m == me, ux, uy, uz);
+        }
+        red3[0][threadIdx.x] = ux;
+        red3[1][threadIdx.x] = uy;
+        red3[2][threadIdx.x] = uz;
+        __syncthreads();
+        if (w == 0 && live) {
+            double *pp = A.part + 3 * (static_cast<long long>(s) * n + i);
+            for (int c = 0; c < 3; ++c) {
+                double acc = red3[c][lane];
+                for (int q = 1; q < kPW; ++q) acc += red3[c][q * kWave + lane];
+                pp[c] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// U of particle i: the self terms plus the splits' sums, in split order.
+// The split loads go out in groups of kPGroup before any is added, so a
+// contact waits about S / kPGroup memory latencies instead of 3 S.
+constexpr int kPGroup = 4;
+__device__ __forceinline__ void p_velocity(const RpyPersArgs &A, int i, double (&u)[6]) {
+    const double a = A.rad[i];
+    const double *fi = A.F + 6 * static_cast<long long>(i);
+    const double st = A.K.k6 / a, sr = 0.75 * A.K.k6 / (a * a * a);
+    const long long stride = 3LL * A.V.n;
+    const double *pp = A.part + 3LL * i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        u[c] = st * fi[c];
+        u[3 + c] = sr * fi[3 + c];
+    }
+    const int S = A.splits;
+    int s = 0;
+    for (; s + kPGroup <= S; s += kPGroup) {
+        double t[kPGroup][3];
+#pragma unroll
+        for (int k = 0; k < kPGroup; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) t[k][c] = pp[(s + k) * stride + c];
+#pragma unroll
+        for (int k = 0; k < kPGroup; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) u[c] += t[k][c];
+    }
+    for (; s < S; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) u[c] += pp[s * stride + c];
+}
+
+// D_l^T U for contact l with U formed from the partial sums.
+__device__ __forceinline__ double p_dt_u(const RpyPersArgs &A, int l) {
+    const MsView &V = A.V;
+    const double *fr = V.frame + 9 * static_cast<long long>(l);
+    double ui[6];
+    p_velocity(A, V.ci[l], ui);
+    const double vi = -(fr[0] * ui[0] + fr[1] * ui[1] + fr[2] * ui[2]) -
+                      (fr[3] * ui[3] + fr[4] * ui[4] + fr[5] * ui[5]);
+    const int j = V.cj[l];
+    if (j < 0) return vi;
+    double uj[6];
+    p_velocity(A, j, uj);
+    return vi + (fr[0] * uj[0] + fr[1] * uj[1] + fr[2] * uj[2]) +
+           (fr[6] * uj[3] + fr[7] * uj[4] + fr[8] * uj[5]);
+}
+
+// The gather over this workgroup's contacts; modes as k_ms_gather. Partials
+// go to A.red through write_partial (slot = logical workgroup).
+template <int MODE>
+__device__ void p_gather(const RpyPersArgs &A, const double *gam, const double *gc,
+                         const double *ggc, double *out) {
+    const MsView &V = A.V;
+    int l0, l1;
+    chunk(V.nc, l0, l1);
+    double v[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int l = l0 + threadIdx.x; l < l1; l += kPB) {
+        const double du = p_dt_u(A, l);
+        if (MODE == kAlpha0) {
+            const double gl = ggc[l];
+            v[0] += gl * gl;
+            v[1] += gl * du;
+            v[4] = fmax(v[4], self_diag(V, l));
+        } else {
+            const double gn = du + V.q[l];
+            out[l] = gn;
+            const double gm = gam[l];
+            const double m = gm < gn ? gm : gn;
+            v[0] += m * m;
+            v[4] += gm > 0.0 ? 1.0 : 0.0;
+            if (MODE == kIter) {
+                const double sd = gm - gc[l], y = gn - ggc[l];
+                v[1] += sd * sd;
+                v[2] += sd * y;
+                v[3] += y * y;
+            }
+        }
+    }
+    write_partial<kNV, kPB, MODE == kAlpha0 ? 4 : -1>(A.red, v);
+}
+
+__global__ void __launch_bounds__(kPB) k_bbpgd_rpy(RpyPersArgs A) {
+    GridBarrier bar;
+    bar.init(A.sync);
+    double tot[kNV];
+    double alpha = 0.0, res = 0.0;
+    int status = SC_NOT_CONVERGED, iters = 0, mvops = 0, ndegen = 0, n_active = 0, last = 0;
+    // g0 = M gamma0 + q
+    p_scatter<false>(A, A.gam[0], nullptr, nullptr, nullptr, 0.0);
+    bool ok = bar.sync();
+    p_pairs(A);
+    ok = ok && bar.sync();
+    p_gather<kG0>(A, A.gam[0], nullptr, nullptr, A.gg[0]);
+    ok = ok && bar.sync();
+    grid_reduce<kNV, kPB>(A.red, tot);
+    mvops = 1;
+    res = sqrt(tot[0]);
+    n_active = static_cast<int>(tot[4]);
+    if (!ok) {
+        status = SC_ERR_TIMEOUT;
+    } else if (!isfinite(res)) {
+        status = SC_ERR_NONFINITE;
+    } else if (res < A.tol) {
+        status = SC_OK;
+    } else {
+        // alpha0 = g0^T g0 / g0^T M g0 (fallback: 1 / max self diagonal)
+        p_scatter<false>(A, A.gg[0], nullptr, nullptr, nullptr, 0.0);
+        ok = bar.sync();
+        p_pairs(A);
+        ok = ok && bar.sync();
+        p_gather<kAlpha0>(A, nullptr, nullptr, A.gg[0], nullptr);
+        ok = ok && bar.sync();
+        grid_reduce<kNV, kPB, 4>(A.red, tot);
+        mvops = 2;
+        if (tot[1] > 0.0 && isfinite(tot[1]) && isfinite(tot[0])) {
+            alpha = tot[0] / tot[1];
+        } else {
+            alpha = tot[4] > 0.0 ? 1.0 / tot[4] : 1.0;
+            ++ndegen;
+        }
+        if (!ok) status = SC_ERR_TIMEOUT;
+        for (int j = 1; ok && j <= A.max_iter; ++j) {
+            const int cur = (j - 1) & 1, nxt = j & 1;
+            p_scatter<true>(A, nullptr, A.gam[cur], A.gg[cur], A.gam[nxt], alpha);
+            ok = bar.sync();
+            p_pairs(A);
+            ok = ok && bar.sync();
+            p_gather<kIter>(A, A.gam[nxt], A.gam[cur], A.gg[cur], A.gg[nxt]);
+            ok = ok && bar.sync();
+            grid_reduce<kNV, kPB>(A.red, tot);
+            iters = j;
+            last = nxt;
+            ++mvops;
+            res = sqrt(tot[0]);
+            n_active = static_cast<int>(tot[4]);
+            if (!ok) {
+                status = SC_ERR_TIMEOUT;
+                break;
+            }
+            if (!isfinite(res)) {
+                status = SC_ERR_NONFINITE;
+                break;
+            }
+            if (res < A.tol) {
+                status = SC_OK;
+                break;
+            }
+            const bool bb2 = A.bb == 2 || (A.bb == 3 && (j % 2 == 0));
+            const double num = bb2 ? tot[2] : tot[1];
+            const double den = bb2 ? tot[3] : tot[2];
+            if (den > 0.0 && num > 0.0 && isfinite(num) && isfinite(den))
+                alpha = num / den;
+            else
+                ++ndegen;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        MsCtrl C;
+        C.alpha = alpha;
+        C.res = res;
+        C.iters = iters;
+        C.mvops = mvops;
+        C.status = status;
+        C.ndegen = ndegen;
+        C.done = 1;
+        C.n_active = n_active;
+        C.final_buf = last;
+        C.pad = 0;
+        *A.ctrl = C;
+    }
+}
+
+// Source splits of the persistent pair phase: about one (target block,
+// split) unit per workgroup, so that each workgroup loads and reduces once
+// per product and U sums few partials (measured faster than two or four
+// units per workgroup up to 2000 spheres); never more than rpy_splits(n),
+// whose partial sums the sc_rpy workspace holds.
+int rpy_pers_splits(int n, int grid) {
+    const int bx = (n + kRpyTargets - 1) / kRpyTargets;
+    int s = (grid + bx - 1) / bx;
+    const int smax = rpy_splits(n);
+    if (s > smax) s = smax;
+    return s < 1 ? 1 : s;
+}
+
+size_t rpy_pers_ws_bytes(int32_t n, int32_t cap) {
+    const size_t nn = static_cast<size_t>(n), cc = static_cast<size_t>(cap);
+    size_t b = 0;
+    b += 2 * align_up(cc * sizeof(double), 256);       // second gamma / g buffers
+    b += align_up(6 * nn * sizeof(double), 256);       // F
+    b += align_up(kNV * kMaxReduceBlocks * sizeof(double), 256);
+    b += align_up(sizeof(GridSync), 256);
+    b += align_up(sizeof(MsCtrl), 256);
+    return b + 1024;
+}
+
 // ------------------------------------------------------------------ host
 
 // Host copies of a control block, one per chunk parity, in pinned memory
@@ -1146,5 +1495,120 @@ extern "C" int sc_solve_lcp_adjoint_mob(const sc_particles *p, const sc_box *box
     st->block = kBlock;
     st->lanes_per_particle = kMsLanes;
     st->op = SC_OP_CALLBACK;
+    return hc.status;
+}
+
+extern "C" size_t sc_solve_rpy_work_bytes(int32_t n, int32_t capacity) {
+    if (n < 0 || capacity < 0) return 0;
+    return rpy_pers_ws_bytes(n, capacity);
+}
+
+extern "C" int sc_solve_lcp_rpy(const sc_particles *p, const sc_contacts *c, const sc_rpy *R,
+                                const sc_solve_opts *opts, double *gamma, double *g,
+                                double *f_c, double *u_c, sc_stats *st, void *ws,
+                                size_t ws_bytes, void *stream_) {
+    if (!p || !c || !R || !opts || !st || p->n < 0 || c->count < 0 || c->count > c->capacity)
+        return SC_ERR_INVALID;
+    if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->bb < 1 || opts->bb > 3 ||
+        opts->grid < 0 || opts->spin_limit < 0)
+        return SC_ERR_INVALID;
+    if (R->n != p->n || !(R->mu > 0.0) || !std::isfinite(R->mu)) return SC_ERR_INVALID;
+    Plan pl;
+    if (!carve_plan(c->plan, c->plan_bytes, p->n, c->capacity, pl)) return SC_ERR_INVALID;
+    const int n = p->n, nc = c->count;
+    if (nc > 0 && (!c->ci || !c->cj || !c->frame || !c->q || !gamma || !g)) return SC_ERR_INVALID;
+    if (n > 0 && (!R->pos || !R->radius)) return SC_ERR_INVALID;
+    if (n > 0 && (!R->work || (reinterpret_cast<uintptr_t>(R->work) & 255) != 0 ||
+                  R->work_bytes < sc_rpy_work_bytes(n)))
+        return SC_ERR_WORKSPACE;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 ||
+        ws_bytes < rpy_pers_ws_bytes(n, c->capacity))
+        return SC_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream_);
+    *st = sc_stats{};
+    Carver cv{static_cast<char *>(ws), ws_bytes};
+    double *gam1 = cv.take<double>(static_cast<size_t>(c->capacity));
+    double *g1 = cv.take<double>(static_cast<size_t>(c->capacity));
+    double *F = cv.take<double>(6 * static_cast<size_t>(n));
+    double *red = cv.take<double>(kNV * static_cast<size_t>(kMaxReduceBlocks));
+    GridSync *sync = cv.take<GridSync>(1);
+    MsCtrl *ctrl = cv.take<MsCtrl>(1);
+    if (!cv.ok) return SC_ERR_WORKSPACE;
+    if (nc == 0) {
+        if (f_c) SC_HIP_TRY(hipMemsetAsync(f_c, 0, 6 * sizeof(double) * n, s));
+        if (u_c) SC_HIP_TRY(hipMemsetAsync(u_c, 0, 6 * sizeof(double) * n, s));
+        SC_HIP_TRY(hipStreamSynchronize(s));
+        st->status = SC_OK;
+        st->mvops = 1;
+        return SC_OK;
+    }
+    Events ev;
+    if (!ev.ok) return SC_ERR_HIP;
+    const int G = persistent_grid(reinterpret_cast<const void *>(k_bbpgd_rpy), kPB, opts->grid);
+    if (G < 1) return SC_ERR_HIP;
+    RpyPersArgs A;
+    A.V = MsView{n, nc, pl.order, pl.inc_ptr, pl.inc, pl.dpm, c->ci, c->cj, pl.cs, pl.pdat,
+                 c->frame, c->q};
+    A.pos = R->pos;
+    A.rad = R->radius;
+    A.K = RpyConst{1.0 / (8.0 * M_PI * R->mu), 1.0 / (6.0 * M_PI * R->mu)};
+    A.splits = rpy_pers_splits(n, G);
+    A.F = F;
+    A.part = static_cast<double *>(R->work);
+    A.gam[0] = gamma;
+    A.gam[1] = gam1;
+    A.gg[0] = g;
+    A.gg[1] = g1;
+    A.red = red;
+    A.sync = sync;
+    A.ctrl = ctrl;
+    A.tol = opts->tol;
+    A.max_iter = opts->max_iter;
+    A.bb = opts->bb;
+    if (!opts->warm_start) SC_HIP_TRY(hipMemsetAsync(gamma, 0, sizeof(double) * nc, s));
+    SC_HIP_TRY(hipMemsetAsync(sync, 0, sizeof(GridSync), s));
+    if (opts->spin_limit > 0)
+        SC_HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(&sync->limit[0]),
+                                     opts->spin_limit, 1, s));
+    SC_HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(MsCtrl), s));
+    void *args[] = {&A};
+    SC_HIP_TRY(hipEventRecord(ev.e[0], s));
+    SC_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_bbpgd_rpy), dim3(G),
+                                          dim3(kPB), args, 0, s));
+    SC_HIP_TRY(hipEventRecord(ev.e[1], s));
+    MsCtrl hc;
+    SC_HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(MsCtrl), hipMemcpyDeviceToHost, s));
+    SC_HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0.0f;
+    SC_HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+    if (hc.final_buf == 1) {
+        SC_HIP_TRY(hipMemcpyAsync(gamma, gam1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+        SC_HIP_TRY(hipMemcpyAsync(g, g1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+    }
+    if (f_c || u_c) {
+        double *fo = f_c ? f_c : F;
+        const int sb = grid_for(static_cast<long long>(n) * kMsLanes);
+        k_ms_scatter<false><<<sb, kBlock, 0, s>>>(A.V, gamma, nullptr, nullptr, nullptr, nullptr,
+                                                  fo);
+        SC_HIP_TRY(hipGetLastError());
+        if (u_c) {
+            const int rc = sc_rpy_apply(const_cast<sc_rpy *>(R), n, fo, u_c, s);
+            if (rc) return rc;
+        }
+    }
+    SC_HIP_TRY(hipStreamSynchronize(s));
+    SC_HIP_TRY(hipGetLastError());
+    st->status = hc.status;
+    st->iters = hc.iters;
+    st->mvops = hc.mvops;
+    st->n_active = hc.n_active;
+    st->residual = hc.res;
+    st->alpha = hc.alpha;
+    st->n_degenerate = hc.ndegen;
+    st->kernel_ms = ms;
+    st->grid = G;
+    st->block = kPB;
+    st->lanes_per_particle = kMsLanes;
+    st->op = SC_OP_RPY;
     return hc.status;
 }

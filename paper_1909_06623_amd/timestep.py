@@ -14,7 +14,7 @@ import torch
 
 from . import _abi as A
 from .api import (RPY, Box, Contacts, Particles, Workspace, _check, _dev, _ptr, _stream,
-                  apply_mobility, build_contacts, solve_lcp, solve_lcp_mob)
+                  apply_mobility, build_contacts, solve_lcp, solve_lcp_mob, solve_lcp_rpy)
 
 
 def quat_from_axis(axis: torch.Tensor) -> torch.Tensor:
@@ -61,12 +61,15 @@ class TimeStepper:
     (every product through ``solve_lcp_mob``) instead of the dry mobility.
     ``mobility``: any mobility object with ``apply(f)`` and ``fn_ctx()``
     (RPY, DryMobility, FnMobility); it must follow the particles' centres,
-    which the steps update in place."""
+    which the steps update in place. ``persistent``: with an RPY mobility,
+    solve in one persistent launch (solve_lcp_rpy) instead of a launch per
+    phase (faster for cold solves of up to about 2000 spheres; a warm-started
+    step of the 1000-sphere cluster takes the same time either way)."""
 
     def __init__(self, particles: Particles, box: Box, delta: float, dt: float,
                  f_ext: torch.Tensor, tol: float = 1e-6, warm_start: bool = True,
                  max_iter: int = 100000, hydro_radius: Optional[torch.Tensor] = None,
-                 mu: float = 1.0, mobility=None):
+                 mu: float = 1.0, mobility=None, persistent: bool = False):
         self.P = particles
         self.box = box
         self.delta = float(delta)
@@ -84,6 +87,7 @@ class TimeStepper:
             raise ValueError("give either hydro_radius or mobility")
         self.rpy = mobility if mobility is not None else (
             None if hydro_radius is None else RPY(particles.pos, hydro_radius, mu))
+        self.persistent = bool(persistent) and isinstance(self.rpy, RPY)
 
     def step(self) -> StepInfo:
         P = self.P
@@ -96,6 +100,10 @@ class TimeStepper:
         if self.rpy is None:
             gamma, g, st, f_c, u_c = solve_lcp(P, con, tol=self.tol, max_iter=self.max_iter,
                                                gamma0=gamma0, want_fc=True, workspace=self.ws)
+        elif self.persistent:
+            gamma, g, st, f_c, u_c = solve_lcp_rpy(P, con, self.rpy, tol=self.tol,
+                                                   max_iter=self.max_iter, gamma0=gamma0,
+                                                   want_fc=True)
         else:
             gamma, g, st, f_c, u_c = solve_lcp_mob(P, con, self.rpy, tol=self.tol,
                                                    max_iter=self.max_iter, gamma0=gamma0,

@@ -125,7 +125,8 @@ def test_rod_suspension_trajectory_matches_oracle(warm):
 def test_time_stepper_with_mobility_objects():
     """TimeStepper(mobility=...): the dry mobility through the callback path
     follows the default (persistent, assembled-M) stepper; RPY given as an
-    object steps exactly as RPY given by its radii."""
+    object steps exactly as RPY given by its radii; the persistent and the
+    per-phase RPY solves step to the same centres."""
     import paper_1909_06623_amd as sc
     from paper_1909_06623_amd import timestep as ts
     s = W.spheres(400, 0.3, W.SEED_BASE + 919)
@@ -145,7 +146,14 @@ def test_time_stepper_with_mobility_objects():
     c = ts.TimeStepper(Pc, box, s.delta, s.dt, fe, tol=s.tol, hydro_radius=Pc.radius.clone())
     d = ts.TimeStepper(Pd, box, s.delta, s.dt, fe, tol=s.tol,
                        mobility=sc.RPY(Pd.pos, Pd.radius.clone()))
+    Pe = sc.Particles.from_suspension(s)
+    e = ts.TimeStepper(Pe, box, s.delta, s.dt, fe, tol=s.tol, hydro_radius=Pe.radius.clone(),
+                       persistent=True)
+    assert e.persistent and not c.persistent and not d.persistent
     for _ in range(4):
         c.step()
         d.step()
+        e.step()
     assert torch.equal(Pc.pos, Pd.pos)
+    # the persistent RPY solve and the per-phase one step to the same centres
+    np.testing.assert_allclose(Pe.pos.cpu().numpy(), Pc.pos.cpu().numpy(), rtol=0, atol=1e-9)
