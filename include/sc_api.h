@@ -502,9 +502,10 @@ size_t sc_solve_rpy_work_bytes(int32_t n, int32_t capacity);
 
 /* Algorithm 1 with the RPY mobility of `rpy` (same arithmetic definition as
  * sc_solve_lcp_mob with sc_rpy_apply) in one persistent cooperative launch
- * (one 1024-thread workgroup per CU, three grid barriers per iteration:
- * after the projected step and F = D gamma, after the RPY pair sum, after
- * g = D^T U + q and its partial sums). For systems small enough that the
+ * (one 1024-thread workgroup per CU, two grid barriers per iteration:
+ * after the RPY pair sum, whose work units form F = D gamma of their
+ * sources from the previous iterate, and after g = D^T U + q and its
+ * partial sums). For systems small enough that the
  * launches of the function-based solve dominate (measured faster for cold
  * solves up to about 2000 spheres, slower beyond). Sums run in fixed orders:
  * a given grid gives bitwise repeatable iterates, which differ from

@@ -754,14 +754,17 @@ int rpy_splits(int n) {
 //
 // Algorithm 1 with the RPY mobility in one cooperative launch (one 1024-thread
 // workgroup per CU), for systems small enough that launch gaps would
-// dominate the callback path. One iteration is three phases separated by grid
-// barriers: scatter (projected step, F = D gamma), pairs (the RPY sum in
-// units of 64 targets x one source split, the 16 waves of a workgroup taking
-// every 16th source of each LDS tile, partial sums per split), gather (U
-// from the self terms and the splits' partial sums, g = D^T U + q, partial
-// sums of the iteration), then a fixed-order grid reduction after which
-// every workgroup takes the same decision. All sums are in fixed orders, so
-// the iterates are reproducible for a given grid.
+// dominate the callback path. One iteration is two phases separated by grid
+// barriers. Pairs: the RPY sum in units of 64 targets x one source split (the
+// 16 waves of a workgroup take every 16th source of each LDS tile; partial
+// sums per split); each unit forms F = D gamma_j of its sources itself, with
+// gamma_j = max(0, gamma_{j-1} - alpha g_{j-1}) taken per incidence from the
+// previous iterate, and the units of the first target block store F for the
+// self terms. Gather: gamma_j per contact (stored), U from the self terms and
+// the splits' partial sums, g = D^T U + q and the iteration's partial sums.
+// A fixed-order grid reduction follows, after which every workgroup takes
+// the same decision. All sums are in fixed orders, so the iterates are
+// reproducible for a given grid.
 
 constexpr int kPB = 1024;                 // threads per workgroup
 constexpr int kPW = kPB / kWave;          // waves per workgroup
@@ -782,52 +785,52 @@ struct RpyPersArgs {
     int max_iter, bb;
 };
 
-// F = D w per particle over this workgroup's ranks; STEP as in k_ms_scatter.
-template <bool STEP>
-__device__ void p_scatter(const RpyPersArgs &A, const double *x, const double *gc,
-                          const double *ggc, double *gn, double alpha) {
+// What the pair phase multiplies by D: x itself, or (step) the projected
+// step max(0, gc - alpha ggc). A runtime flag, so that the pair phase and
+// its LDS tiles exist once in the kernel.
+struct PWeights {
+    const double *x, *gc, *ggc;
+    double alpha;
+    bool step;
+};
+
+// Source of rank k for the pair sum: centre, radius and the force part of
+// F_k = sum over its incidences of w_m D-column entries (in incidence
+// order); the whole F_k (force and torque) is stored when `store`.
+__device__ __forceinline__ void p_source(const RpyPersArgs &A, const PWeights &Wt, int k,
+                                         bool store, double (&v)[7]) {
     const MsView &V = A.V;
-    int k0, k1;
-    chunk(V.n, k0, k1);
-    constexpr int PER = kPB / kMsLanes;
-    const int sub = threadIdx.x / kMsLanes, lane = threadIdx.x % kMsLanes;
-    for (int base = k0; base < k1; base += PER) {
-        const int k = base + sub;
-        double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (k < k1) {
-            const int e1 = V.inc_ptr[k + 1];
-            for (int e = V.inc_ptr[k] + lane; e < e1; e += kMsLanes) {
-                const int code = V.inc[e];
-                const int m = code >> 1;
-                double w;
-                if (STEP) {
-                    w = project(gc[m] - alpha * ggc[m]);
-                    if (code & 1) gn[m] = w;
-                } else {
-                    w = x[m];
-                }
-                const double *d = V.dpm + 6 * static_cast<long long>(e);
+    const int j = V.order[k];
+    v[0] = A.pos[3 * j];
+    v[1] = A.pos[3 * j + 1];
+    v[2] = A.pos[3 * j + 2];
+    v[3] = A.rad[j];
+    double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int e1 = V.inc_ptr[k + 1];
+    for (int e = V.inc_ptr[k]; e < e1; ++e) {
+        const int m = V.inc[e] >> 1;
+        const double w = Wt.step ? project(Wt.gc[m] - Wt.alpha * Wt.ggc[m]) : Wt.x[m];
+        const double *d = V.dpm + 6 * static_cast<long long>(e);
 #pragma unroll
-                for (int c = 0; c < 6; ++c) a[c] += w * d[c];
-            }
-        }
+        for (int c = 0; c < 6; ++c) a[c] += w * d[c];
+    }
+    v[4] = a[0];
+    v[5] = a[1];
+    v[6] = a[2];
+    if (store) {
+        double *fj = A.F + 6 * static_cast<long long>(j);
 #pragma unroll
-        for (int off = kMsLanes / 2; off > 0; off >>= 1)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) a[c] += __shfl_xor(a[c], off, kWave);
-        if (k < k1 && lane == 0) {
-            double *fk = A.F + 6 * static_cast<long long>(V.order[k]);
-#pragma unroll
-            for (int c = 0; c < 6; ++c) fk[c] = a[c];
-        }
+        for (int c = 0; c < 6; ++c) fj[c] = a[c];
     }
 }
 
 // The RPY pair sum: units (64-target block, source split), dealt to the
 // workgroups in logical order; part[s][i] = sum over split s of the pairs.
-__device__ void p_pairs(const RpyPersArgs &A) {
+// Splits are ranges of ranks (sources in the contact plan's order).
+__device__ void p_pairs(const RpyPersArgs &A, const PWeights &Wt) {
     __shared__ double sx[kPTile], sy[kPTile], sz[kPTile], sa[kPTile];
     __shared__ double sfx[kPTile], sfy[kPTile], sfz[kPTile];
+    __shared__ int sj[kPTile];
     __shared__ double red3[3][kPB];
     const int n = A.V.n, S = A.splits;
     const int bx = (n + kRpyTargets - 1) / kRpyTargets;
@@ -835,54 +838,44 @@ __device__ void p_pairs(const RpyPersArgs &A) {
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     for (int u = logical_block(); u < units; u += gridDim.x) {
         const int tx = u % bx, s = u / bx;
+        const bool store = tx == 0;
         const int i = tx * kRpyTargets + lane;
-        const int j0 = static_cast<int>(static_cast<long long>(s) * n / S);
-        const int j1 = static_cast<int>(static_cast<long long>(s + 1) * n / S);
+        const int k0 = static_cast<int>(static_cast<long long>(s) * n / S);
+        const int k1 = static_cast<int>(static_cast<long long>(s + 1) * n / S);
         const bool live = i < n;
         const double xi = live ? A.pos[3 * i] : 0.0, yi = live ? A.pos[3 * i + 1] : 0.0,
                      zi = live ? A.pos[3 * i + 2] : 0.0, ai = live ? A.rad[i] : 1.0;
         double ux = 0.0, uy = 0.0, uz = 0.0;
-        // the next tile's source is loaded into registers while the current
+        // the next tile's sources are formed in registers while the current
         // tile is summed
-        double nx = 0.0, ny = 0.0, nz = 0.0, na = 0.0, nfx = 0.0, nfy = 0.0, nfz = 0.0;
-        if (threadIdx.x < kPTile && j0 + static_cast<int>(threadIdx.x) < j1) {
-            const int j = j0 + threadIdx.x;
-            nx = A.pos[3 * j];
-            ny = A.pos[3 * j + 1];
-            nz = A.pos[3 * j + 2];
-            na = A.rad[j];
-            nfx = A.F[6 * static_cast<long long>(j)];
-            nfy = A.F[6 * static_cast<long long>(j) + 1];
-            nfz = A.F[6 * static_cast<long long>(j) + 2];
+        double nv[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int nj = -1;
+        if (threadIdx.x < kPTile && k0 + static_cast<int>(threadIdx.x) < k1) {
+            p_source(A, Wt, k0 + threadIdx.x, store, nv);
+            nj = A.V.order[k0 + threadIdx.x];
         }
-        for (int t = j0; t < j1; t += kPTile) {
-            const int cnt = j1 - t < kPTile ? j1 - t : kPTile;
+        for (int t = k0; t < k1; t += kPTile) {
+            const int cnt = k1 - t < kPTile ? k1 - t : kPTile;
             __syncthreads();
             if (threadIdx.x < cnt) {
-                sx[threadIdx.x] = nx;
-                sy[threadIdx.x] = ny;
-                sz[threadIdx.x] = nz;
-                sa[threadIdx.x] = na;
-                sfx[threadIdx.x] = nfx;
-                sfy[threadIdx.x] = nfy;
-                sfz[threadIdx.x] = nfz;
+                sx[threadIdx.x] = nv[0];
+                sy[threadIdx.x] = nv[1];
+                sz[threadIdx.x] = nv[2];
+                sa[threadIdx.x] = nv[3];
+                sfx[threadIdx.x] = nv[4];
+                sfy[threadIdx.x] = nv[5];
+                sfz[threadIdx.x] = nv[6];
+                sj[threadIdx.x] = nj;
             }
             __syncthreads();
             const int tn = t + kPTile;
-            if (threadIdx.x < kPTile && tn + static_cast<int>(threadIdx.x) < j1) {
-                const int j = tn + threadIdx.x;
-                nx = A.pos[3 * j];
-                ny = A.pos[3 * j + 1];
-                nz = A.pos[3 * j + 2];
-                na = A.rad[j];
-                nfx = A.F[6 * static_cast<long long>(j)];
-                nfy = A.F[6 * static_cast<long long>(j) + 1];
-                nfz = A.F[6 * static_cast<long long>(j) + 2];
+            if (threadIdx.x < kPTile && tn + static_cast<int>(threadIdx.x) < k1) {
+                p_source(A, Wt, tn + threadIdx.x, store, nv);
+                nj = A.V.order[tn + threadIdx.x];
             }
-            const int me = i - t;
             for (int m = w; m < cnt; m += kPW)
                 rpy_pair(A.K, xi - sx[m], yi - sy[m], zi - sz[m], ai, sa[m], sfx[m], sfy[m],
-                         sfz[m], m == me, ux, uy, uz);
+                         sfz[m], sj[m] == i, ux, uy, uz);
         }
         red3[0][threadIdx.x] = ux;
         red3[1][threadIdx.x] = uy;
@@ -949,11 +942,12 @@ __device__ __forceinline__ double p_dt_u(const RpyPersArgs &A, int l) {
            (fr[6] * uj[3] + fr[7] * uj[4] + fr[8] * uj[5]);
 }
 
-// The gather over this workgroup's contacts; modes as k_ms_gather. Partials
-// go to A.red through write_partial (slot = logical workgroup).
+// The gather over this workgroup's contacts; modes as k_ms_gather. kIter
+// forms gamma_j = max(0, gc - alpha ggc) per contact and stores it in gn.
+// Partials go to A.red through write_partial (slot = logical workgroup).
 template <int MODE>
 __device__ void p_gather(const RpyPersArgs &A, const double *gam, const double *gc,
-                         const double *ggc, double *out) {
+                         const double *ggc, double alpha, double *gn, double *out) {
     const MsView &V = A.V;
     int l0, l1;
     chunk(V.nc, l0, l1);
@@ -966,14 +960,20 @@ __device__ void p_gather(const RpyPersArgs &A, const double *gam, const double *
             v[1] += gl * du;
             v[4] = fmax(v[4], self_diag(V, l));
         } else {
-            const double gn = du + V.q[l];
-            out[l] = gn;
-            const double gm = gam[l];
-            const double m = gm < gn ? gm : gn;
+            double gm;
+            if (MODE == kIter) {
+                gm = project(gc[l] - alpha * ggc[l]);
+                gn[l] = gm;
+            } else {
+                gm = gam[l];
+            }
+            const double gnew = du + V.q[l];
+            out[l] = gnew;
+            const double m = gm < gnew ? gm : gnew;
             v[0] += m * m;
             v[4] += gm > 0.0 ? 1.0 : 0.0;
             if (MODE == kIter) {
-                const double sd = gm - gc[l], y = gn - ggc[l];
+                const double sd = gm - gc[l], y = gnew - ggc[l];
                 v[1] += sd * sd;
                 v[2] += sd * y;
                 v[3] += y * y;
@@ -990,11 +990,9 @@ __global__ void __launch_bounds__(kPB) k_bbpgd_rpy(RpyPersArgs A) {
     double alpha = 0.0, res = 0.0;
     int status = SC_NOT_CONVERGED, iters = 0, mvops = 0, ndegen = 0, n_active = 0, last = 0;
     // g0 = M gamma0 + q
-    p_scatter<false>(A, A.gam[0], nullptr, nullptr, nullptr, 0.0);
+    p_pairs(A, PWeights{A.gam[0], nullptr, nullptr, 0.0, false});
     bool ok = bar.sync();
-    p_pairs(A);
-    ok = ok && bar.sync();
-    p_gather<kG0>(A, A.gam[0], nullptr, nullptr, A.gg[0]);
+    p_gather<kG0>(A, A.gam[0], nullptr, nullptr, 0.0, nullptr, A.gg[0]);
     ok = ok && bar.sync();
     grid_reduce<kNV, kPB>(A.red, tot);
     mvops = 1;
@@ -1008,11 +1006,9 @@ __global__ void __launch_bounds__(kPB) k_bbpgd_rpy(RpyPersArgs A) {
         status = SC_OK;
     } else {
         // alpha0 = g0^T g0 / g0^T M g0 (fallback: 1 / max self diagonal)
-        p_scatter<false>(A, A.gg[0], nullptr, nullptr, nullptr, 0.0);
+        p_pairs(A, PWeights{A.gg[0], nullptr, nullptr, 0.0, false});
         ok = bar.sync();
-        p_pairs(A);
-        ok = ok && bar.sync();
-        p_gather<kAlpha0>(A, nullptr, nullptr, A.gg[0], nullptr);
+        p_gather<kAlpha0>(A, nullptr, nullptr, A.gg[0], 0.0, nullptr, nullptr);
         ok = ok && bar.sync();
         grid_reduce<kNV, kPB, 4>(A.red, tot);
         mvops = 2;
@@ -1025,11 +1021,12 @@ __global__ void __launch_bounds__(kPB) k_bbpgd_rpy(RpyPersArgs A) {
         if (!ok) status = SC_ERR_TIMEOUT;
         for (int j = 1; ok && j <= A.max_iter; ++j) {
             const int cur = (j - 1) & 1, nxt = j & 1;
-            p_scatter<true>(A, nullptr, A.gam[cur], A.gg[cur], A.gam[nxt], alpha);
+            // both phases read gamma_{j-1}, g_{j-1} (buffers cur); the gather
+            // stores gamma_j, g_j (buffers nxt), which nothing reads before
+            // the barrier that ends this iteration
+            p_pairs(A, PWeights{nullptr, A.gam[cur], A.gg[cur], alpha, true});
             ok = bar.sync();
-            p_pairs(A);
-            ok = ok && bar.sync();
-            p_gather<kIter>(A, A.gam[nxt], A.gam[cur], A.gg[cur], A.gg[nxt]);
+            p_gather<kIter>(A, nullptr, A.gam[cur], A.gg[cur], alpha, A.gam[nxt], A.gg[nxt]);
             ok = ok && bar.sync();
             grid_reduce<kNV, kPB>(A.red, tot);
             iters = j;
