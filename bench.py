@@ -205,20 +205,20 @@ def hydro(sc, W, torch, np, steps):
             "active": [x.stats["n_active"] for x in infos],
             "mean_fall_speed": (z0 - z1) / (nsteps * s.dt),
             "all_converged": all(x.stats["status"] == 0 for x in infos),
-            "solver": "per-phase"}
-        if n <= 2000:
-            # the same steps with the solve in one persistent launch
+            "solver": "persistent" if stp.persistent else "per-phase"}
+        if stp.persistent:
+            # the same steps with a launch per phase, for comparison
             P2 = sc.Particles.from_suspension(s)
             stp2 = ts.TimeStepper(P2, box, s.delta, s.dt, torch.from_numpy(s.f_ext).cuda(),
                                   tol=s.tol, hydro_radius=torch.from_numpy(s.hydro_radius).cuda(),
-                                  persistent=True)
+                                  persistent=False)
             stp2.step()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(nsteps):
                 stp2.step()
             torch.cuda.synchronize()
-            out[f"cluster{n}_steps"]["ms_per_step_persistent"] = \
+            out[f"cluster{n}_steps"]["ms_per_step_per_phase"] = \
                 1e3 * (time.perf_counter() - t0) / nsteps
     return out
 

@@ -63,13 +63,15 @@ class TimeStepper:
     (RPY, DryMobility, FnMobility); it must follow the particles' centres,
     which the steps update in place. ``persistent``: with an RPY mobility,
     solve in one persistent launch (solve_lcp_rpy) instead of a launch per
-    phase (faster for cold solves of up to about 2000 spheres; a warm-started
-    step of the 1000-sphere cluster takes the same time either way)."""
+    phase; None chooses by size: persistent up to PERSISTENT_RPY_MAX_N
+    particles (measured faster there, slower beyond)."""
+
+    PERSISTENT_RPY_MAX_N = 2048
 
     def __init__(self, particles: Particles, box: Box, delta: float, dt: float,
                  f_ext: torch.Tensor, tol: float = 1e-6, warm_start: bool = True,
                  max_iter: int = 100000, hydro_radius: Optional[torch.Tensor] = None,
-                 mu: float = 1.0, mobility=None, persistent: bool = False):
+                 mu: float = 1.0, mobility=None, persistent: Optional[bool] = None):
         self.P = particles
         self.box = box
         self.delta = float(delta)
@@ -87,6 +89,8 @@ class TimeStepper:
             raise ValueError("give either hydro_radius or mobility")
         self.rpy = mobility if mobility is not None else (
             None if hydro_radius is None else RPY(particles.pos, hydro_radius, mu))
+        if persistent is None:
+            persistent = particles.n <= self.PERSISTENT_RPY_MAX_N
         self.persistent = bool(persistent) and isinstance(self.rpy, RPY)
 
     def step(self) -> StepInfo:

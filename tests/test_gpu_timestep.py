@@ -148,8 +148,8 @@ def test_time_stepper_with_mobility_objects():
                        mobility=sc.RPY(Pd.pos, Pd.radius.clone()))
     Pe = sc.Particles.from_suspension(s)
     e = ts.TimeStepper(Pe, box, s.delta, s.dt, fe, tol=s.tol, hydro_radius=Pe.radius.clone(),
-                       persistent=True)
-    assert e.persistent and not c.persistent and not d.persistent
+                       persistent=False)
+    assert c.persistent and d.persistent and not e.persistent
     for _ in range(4):
         c.step()
         d.step()
