@@ -501,26 +501,28 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
     return y;
 }
 
-// acc += RPY(x_i - x_j; a_i, a_j) F_j (translational coupling); the self pair
-// (same index) adds nothing. Separated pairs take the first branch; the
-// overlap forms and the self pair share the rare second one.
-__device__ __forceinline__ void rpy_pair(const RpyConst &K, double dx, double dy, double dz,
-                                         double ai, double aj, double fx, double fy, double fz,
-                                         bool self, double &ux, double &uy, double &uz) {
+// acc += RPY(x_i - x_j; a_i, a_j) F_j / (8 pi mu) (translational coupling),
+// with (fx, fy, fz) = F_j / (8 pi mu): the callers scale each source's force
+// once when they load it, which takes a product out of every pair. The self
+// pair (same index) adds nothing. Separated pairs take the first branch; the
+// overlap forms and the self pair share the rare second one, whose
+// 1 / (6 pi mu) prefactors become 4/3 relative to 1 / (8 pi mu).
+__device__ __forceinline__ void rpy_pair(double dx, double dy, double dz, double ai, double aj,
+                                         double fx, double fy, double fz, bool self, double &ux,
+                                         double &uy, double &uz) {
     // The library is built without floating-point contraction (the contact
     // geometry rounds exactly as written); this sum, checked against the
     // oracle to a tolerance, lets the compiler fuse multiply-adds.
 #pragma clang fp contract(fast)
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double sa = ai + aj;
-    double A, B;   // U = A F + B (d.F) d, d unnormalised
+    double A, B;   // U = A F + B (d.F) d, d unnormalised, F scaled as above
     if (r2 > sa * sa) {
         const double ri = rsqrt_nr(r2);
         const double ri2 = ri * ri;
         const double s2 = (ai * ai + aj * aj) * ri2;
-        const double c = K.k8 * ri;
-        A = c * (1.0 + s2 * (1.0 / 3.0));
-        B = c * (1.0 - s2) * ri2;
+        A = ri * (1.0 + s2 * (1.0 / 3.0));
+        B = ri * (1.0 - s2) * ri2;
     } else {
         const double da = ai - aj;
         if (self) {
@@ -528,7 +530,7 @@ __device__ __forceinline__ void rpy_pair(const RpyConst &K, double dx, double dy
             B = 0.0;
         } else if (r2 > da * da) {
             const double r = sqrt(r2);
-            const double pre = K.k6 / (ai * aj);
+            const double pre = (4.0 / 3.0) / (ai * aj);
             const double dd = da * da;
             const double t = dd + 3.0 * r2;
             const double r3 = r2 * r;
@@ -536,15 +538,19 @@ __device__ __forceinline__ void rpy_pair(const RpyConst &K, double dx, double dy
             const double w = dd - r2;
             B = pre * 3.0 * w * w / (32.0 * r3) / r2;
         } else {
-            A = K.k6 / (ai > aj ? ai : aj);
+            A = (4.0 / 3.0) / (ai > aj ? ai : aj);
             B = 0.0;
         }
     }
     const double dF = dx * fx + dy * fy + dz * fz;
     const double bd = B * dF;
-    ux += A * fx + bd * dx;
-    uy += A * fy + bd * dy;
-    uz += A * fz + bd * dz;
+    // two fused multiply-adds per component into the running sum
+    ux += A * fx;
+    ux += bd * dx;
+    uy += A * fy;
+    uy += bd * dy;
+    uz += A * fz;
+    uz += bd * dz;
 }
 
 // Workgroup: 64 targets (one per lane) and 4 waves; the waves take every
@@ -574,15 +580,15 @@ k_rpy_pairs(int n, const double *__restrict__ pos, const double *__restrict__ ra
             sy[threadIdx.x] = pos[3 * j + 1];
             sz[threadIdx.x] = pos[3 * j + 2];
             sa[threadIdx.x] = rad[j];
-            sfx[threadIdx.x] = f[6 * static_cast<long long>(j)];
-            sfy[threadIdx.x] = f[6 * static_cast<long long>(j) + 1];
-            sfz[threadIdx.x] = f[6 * static_cast<long long>(j) + 2];
+            sfx[threadIdx.x] = K.k8 * f[6 * static_cast<long long>(j)];
+            sfy[threadIdx.x] = K.k8 * f[6 * static_cast<long long>(j) + 1];
+            sfz[threadIdx.x] = K.k8 * f[6 * static_cast<long long>(j) + 2];
         }
         __syncthreads();
         const int me = i - t;   // this target's own index within the tile, if there
 #pragma unroll 2
         for (int m = w; m < cnt; m += NW)
-            rpy_pair(K, xi - sx[m], yi - sy[m], zi - sz[m], ai, sa[m], sfx[m], sfy[m], sfz[m],
+            rpy_pair(xi - sx[m], yi - sy[m], zi - sz[m], ai, sa[m], sfx[m], sfy[m], sfz[m],
                      m == me, ux, uy, uz);
     }
     red[0][threadIdx.x] = ux;
@@ -862,9 +868,9 @@ __device__ void p_pairs(const RpyPersArgs &A, const PWeights &Wt) {
                 sy[threadIdx.x] = nv[1];
                 sz[threadIdx.x] = nv[2];
                 sa[threadIdx.x] = nv[3];
-                sfx[threadIdx.x] = nv[4];
-                sfy[threadIdx.x] = nv[5];
-                sfz[threadIdx.x] = nv[6];
+                sfx[threadIdx.x] = A.K.k8 * nv[4];
+                sfy[threadIdx.x] = A.K.k8 * nv[5];
+                sfz[threadIdx.x] = A.K.k8 * nv[6];
                 sj[threadIdx.x] = nj;
             }
             __syncthreads();
@@ -874,7 +880,7 @@ __device__ void p_pairs(const RpyPersArgs &A, const PWeights &Wt) {
                 nj = A.V.order[tn + threadIdx.x];
             }
             for (int m = w; m < cnt; m += kPW)
-                rpy_pair(A.K, xi - sx[m], yi - sy[m], zi - sz[m], ai, sa[m], sfx[m], sfy[m],
+                rpy_pair(xi - sx[m], yi - sy[m], zi - sz[m], ai, sa[m], sfx[m], sfy[m],
                          sfz[m], sj[m] == i, ux, uy, uz);
         }
         red3[0][threadIdx.x] = ux;
