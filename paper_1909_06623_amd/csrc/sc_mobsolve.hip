@@ -490,15 +490,16 @@ struct RpyConst {
     double k6;      // 1 / (6 pi mu)
 };
 
-// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
-// (each roughly squares the relative error of the estimate).
-__device__ __forceinline__ double rsqrt_nr(double x) {
+// 1/sqrt(x) for x > 0: the hardware estimate y (relative error below 2^-24,
+// measured on 2^20 arguments from 1e-6 to 1e8) refined by one third-order
+// step of the binomial series of (1 - e)^(-1/2), e = 1 - x y^2:
+// y (1 + e/2 + 3 e^2 / 8), whose truncation error (about 5/16 e^3) is far
+// below rounding; five operations against seven for two Newton steps.
+__device__ __forceinline__ double rsqrt_refined(double x) {
 #pragma clang fp contract(fast)
-    double y = __builtin_amdgcn_rsq(x);
-    const double hx = 0.5 * x;
-    y = y * (1.5 - hx * y * y);
-    y = y * (1.5 - hx * y * y);
-    return y;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = 1.0 - (x * y) * y;
+    return y + (y * e) * (0.5 + 0.375 * e);
 }
 
 // acc += RPY(x_i - x_j; a_i, a_j) F_j / (8 pi mu) (translational coupling),
@@ -518,7 +519,7 @@ __device__ __forceinline__ void rpy_pair(double dx, double dy, double dz, double
     const double sa = ai + aj;
     double A, B;   // U = A F + B (d.F) d, d unnormalised, F scaled as above
     if (r2 > sa * sa) {
-        const double ri = rsqrt_nr(r2);
+        const double ri = rsqrt_refined(r2);
         const double ri2 = ri * ri;
         const double s2 = (ai * ai + aj * aj) * ri2;
         A = ri * (1.0 + s2 * (1.0 / 3.0));
@@ -555,12 +556,15 @@ __device__ __forceinline__ void rpy_pair(double dx, double dy, double dz, double
 
 // Workgroup: 64 targets (one per lane) and 4 waves; the waves take every
 // fourth source of each LDS tile, and their sums are added in wave order.
+// A source is three 16-byte pairs and one double in LDS, so a pair reads it
+// with four LDS loads instead of seven (the LDS pipe is shared by the four
+// SIMDs of the CU).
 __global__ void __launch_bounds__(kRpyBlock)
 k_rpy_pairs(int n, const double *__restrict__ pos, const double *__restrict__ rad,
             const double *__restrict__ f, RpyConst K, int splits, double *__restrict__ part) {
     constexpr int NW = kRpyBlock / kWave;
-    __shared__ double sx[kRpyBlock], sy[kRpyBlock], sz[kRpyBlock], sa[kRpyBlock];
-    __shared__ double sfx[kRpyBlock], sfy[kRpyBlock], sfz[kRpyBlock];
+    __shared__ double2 sxy[kRpyBlock], sza[kRpyBlock], sfxy[kRpyBlock];
+    __shared__ double sfz[kRpyBlock];
     __shared__ double red[3][kRpyBlock];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int i = blockIdx.x * kRpyTargets + lane;
@@ -576,20 +580,20 @@ k_rpy_pairs(int n, const double *__restrict__ pos, const double *__restrict__ ra
         __syncthreads();
         if (threadIdx.x < cnt) {
             const int j = t + threadIdx.x;
-            sx[threadIdx.x] = pos[3 * j];
-            sy[threadIdx.x] = pos[3 * j + 1];
-            sz[threadIdx.x] = pos[3 * j + 2];
-            sa[threadIdx.x] = rad[j];
-            sfx[threadIdx.x] = K.k8 * f[6 * static_cast<long long>(j)];
-            sfy[threadIdx.x] = K.k8 * f[6 * static_cast<long long>(j) + 1];
+            sxy[threadIdx.x] = make_double2(pos[3 * j], pos[3 * j + 1]);
+            sza[threadIdx.x] = make_double2(pos[3 * j + 2], rad[j]);
+            sfxy[threadIdx.x] = make_double2(K.k8 * f[6 * static_cast<long long>(j)],
+                                             K.k8 * f[6 * static_cast<long long>(j) + 1]);
             sfz[threadIdx.x] = K.k8 * f[6 * static_cast<long long>(j) + 2];
         }
         __syncthreads();
         const int me = i - t;   // this target's own index within the tile, if there
 #pragma unroll 2
-        for (int m = w; m < cnt; m += NW)
-            rpy_pair(xi - sx[m], yi - sy[m], zi - sz[m], ai, sa[m], sfx[m], sfy[m], sfz[m],
-                     m == me, ux, uy, uz);
+        for (int m = w; m < cnt; m += NW) {
+            const double2 p = sxy[m], q = sza[m], fq = sfxy[m];
+            rpy_pair(xi - p.x, yi - p.y, zi - q.x, ai, q.y, fq.x, fq.y, sfz[m], m == me, ux, uy,
+                     uz);
+        }
     }
     red[0][threadIdx.x] = ux;
     red[1][threadIdx.x] = uy;
@@ -644,7 +648,7 @@ __device__ __forceinline__ void rpy_grad_pair(const RpyConst &K, double dx, doub
     const double sa = ai + aj;
     double dA, Bt, dB, ri;
     if (r2 > sa * sa) {
-        ri = rsqrt_nr(r2);
+        ri = rsqrt_refined(r2);
         const double ri2 = ri * ri;
         const double S = ai * ai + aj * aj;
         dA = K.k8 * ri2 * (-1.0 - S * ri2);
