@@ -113,8 +113,9 @@ def test_product_path_has_no_cpu_fallback():
 
 
 def test_mobility_entry_points_reject_bad_arguments_without_device_work():
-    """The solve and adjoint behind a mobility function, and the RPY
-    functions, validate their arguments before touching the device."""
+    """The solve and adjoint behind a mobility function, the persistent RPY
+    solve and the RPY functions validate their arguments before touching the
+    device."""
     from paper_1909_06623_amd import _abi as A
     L = A.lib()
     rpy_fn = ctypes.cast(L.sc_rpy_apply, ctypes.c_void_p)
@@ -163,3 +164,24 @@ def test_mobility_entry_points_reject_bad_arguments_without_device_work():
     assert L.sc_rpy_apply(ctypes.addressof(R0), 0, None, None, None) == A.SC_OK
     assert L.sc_rpy_work_bytes(1000) >= 3 * 8 * 1000
     assert L.sc_solve_mob_work_bytes(-1, 10) == 0 and L.sc_adjoint_mob_work_bytes(10, -1) == 0
+    # the persistent RPY solve: missing RPY, bad options, particle counts that
+    # differ, mu <= 0, count beyond capacity
+    Rp = A.sc_rpy(0, 0, 0, 0, 1.0, 0, 0)
+    pers = lambda r, o: L.sc_solve_lcp_rpy(ctypes.byref(p0), ctypes.byref(c), r, ctypes.byref(o),
+                                           None, None, None, None, ctypes.byref(st), None, 0,
+                                           None)
+    assert pers(None, opts) == A.SC_ERR_INVALID
+    for bad in (A.sc_solve_opts(0.0, 100, 1, 0, 0), A.sc_solve_opts(1e-6, -1, 1, 0, 0),
+                A.sc_solve_opts(1e-6, 100, 0, 0, 0), A.sc_solve_opts(1e-6, 100, 1, 0, 0, -1),
+                A.sc_solve_opts(1e-6, 100, 1, 0, 0, 0, 0, 0, 0, 0, -1)):
+        assert pers(ctypes.addressof(Rp), bad) == A.SC_ERR_INVALID
+    Rp.n = 4
+    assert pers(ctypes.addressof(Rp), opts) == A.SC_ERR_INVALID
+    Rp.n, Rp.mu = 0, -1.0
+    assert pers(ctypes.addressof(Rp), opts) == A.SC_ERR_INVALID
+    Rp.mu = 1.0
+    c.capacity, c.count = 2, 3
+    assert pers(ctypes.addressof(Rp), opts) == A.SC_ERR_INVALID
+    c.capacity, c.count = 0, 0
+    assert L.sc_solve_rpy_work_bytes(-1, 10) == 0 and L.sc_solve_rpy_work_bytes(10, -1) == 0
+    assert L.sc_solve_rpy_work_bytes(1000, 3000) >= 2 * 8 * 3000 + 6 * 8 * 1000
