@@ -143,3 +143,42 @@ def test_persistent_rpy_solve_with_walls_matches_oracle():
                                atol=1e-6 * max(1.0, np.abs(go).max()))
     F_o = O.D_apply(n, c, go)
     np.testing.assert_allclose(f_c.cpu().numpy(), F_o, rtol=0, atol=1e-6 * np.abs(F_o).max())
+
+
+@pytest.mark.parametrize("n", [4000, 20000])
+def test_persistent_rpy_solve_with_multi_tile_units_properties(n):
+    """Sizes whose pair units span several 512-source LDS tiles (the tile
+    prefetch path), too large for the oracle's dense M: KKT, the per-phase
+    solve's point, F_c = D gamma against the oracle's D on the oracle's
+    contact list, and sampled rows of U_c against the oracle's pair formula."""
+    import math
+    import paper_1909_06623_amd as sc
+    s = W.spheres(n, 0.3, W.SEED_BASE + 909)
+    s.periodic = 0
+    _say(f"persistent rpy solve, {n} spheres, properties")
+    P, R, con = _setup(s)
+    tol = 1e-6
+    gam, g, st, f_c, u_c = sc.solve_lcp_rpy(P, con, R, tol=tol, want_fc=True)
+    assert st["status"] == 0 and st["n_active"] > n // 2
+    ga, gg = gam.cpu().numpy(), g.cpu().numpy()
+    assert ga.min() >= 0.0 and gg.min() > -tol
+    assert np.linalg.norm(np.minimum(ga, gg)) < tol
+    gm, _, stm, _, _ = sc.solve_lcp_mob(P, con, R, tol=tol)
+    assert stm["status"] == 0
+    np.testing.assert_allclose(ga, gm.cpu().numpy(), rtol=0,
+                               atol=1e-5 * max(1.0, np.abs(ga).max()))
+    c = O.find_contacts(s)
+    assert con.count == c.nc
+    pm = con.canonical_order().cpu().numpy()
+    F_o = O.D_apply(s.n, c, ga[pm])
+    np.testing.assert_allclose(f_c.cpu().numpy(), F_o, rtol=0, atol=1e-12 * np.abs(F_o).max())
+    rows = np.random.default_rng(17).choice(s.n, 3, replace=False)
+    Fc = f_c.cpu().numpy()
+    for r in rows:
+        acc = Fc[r, :3] / (6.0 * math.pi * s.radius[r])
+        for j in range(s.n):
+            if j != r:
+                acc = acc + OM.rpy_block(s.pos[r] - s.pos[j], s.radius[r], s.radius[j],
+                                         1.0) @ Fc[j, :3]
+        np.testing.assert_allclose(u_c.cpu().numpy()[r, :3], acc, rtol=0,
+                                   atol=1e-11 * max(1.0, np.abs(acc).max()))
