@@ -350,6 +350,7 @@ def test_hydro_collision_solve_autograd():
     gamma, f_c, info = sc.hydro_collision_solve(pos, P, box, fe, s.dt, s.delta, tol=1e-10,
                                                 adjoint_tol=1e-13)
     assert info.stats["status"] == 0
+    assert info.stats["op"] == 4     # 250 spheres: the persistent RPY solve
     loss = 0.5 * (f_c * f_c).sum()
     loss.backward()
     con = info.contacts
