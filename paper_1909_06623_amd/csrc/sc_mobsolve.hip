@@ -1615,7 +1615,7 @@ extern "C" int sc_solve_lcp_rpy(const sc_particles *p, const sc_contacts *c, con
     st->kernel_ms = ms;
     st->grid = G;
     st->block = kPB;
-    st->lanes_per_particle = kMsLanes;
+    st->lanes_per_particle = 1;   // one thread forms a source's F in the pair phase
     st->op = SC_OP_RPY;
     return hc.status;
 }
