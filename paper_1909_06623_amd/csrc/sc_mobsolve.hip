@@ -778,7 +778,8 @@ int rpy_splits(int n) {
 
 constexpr int kPB = 1024;                 // threads per workgroup
 constexpr int kPW = kPB / kWave;          // waves per workgroup
-constexpr int kPTile = 512;               // sources per LDS tile
+constexpr int kPLanes = 4;                // threads forming one source's F
+constexpr int kPTile = kPB / kPLanes;     // sources per LDS tile
 
 struct RpyPersArgs {
     MsView V;
@@ -805,10 +806,12 @@ struct PWeights {
 };
 
 // Source of rank k for the pair sum: centre, radius and the force part of
-// F_k = sum over its incidences of w_m D-column entries (in incidence
-// order); the whole F_k (force and torque) is stored when `store`.
+// F_k = sum over its incidences of w_m D-column entries. kPLanes adjacent
+// threads take every kPLanes-th incidence and add their sums in a fixed
+// butterfly, so all of them must call this together; lane 0 stores the whole
+// F_k (force and torque) when `store`.
 __device__ __forceinline__ void p_source(const RpyPersArgs &A, const PWeights &Wt, int k,
-                                         bool store, double (&v)[7]) {
+                                         int lane, bool store, double (&v)[7]) {
     const MsView &V = A.V;
     const int j = V.order[k];
     v[0] = A.pos[3 * j];
@@ -817,17 +820,21 @@ __device__ __forceinline__ void p_source(const RpyPersArgs &A, const PWeights &W
     v[3] = A.rad[j];
     double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int e1 = V.inc_ptr[k + 1];
-    for (int e = V.inc_ptr[k]; e < e1; ++e) {
+    for (int e = V.inc_ptr[k] + lane; e < e1; e += kPLanes) {
         const int m = V.inc[e] >> 1;
         const double w = Wt.step ? project(Wt.gc[m] - Wt.alpha * Wt.ggc[m]) : Wt.x[m];
         const double *d = V.dpm + 6 * static_cast<long long>(e);
 #pragma unroll
         for (int c = 0; c < 6; ++c) a[c] += w * d[c];
     }
+#pragma unroll
+    for (int off = kPLanes / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a[c] += __shfl_xor(a[c], off, kWave);
     v[4] = a[0];
     v[5] = a[1];
     v[6] = a[2];
-    if (store) {
+    if (store && lane == 0) {
         double *fj = A.F + 6 * static_cast<long long>(j);
 #pragma unroll
         for (int c = 0; c < 6; ++c) fj[c] = a[c];
@@ -846,6 +853,7 @@ __device__ void p_pairs(const RpyPersArgs &A, const PWeights &Wt) {
     const int bx = (n + kRpyTargets - 1) / kRpyTargets;
     const int units = bx * S;
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int src = threadIdx.x / kPLanes, sl = threadIdx.x % kPLanes;
     for (int u = logical_block(); u < units; u += gridDim.x) {
         const int tx = u % bx, s = u / bx;
         const bool store = tx == 0;
@@ -860,28 +868,28 @@ __device__ void p_pairs(const RpyPersArgs &A, const PWeights &Wt) {
         // tile is summed
         double nv[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int nj = -1;
-        if (threadIdx.x < kPTile && k0 + static_cast<int>(threadIdx.x) < k1) {
-            p_source(A, Wt, k0 + threadIdx.x, store, nv);
-            nj = A.V.order[k0 + threadIdx.x];
+        if (k0 + src < k1) {   // the same for the kPLanes threads of a source
+            p_source(A, Wt, k0 + src, sl, store, nv);
+            nj = A.V.order[k0 + src];
         }
         for (int t = k0; t < k1; t += kPTile) {
             const int cnt = k1 - t < kPTile ? k1 - t : kPTile;
             __syncthreads();
-            if (threadIdx.x < cnt) {
-                sx[threadIdx.x] = nv[0];
-                sy[threadIdx.x] = nv[1];
-                sz[threadIdx.x] = nv[2];
-                sa[threadIdx.x] = nv[3];
-                sfx[threadIdx.x] = A.K.k8 * nv[4];
-                sfy[threadIdx.x] = A.K.k8 * nv[5];
-                sfz[threadIdx.x] = A.K.k8 * nv[6];
-                sj[threadIdx.x] = nj;
+            if (sl == 0 && src < cnt) {
+                sx[src] = nv[0];
+                sy[src] = nv[1];
+                sz[src] = nv[2];
+                sa[src] = nv[3];
+                sfx[src] = A.K.k8 * nv[4];
+                sfy[src] = A.K.k8 * nv[5];
+                sfz[src] = A.K.k8 * nv[6];
+                sj[src] = nj;
             }
             __syncthreads();
             const int tn = t + kPTile;
-            if (threadIdx.x < kPTile && tn + static_cast<int>(threadIdx.x) < k1) {
-                p_source(A, Wt, tn + threadIdx.x, store, nv);
-                nj = A.V.order[tn + threadIdx.x];
+            if (tn + src < k1) {
+                p_source(A, Wt, tn + src, sl, store, nv);
+                nj = A.V.order[tn + src];
             }
             for (int m = w; m < cnt; m += kPW)
                 rpy_pair(xi - sx[m], yi - sy[m], zi - sz[m], ai, sa[m], sfx[m], sfy[m],
