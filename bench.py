@@ -185,6 +185,28 @@ def hydro(sc, W, torch, np, steps):
     out["solve_rpy"]["adjoint"] = {"ms": adj_ms, "status": sta["status"], "cg_iters": sta["iters"],
                                    "adjoint_forward_ratio": adj_ms / wall}
 
+    # cold solves of the 1000-sphere cluster: one persistent launch against a
+    # launch per phase (the same iteration; HIP events per solve)
+    s = W.sphere_cluster(1000, W.SEED_BASE + 900)
+    P = sc.Particles.from_suspension(s)
+    box = sc.Box(tuple(s.box), lo=tuple(s.lo), periodic=False)
+    R = sc.RPY(P.pos, torch.from_numpy(s.hydro_radius).cuda())
+    con = sc.build_contacts(P, box, s.delta, R.apply(torch.from_numpy(s.f_ext).cuda()), s.dt,
+                            assemble=False)
+    small = {"workload": "1000-sphere cluster (section 6.3 recipe), cold solve to its tolerance",
+             "n_contacts": con.count}
+    for name, fn in (("persistent", sc.solve_lcp_rpy), ("per_phase", sc.solve_lcp_mob)):
+        fn(P, con, R, tol=s.tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            _, _, st, _, _ = fn(P, con, R, tol=s.tol)
+        torch.cuda.synchronize()
+        small[name] = {"ms": 1e3 * (time.perf_counter() - t0) / reps, "mvops": st["mvops"],
+                       "status": st["status"]}
+    out["solve_rpy_small"] = small
+
     for n, nsteps in ((1000, steps), (20000, max(2, steps // 4))):
         s = W.sphere_cluster(n, W.SEED_BASE + 900 + (n == 20000))
         P = sc.Particles.from_suspension(s)
