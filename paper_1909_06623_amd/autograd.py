@@ -158,7 +158,10 @@ def hydro_collision_solve(pos: torch.Tensor, particles: Particles, box: Box,
                           info: Optional[SolveInfo] = None):
     """(gamma, F_c, info) for sphere centres ``pos`` [n, 3] with the RPY
     mobility (hydrodynamic radii default to the collision radii), external
-    forces and torques ``f_ext`` [n, 6]; differentiable in ``pos``."""
+    forces and torques ``f_ext`` [n, 6]; differentiable in ``pos``. The
+    forward solve is one persistent launch up to PERSISTENT_RPY_MAX_N spheres
+    (solve_lcp_rpy) and a launch per phase beyond (solve_lcp_mob); the
+    backward is the adjoint behind the RPY mobility."""
     info = SolveInfo() if info is None else info
     hr = particles.radius if hydro_radius is None else hydro_radius
     f_ext = f_ext.to(device="cuda", dtype=torch.float64).contiguous()
