@@ -23,6 +23,7 @@ HBM_PEAK_GBS = 8000.0
 # Counter summary of the solve kernel on this workload (rocprofv3 FETCH_SIZE
 # and WRITE_SIZE passes, scaled by a plain-copy calibration).
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bbpgd_mat_rods100k_traffic.json")
+TRAFFIC_FILE_LARGE = os.path.join(ROOT, "profiles", "k_bbpgd_mat_rods1M_spheres100k_traffic.json")
 # Sources that define the persistent matrix solve kernel.
 KERNEL_SOURCES = ["sc_matrix.hip", "sc_matrix.hpp", "sc_matrix_pass.hpp", "sc_chain.hpp", "sc_sync.hpp",
                   "sc_common.hpp"]
@@ -43,16 +44,22 @@ def mixed_iteration_bytes(nc_rod, nc_sph, n_rod, n_sph):
     return 216 * nc_rod + 120 * nc_sph + 120 * n_rod + 56 * n_sph
 
 
-def large(sc, W, torch, np):
+def large(sc, W, torch, np, steps=3):
     """Forward solve of the 1,000,000-rod + 100,000-sphere suspension (aligned
-    rods, Watson kappa 5): the largest single-GPU configuration, timed on its
-    own (two solves after one warm-up, HIP events of the persistent kernel)."""
+    rods, Watson kappa 5): the largest single-GPU configuration, whose
+    iterate records and operator (about 0.7 GB per product) do not fit the
+    caches, so its roofline is the HBM one. One warm-up solve, then `steps`
+    timed solves (HIP events of the persistent kernel on its stream)."""
     s = W.workload(3)
     P = sc.Particles.from_suspension(s)
     box = sc.Box(tuple(s.box))
     u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     con = sc.build_contacts(P, box, s.delta, u_nc, s.dt)
-    sts = [sc.solve_lcp(P, con, tol=s.tol)[2] for _ in range(3)][1:]
+    torch.cuda.synchronize()
+    build_ms = 1e3 * (time.perf_counter() - t0)
+    sts = [sc.solve_lcp(P, con, tol=s.tol)[2] for _ in range(steps + 1)][1:]
     st = sts[-1]
     ci = con.i.cpu().numpy()
     cj = con.j.cpu().numpy()
@@ -63,13 +70,25 @@ def large(sc, W, torch, np):
     products = st["iters"] + 2
     kernel_ms = float(np.mean([x["kernel_ms"] for x in sts]))
     achieved = bytes_iter * products / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(st["iters"], TRAFFIC_FILE_LARGE)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_frac": achieved / HBM_PEAK_GBS,
+            "hbm_frac": (None if traffic is None
+                         else traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS),
+            "kernel": "k_bbpgd_mat (persistent BBPGD solve, one launch per solve)",
+            "bytes_model": "216 n_c,rod + 120 n_c,sph + 120 N_rod + 56 N_sph bytes per "
+                           "product (contacts touching a rod priced as rods), (iterations "
+                           "+ 2) products per launch",
+            "bytes_per_product": bytes_iter, "products_per_launch": products,
+            "bytes_per_launch": bytes_iter * products, "launch_ms": kernel_ms,
+            "us_per_product": 1e3 * kernel_ms / products, "grid": st["grid"],
+            "lds_entries_per_wave": st["lds_entries_per_wave"]}
     return {"workload": "1,000,000 spherocylinders (Watson-aligned, kappa 5) + 100,000 "
-                        "spheres D=0.1, periodic box, BBPGD (BB1) to 1e-6",
+                        "spheres D=0.1, periodic box 27.864, delta 0.015, BBPGD (BB1) to 1e-6",
             "n": s.n, "n_contacts": con.count, "nnz_M": con.nnz, "iters": st["iters"],
-            "status": st["status"], "solve_ms": kernel_ms,
-            "us_per_product": 1e3 * kernel_ms / products,
-            "bytes_per_product": bytes_iter, "achieved_gbs": achieved,
-            "frac": achieved / HBM_PEAK_GBS, "rods_per_s": s.n / (kernel_ms * 1e-3)}
+            "status": st["status"], "build_ms": build_ms, "solve_ms": kernel_ms,
+            "rods_per_s": s.n / (kernel_ms * 1e-3), "roofline": roof}
 
 
 def timestepping(sc, W, torch, np, steps):
@@ -186,7 +205,8 @@ def hydro(sc, W, torch, np, steps):
                                    "adjoint_forward_ratio": adj_ms / wall}
 
     # cold solves of the 1000-sphere cluster: one persistent launch against a
-    # launch per phase (the same iteration; HIP events per solve)
+    # launch per phase (the same iteration; host wall clock over 20 solves
+    # after a synchronisation)
     s = W.sphere_cluster(1000, W.SEED_BASE + 900)
     P = sc.Particles.from_suspension(s)
     box = sc.Box(tuple(s.box), lo=tuple(s.lo), periodic=False)
@@ -260,11 +280,11 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def measured_traffic(iters):
+def measured_traffic(iters, path=TRAFFIC_FILE):
     """HBM bytes per launch from the stored counter summary, or None if the
     kernel sources or the launch (iteration count) changed since."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -338,8 +358,52 @@ def batched(sc, W, torch, np, count):
         solve_one(*it)
     torch.cuda.synchronize()
     single_solve_ms = 1e3 * (time.perf_counter() - t0)
+
+    # kernel times of the persistent batched kernels: eager solves on the
+    # current stream bracketed by HIP events, forward alone (a batch without
+    # the adjoint) and forward + adjoint; the difference is the adjoint launch
+    bf = sc.Batch([(P, con) for P, con, _, _, _ in items], tol=tol, team=info["team"])
+
+    def event_ms(b, reps=3):
+        b.solve()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.solve()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    fwd_ms = event_ms(bf)
+    fwd_adj_ms = event_ms(bs)
+    sf, _, _ = bf.stats()
+    sfa, adj2, _ = bs.stats()
+    bf.close()
     bs.close()
     bb.close()
+    fwd_bytes = adj_bytes = 0
+    for s, (P, con, _, _, _), x, a in zip(sus, items, sf, adj2):
+        rods = bool(np.all(s.half_len > 0))
+        fwd_bytes += (x["iters"] + 2) * iteration_bytes(con.count, s.n, rods)
+        adj_bytes += a["iters"] * iteration_bytes(a["n_active"], s.n, rods)
+    adj_ms = max(1e-9, fwd_adj_ms - fwd_ms)
+
+    def roof(nbytes, ms, kernel, model):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+                "bytes_model": model, "bytes_per_launch": nbytes, "launch_ms": ms}
+
+    kernels = {
+        "forward": roof(fwd_bytes, fwd_ms, "k_bbpgd_batch (every instance's Algorithm 1, one "
+                        "cooperative launch; eager, HIP events)",
+                        "per instance (iterations + 2) x (216 n_c + 120 N) bytes for rods, "
+                        "(120 n_c + 56 N) for spheres, summed"),
+        "adjoint": roof(adj_bytes, adj_ms, "k_bbpgd_batch adjoint instantiation (every "
+                        "instance's masked CG; forward + adjoint time minus forward)",
+                        "per instance CG iterations x (216 |A| + 120 N) bytes for rods, "
+                        "(120 |A| + 56 N) for spheres, summed"),
+        "forward_iters_match": [x["iters"] for x in sf] == [x["iters"] for x in sfa]}
     n_tot = sum(s.n for s in sus)
     return {"instances": count, "particles": n_tot,
             "contacts": sum(c for c, _, _ in cnt),
@@ -359,10 +423,76 @@ def batched(sc, W, torch, np, count):
             "iters_sum": sum(x["iters"] for x in st),
             "single_iters_sum": int(sum(i for _, i in singles)),
             "tol": tol, "adjoint_tol": atol,
+            "kernels": kernels,
             "work": "contact build with assembly of M + forward BBPGD + adjoint (CG, geometric "
                     "gradient) per instance",
             "launch": "batched build kernels + reset + cooperative persistent forward and "
                       "adjoint kernels, one HIP graph replay"}
+
+
+def host_cpu():
+    """(CPU model, logical CPUs of the host, CPUs this process may run on)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline(s, W, no_hydro):
+    """The oracle (plain FP64 C) on the same workload: cell-list contacts, q
+    and Algorithm 1 to 1e-6, once on one core and once on all the cores this
+    process may use (OpenMP; the same contact list and products, the sums of
+    Algorithm 1 added per thread in thread order). `value` is the all-cores
+    leg."""
+    import oracle as O
+    model, nproc, usable = host_cpu()
+    env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    nt = max(1, min(usable, env) if env else usable)
+    legs = {}
+    for name, t in (("one_core", 1), ("all_cores", nt)):
+        with O.threads(t):
+            t1 = time.perf_counter()
+            c, u_o, q_o = O.setup(s)
+            tc = time.perf_counter() - t1
+            t1 = time.perf_counter()
+            go, gg, sto = O.bbpgd(s, c, q_o)
+            ts = time.perf_counter() - t1
+        legs[name] = {"value": s.n / (tc + ts), "unit": "rods/s", "cores": t,
+                      "contacts_s": tc, "bbpgd_s": ts, "iters": sto.iters,
+                      "solve_only_rods_per_s": s.n / ts}
+    a = legs["all_cores"]
+    cpu = {"value": a["value"], "unit": "rods/s", "cores": a["cores"], "kind": "oracle",
+           "sample": (f"the full 100k-rod workload once per leg: cell-list contacts + q + "
+                      f"BBPGD to 1e-6 (serial FP64 C; all cores: OpenMP over particles and "
+                      f"contacts): {a['contacts_s']:.1f} s + {a['bbpgd_s']:.1f} s on "
+                      f"{a['cores']} threads, {legs['one_core']['contacts_s']:.1f} s + "
+                      f"{legs['one_core']['bbpgd_s']:.1f} s on one"),
+           "one_core": legs["one_core"], "all_cores": a, "cpu_model": model, "nproc": nproc,
+           "usable_cpus": usable}
+    if not no_hydro:
+        # the oracle's time step behind the RPY mobility (dense NumPy on one
+        # thread) on the 1000-sphere cluster, beside the GPU's in `hydro`
+        import oracle.timestep as OT
+        from threadpoolctl import threadpool_limits
+        cl = W.sphere_cluster(1000, W.SEED_BASE + 900)
+        with threadpool_limits(1):
+            t1 = time.perf_counter()
+            OT.step(cl, OT.quat_from_axis(cl.axis), None, hydro="rpy")
+            tr = time.perf_counter() - t1
+        cpu["rpy_cluster1000_step_ms"] = 1e3 * tr
+        cpu["rpy_sample"] = ("one time step of the 1000-sphere cluster with the RPY mobility: "
+                             "contacts, dense Mob and M, Algorithm 1, update; one thread")
+    return cpu
 
 
 def main():
@@ -380,8 +510,11 @@ def main():
                     help="skip the RPY-mobility leg")
     ap.add_argument("--hydro-steps", type=int, default=20)
     ap.add_argument("--timestep-steps", type=int, default=8)
-    ap.add_argument("--large", action="store_true",
-                    help="also time the 1.1M-particle forward solve")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 1.1M-particle forward solve")
+    ap.add_argument("--only-large", action="store_true",
+                    help="run only the 1.1M-particle forward solve (for profiling)")
+    ap.add_argument("--large-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
     args = ap.parse_args()
@@ -397,6 +530,12 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.only_large:
+        big = large(sc, W, torch, np, args.large_steps)
+        torch.cuda.synchronize()
+        sc.release()
+        print(json.dumps({"large": big}), flush=True)
+        return
     if args.calibrate_copy:
         # a plain copy of known size: 1 GiB read + 1 GiB written per launch
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -471,42 +610,28 @@ def main():
                                              tol=1e-8, workspace=ws)
         torch.cuda.synchronize()
         adj_ms = 1e3 * (time.perf_counter() - t1)
+        cg_bytes = sta["iters"] * iteration_bytes(sta["n_active"], s.n, rods)
+        cg_gbs = cg_bytes / (sta["kernel_ms"] * 1e-3) / 1e9
         adj = {"adjoint_ms": adj_ms, "forward_solve_ms": solve_ms,
                "ratio": adj_ms / solve_ms, "cg_iters": sta["iters"],
-               "cg_rel_residual": sta["residual"], "n_active": sta["n_active"]}
+               "cg_rel_residual": sta["residual"], "n_active": sta["n_active"],
+               "cg_kernel_ms": sta["kernel_ms"],
+               "roofline": {"bound": "hbm", "achieved": cg_gbs, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": cg_gbs / HBM_PEAK_GBS, "traffic": None,
+                            "kernel": "k_cg_mat (persistent masked CG on M_AA, one launch)",
+                            "bytes_model": "216 |A| + 120 N bytes per CG iteration (one "
+                                           "masked product on the active set)",
+                            "bytes_per_launch": cg_bytes, "launch_ms": sta["kernel_ms"],
+                            "us_per_iteration": 1e3 * sta["kernel_ms"] / max(1, sta["iters"])}}
 
     batch = None if args.no_batch else batched(sc, W, torch, np, args.batch_count)
-    big = large(sc, W, torch, np) if args.large else None
+    big = None if args.no_large else large(sc, W, torch, np, args.large_steps)
     tsl = None if args.no_timestep else timestepping(sc, W, torch, np, args.timestep_steps)
     hyd = None if args.no_hydro else hydro(sc, W, torch, np, args.hydro_steps)
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle as O
-        t1 = time.perf_counter()
-        c, u_o, q_o = O.setup(s)
-        tc = time.perf_counter() - t1
-        t1 = time.perf_counter()
-        go, gg, sto = O.bbpgd(s, c, q_o)
-        ts = time.perf_counter() - t1
-        cpu = {"value": s.n / (tc + ts), "unit": "rods/s", "cores": 1, "kind": "oracle",
-               "sample": f"the full workload once: cell-list contacts {tc:.1f} s + "
-                         f"BBPGD {ts:.1f} s ({sto.iters} iterations), serial FP64 C",
-               "solve_only_rods_per_s": s.n / ts, "iters": sto.iters}
-        if not args.no_hydro:
-            # the oracle's time step behind the RPY mobility (dense NumPy on one
-            # thread) on the 1000-sphere cluster, beside the GPU's in `hydro`
-            import oracle.timestep as OT
-            from threadpoolctl import threadpool_limits
-            cl = W.sphere_cluster(1000, W.SEED_BASE + 900)
-            with threadpool_limits(1):
-                t1 = time.perf_counter()
-                OT.step(cl, OT.quat_from_axis(cl.axis), None, hydro="rpy")
-                tr = time.perf_counter() - t1
-            cpu["rpy_cluster1000_step_ms"] = 1e3 * tr
-            cpu["rpy_sample"] = ("one time step of the 1000-sphere cluster with the RPY mobility: "
-                                 "contacts, dense Mob and M, Algorithm 1, update; one thread")
-
+        cpu = cpu_baseline(s, W, args.no_hydro)
     line = {
         "metric": "BBPGD solve time to res 1e-6 (rods/s), HBM GB/s; adjoint/forward time ratio",
         "value": s.n / (ms_step * 1e-3),
@@ -527,6 +652,15 @@ def main():
                    "mvops": st["mvops"], "n_active": st["n_active"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_frac": achieved / HBM_PEAK_GBS,
+                     "hbm_frac": (None if traffic is None
+                                  else traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS),
+                     "note": ("frac and achieved count the method's algorithmic bytes; the "
+                              "77 MB per product stays in LDS (most of M) and the 256 MB "
+                              "Infinity Cache, so hbm_frac (measured HBM bytes, traffic) is "
+                              "far lower and the kernel is bound by its per-iteration "
+                              "latency; the 1.1M-particle leg (large.roofline) is the one "
+                              "that streams from HBM"),
                      "kernel": ("k_bbpgd_mat" if used_matrix else "k_bbpgd")
                                + " (persistent BBPGD solve, one launch per solve)",
                      "bytes_model": ("216 n_c + 120 N" if rods else "120 n_c + 56 N")
@@ -556,6 +690,9 @@ def main():
         "timestep": tsl,
         "hydro": hyd,
     }
+    # everything the library keeps between calls is released before exit
+    torch.cuda.synchronize()
+    sc.release()
     print(json.dumps(line), flush=True)
 
 

@@ -20,7 +20,8 @@
  *   - `stream` is a hipStream_t (NULL = the null stream). Work is enqueued on
  *     it in order. Entry points that must report a count or a status to the
  *     host (build_contacts, solve_lcp, solve_lcp_adjoint) synchronise that
- *     stream before returning; the others do not.
+ *     stream before returning; the others do not. sc_solve_lcp_async is the
+ *     solve with its status left on the device (capturable into a graph).
  *   - A particle's 6-vectors (velocity, force) are (x, y, z, wx, wy, wz):
  *     translational part, then rotational part (section 2 stacks U and F
  *     per particle in this order).
@@ -92,7 +93,8 @@ typedef struct sc_box {
  * the grid reported in `grid`) and, within a cell, by index; contacts are
  * grouped by the rank of their lower-ranked particle, partners by increasing
  * rank. The order is a deterministic function of the inputs, keeps every
- * gather of the solve local, and is the order of gamma and g.
+ * gather of the solve local, and is the order of gamma and g;
+ * sc_canonical_order gives the permutation to the canonical (ci, cj) order.
  *
  * `plan` is a caller-allocated device buffer of at least
  * sc_plan_bytes(n, capacity) bytes (256-byte aligned) in which
@@ -216,6 +218,19 @@ int sc_build_contacts(const sc_particles *p, const sc_box *box, double delta,
                       const double *u_nc, double dt, sc_contacts *c,
                       void *ws, size_t ws_bytes, void *stream);
 
+/* The canonical order of the close-pair set (section 3.1: one constraint per
+ * pair i < j; section 3.2's set listed by ci, then cj, with a wall contact's
+ * negative cj = -1 - face before the particle's pairs): perm[t] = the
+ * solver-order index of the t-th contact in that order, for t < c->count,
+ * so that ci[perm[t]], cj[perm[t]] enumerate the pairs as a plain loop over
+ * i < j would. n: the particles c was built for (sc_build_contacts' plan is
+ * read). perm: device int32 [c->count], OUT. ws: device workspace of at
+ * least sc_workspace_bytes(n, c->capacity) bytes, 256-byte aligned.
+ * Deterministic (no sort, no atomics). Enqueues only; returns SC_OK,
+ * SC_ERR_INVALID, SC_ERR_WORKSPACE or SC_ERR_HIP. */
+int sc_canonical_order(int32_t n, const sc_contacts *c, int32_t *perm, void *ws,
+                       size_t ws_bytes, void *stream);
+
 /* Assemble M = D^T Mob D (LCP LCPdef) into c->mat as a sparse matrix with
  * one row per contact: row l holds M_lm for every contact m sharing a
  * particle with l (deg(ci) + deg(cj) - 1 entries, the diagonal first; rows
@@ -249,6 +264,24 @@ int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
                  double *f_c, double *u_c, sc_stats *st, void *ws,
                  size_t ws_bytes, void *stream);
 
+/* sc_solve_lcp (Algorithm 1, section 3.3.1) without any host
+ * synchronisation, for stream-ordered pipelines and HIP graph capture: the
+ * same checks, kernels and results, but the call only enqueues work on
+ * `stream` (gamma_0, the barrier block and the control block are cleared by
+ * a kernel, no memset), and the statistics are written by a kernel to
+ * `st_dev`, a DEVICE pointer to one sc_stats (status, iters, mvops,
+ * n_active, residual, alpha, n_degenerate and the launch fields;
+ * kernel_ms = 0). The return value reports only argument and launch errors
+ * (SC_OK, SC_ERR_INVALID, SC_ERR_WORKSPACE, SC_ERR_HIP); the solve's own
+ * outcome (SC_OK, SC_NOT_CONVERGED, SC_ERR_NONFINITE, SC_ERR_TIMEOUT) is
+ * st_dev->status once the stream reaches it. Inside a stream capture the
+ * persistent kernel's graph node is marked cooperative by the call. A
+ * replayed graph repeats the captured solve on the buffers it was captured
+ * with, bitwise as an eager call. */
+int sc_solve_lcp_async(const sc_particles *p, const sc_contacts *c,
+                       const sc_solve_opts *opts, double *gamma, double *g, double *f_c,
+                       double *u_c, sc_stats *st_dev, void *ws, size_t ws_bytes, void *stream);
+
 /* Implicit adjoint of a converged solve (not in the paper: it differentiates
  * the LCP of LCP LCPdef on its active set A = {gamma > 0}, section 3.2).
  * Given dL/dgamma [count] and dL/dF_c [n][6] (either may be NULL = zero),
@@ -257,7 +290,8 @@ int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
  * the gradient with respect to the centres with orientations, radii,
  * mobility and u_nc held fixed. gamma must be the solve's output for the
  * same contacts. st (host, OUT): iters = CG iterations, residual = final
- * relative CG residual, n_active = |A|. Synchronises `stream`. */
+ * relative CG residual, n_active = |A|, kernel_ms = GPU time of the
+ * persistent CG kernel (HIP events on `stream`). Synchronises `stream`. */
 int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
                          const sc_contacts *c, const double *u_nc, double dt,
                          const double *gamma, const double *dL_dgamma,
@@ -549,6 +583,15 @@ int sc_solve_lcp_adjoint_mob(const sc_particles *p, const sc_box *box, const sc_
                              void *mob_grad_ctx, const sc_adjoint_opts *opts,
                              int32_t check_every, double *dL_dq, double *dL_dpos, sc_stats *st,
                              void *work, size_t work_bytes, void *stream);
+
+/* Releases the host-side resources the calling thread's earlier calls keep
+ * for reuse (the HIP events that time sc_solve_lcp, the pinned host slots
+ * of the general-mobility solves), after waiting for the current device to
+ * finish its work. Later calls create them again, so it may be called at any
+ * time; a program calls it before it exits so that nothing of the library
+ * is left for the HIP runtime's own teardown. Batches are released by
+ * sc_batch_destroy. Returns SC_OK or SC_ERR_HIP. */
+int sc_release(void);
 
 /* Static string describing a return code. */
 const char *sc_strerror(int code);

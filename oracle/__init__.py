@@ -46,6 +46,10 @@ def _load():
     lib.orc_pair_geometry.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double,
                                       _dp, _dp, ctypes.c_double, ctypes.c_double,
                                       _dp, ctypes.c_int, _dp]
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
+    lib.orc_get_threads.restype = ctypes.c_int
+    lib.orc_get_threads.argtypes = []
     lib.orc_find_contacts.restype = ctypes.c_long
     lib.orc_find_contacts.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp,
                                       _dp, _dp, _dp, ctypes.c_int, ctypes.c_int,
@@ -83,6 +87,34 @@ def _load():
                                           _dp]
     _lib = lib
     return lib
+
+
+def set_threads(t):
+    """Threads of the close-pair search and of Algorithm 1 (default 1).
+    With one thread every result is that of the plain serial loops; with
+    more, the contact list and every product are the same and only the sums
+    over contacts are added as per-thread partial sums in thread order."""
+    _load().orc_set_threads(int(t))
+
+
+def get_threads():
+    return int(_load().orc_get_threads())
+
+
+class threads:
+    """Context manager: ``with threads(8): ...`` runs the oracle on 8 threads."""
+
+    def __init__(self, t):
+        self.t = int(t)
+
+    def __enter__(self):
+        self.prev = get_threads()
+        set_threads(self.t)
+        return self
+
+    def __exit__(self, *exc):
+        set_threads(self.prev)
+        return False
 
 
 def _d(a):

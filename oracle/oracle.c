@@ -20,13 +20,47 @@
  *   (I - pp^T) and B likewise; 6-vectors per particle are (Ux,Uy,Uz,Wx,Wy,Wz).
  *   Contact l joins particles i < j; nrm[l][3] points from i to j.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, so
- * every product and sum is rounded exactly as written).
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no FMA
+ * contraction, so every product and sum is rounded exactly as written).
+ *
+ * Threads. orc_set_threads(T) (default 1) lets the close-pair search and
+ * the BBPGD loop use T OpenMP threads, for timing the oracle on all host
+ * cores. With T = 1 every function computes exactly what the serial loops
+ * below compute. With T > 1 the close pairs are searched per particle in T
+ * contiguous ranges of i and concatenated in range order (the same list),
+ * D gamma is gathered per particle over its contacts in increasing contact
+ * order (the same sums as the contact-order scatter), the per-particle and
+ * per-contact steps are independent, and only the sums over contacts are
+ * formed as T partial sums over contiguous ranges, added in range order.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* threads                                                             */
+/* ------------------------------------------------------------------ */
+#define ORC_MAX_THREADS 256
+static int g_threads = 1;
+
+void orc_set_threads(int t)
+{
+    g_threads = t < 1 ? 1 : (t > ORC_MAX_THREADS ? ORC_MAX_THREADS : t);
+}
+
+int orc_get_threads(void)
+{
+    return g_threads;
+}
+
+/* Range [lo, hi) of `total` items taken by thread t of T. */
+static void thread_range(long total, int t, int T, long *lo, long *hi)
+{
+    *lo = total * t / T;
+    *hi = total * (t + 1) / T;
+}
 
 /* ------------------------------------------------------------------ */
 /* small vector helpers                                                */
@@ -231,13 +265,31 @@ typedef struct {
     int *ci, *cj;
     double *phi, *nrm, *tau_i, *tau_j, *st;
     long nflag_parallel, nflag_zero;
+    int grow; /* 1: the arrays are the sink's own and grow on demand */
 } contact_sink;
+
+static void sink_reserve(contact_sink *k, long need)
+{
+    long cap = k->cap > 0 ? k->cap : 64;
+    while (cap < need)
+        cap *= 2;
+    k->ci = realloc(k->ci, sizeof(int) * (size_t)cap);
+    k->cj = realloc(k->cj, sizeof(int) * (size_t)cap);
+    k->phi = realloc(k->phi, sizeof(double) * (size_t)cap);
+    k->nrm = realloc(k->nrm, sizeof(double) * 3 * (size_t)cap);
+    k->tau_i = realloc(k->tau_i, sizeof(double) * 3 * (size_t)cap);
+    k->tau_j = realloc(k->tau_j, sizeof(double) * 3 * (size_t)cap);
+    k->st = realloc(k->st, sizeof(double) * 2 * (size_t)cap);
+    k->cap = cap;
+}
 
 static void sink_push(contact_sink *k, int i, int j, const double *g, int flags)
 {
     long l = k->count++;
     if (flags & 1) k->nflag_parallel++;
     if (flags & 2) k->nflag_zero++;
+    if (l >= k->cap && k->grow)
+        sink_reserve(k, l + 1);
     if (l >= k->cap)
         return;
     k->ci[l] = i;
@@ -281,6 +333,75 @@ static int cmp_int(const void *a, const void *b)
 {
     int x = *(const int *)a, y = *(const int *)b;
     return (x > y) - (x < y);
+}
+
+typedef struct {
+    const int *nc;
+    const long *start;
+    const int *members, *cell;
+} cell_grid;
+
+typedef struct {
+    int cap_list;
+    int *list;
+} cell_scan;
+
+/* The close pairs (i, j > i) of particle i from the distinct neighbour
+ * cells of its own cell (and i's wall contacts first), in increasing j. */
+static void cell_pairs_of(int i, const cell_grid *grid, cell_scan *scan, const double *pos,
+                          const double *axis, const double *radius, const double *half_len,
+                          const double *lo, const double *L, int periodic, int walls,
+                          double delta, contact_sink *k)
+{
+    const int *nc = grid->nc, *cell = grid->cell, *members = grid->members;
+    const long *start = grid->start;
+    double g[12];
+    int cx = cell[i] % nc[0];
+    int cy = (cell[i] / nc[0]) % nc[1];
+    int cz = cell[i] / (nc[0] * nc[1]);
+    /* distinct neighbour cells along each axis */
+    int off[3][3], noff[3];
+    int cidx[3] = {cx, cy, cz};
+    for (int a = 0; a < 3; ++a) {
+        noff[a] = 0;
+        for (int d = -1; d <= 1; ++d) {
+            int c = cidx[a] + d;
+            if (periodic) {
+                c = (c + nc[a]) % nc[a];
+            } else if (c < 0 || c >= nc[a]) {
+                continue;
+            }
+            int dup = 0;
+            for (int e = 0; e < noff[a]; ++e)
+                if (off[a][e] == c) dup = 1;
+            if (!dup) off[a][noff[a]++] = c;
+        }
+    }
+    int cnt = 0;
+    for (int az = 0; az < noff[2]; ++az)
+        for (int ay = 0; ay < noff[1]; ++ay)
+            for (int ax = 0; ax < noff[0]; ++ax) {
+                long c = ((long)off[2][az] * nc[1] + off[1][ay]) * nc[0] + off[0][ax];
+                for (long m = start[c]; m < start[c + 1]; ++m) {
+                    int j = members[m];
+                    if (j <= i) continue;
+                    if (cnt == scan->cap_list) {
+                        scan->cap_list *= 2;
+                        scan->list = realloc(scan->list, sizeof(int) * (size_t)scan->cap_list);
+                    }
+                    scan->list[cnt++] = j;
+                }
+            }
+    qsort(scan->list, (size_t)cnt, sizeof(int), cmp_int);
+    push_walls(i, pos, axis, radius, half_len, lo, L, walls, delta, sink_push_v, k);
+    for (int m = 0; m < cnt; ++m) {
+        int j = scan->list[m];
+        int fl = pair_geometry(pos + 3 * i, axis + 3 * i, radius[i],
+                               half_len[i], pos + 3 * j, axis + 3 * j,
+                               radius[j], half_len[j], L, periodic, g);
+        if (g[0] <= delta)
+            sink_push(k, i, j, g, fl);
+    }
 }
 
 /* Cell list (section 5.2 names cell lists as a standard near-neighbour
@@ -334,58 +455,59 @@ static void contacts_cells(int n, const double *pos, const double *axis,
         members[fill[cell[i]]++] = i;
     free(fill);
 
-    int cap_list = 64;
-    int *list = malloc(sizeof(int) * (size_t)cap_list);
-    double g[12];
-    for (int i = 0; i < n; ++i) {
-        int cx = cell[i] % nc[0];
-        int cy = (cell[i] / nc[0]) % nc[1];
-        int cz = cell[i] / (nc[0] * nc[1]);
-        /* distinct neighbour cells along each axis */
-        int off[3][3], noff[3];
-        int cidx[3] = {cx, cy, cz};
-        for (int a = 0; a < 3; ++a) {
-            noff[a] = 0;
-            for (int d = -1; d <= 1; ++d) {
-                int c = cidx[a] + d;
-                if (periodic) {
-                    c = (c + nc[a]) % nc[a];
-                } else if (c < 0 || c >= nc[a]) {
-                    continue;
-                }
-                int dup = 0;
-                for (int e = 0; e < noff[a]; ++e)
-                    if (off[a][e] == c) dup = 1;
-                if (!dup) off[a][noff[a]++] = c;
-            }
+    cell_grid grid = {nc, start, members, cell};
+    int T = g_threads;
+    if (T == 1) {
+        cell_scan scan = {64, malloc(sizeof(int) * 64)};
+        for (int i = 0; i < n; ++i)
+            cell_pairs_of(i, &grid, &scan, pos, axis, radius, half_len, lo, L, periodic,
+                          walls, delta, k);
+        free(scan.list);
+    } else {
+        /* T contiguous ranges of i, each into a sink of its own, then
+         * concatenated in range order: the same list as the loop above */
+        contact_sink part[ORC_MAX_THREADS];
+        memset(part, 0, sizeof(part));
+#pragma omp parallel num_threads(T)
+        {
+            int t = omp_get_thread_num(), nt = omp_get_num_threads();
+#pragma omp single
+            T = nt;
+            long i0, i1;
+            thread_range(n, t, nt, &i0, &i1);
+            contact_sink *mine = &part[t];
+            mine->grow = 1;
+            cell_scan scan = {64, malloc(sizeof(int) * 64)};
+            for (long i = i0; i < i1; ++i)
+                cell_pairs_of((int)i, &grid, &scan, pos, axis, radius, half_len, lo, L,
+                              periodic, walls, delta, mine);
+            free(scan.list);
         }
-        int cnt = 0;
-        for (int az = 0; az < noff[2]; ++az)
-            for (int ay = 0; ay < noff[1]; ++ay)
-                for (int ax = 0; ax < noff[0]; ++ax) {
-                    long c = ((long)off[2][az] * nc[1] + off[1][ay]) * nc[0] + off[0][ax];
-                    for (long m = start[c]; m < start[c + 1]; ++m) {
-                        int j = members[m];
-                        if (j <= i) continue;
-                        if (cnt == cap_list) {
-                            cap_list *= 2;
-                            list = realloc(list, sizeof(int) * (size_t)cap_list);
-                        }
-                        list[cnt++] = j;
-                    }
-                }
-        qsort(list, (size_t)cnt, sizeof(int), cmp_int);
-        push_walls(i, pos, axis, radius, half_len, lo, L, walls, delta, sink_push_v, k);
-        for (int m = 0; m < cnt; ++m) {
-            int j = list[m];
-            int fl = pair_geometry(pos + 3 * i, axis + 3 * i, radius[i],
-                                   half_len[i], pos + 3 * j, axis + 3 * j,
-                                   radius[j], half_len[j], L, periodic, g);
-            if (g[0] <= delta)
-                sink_push(k, i, j, g, fl);
+        for (int t = 0; t < T; ++t) {
+            contact_sink *p = &part[t];
+            for (long l = 0; l < p->count; ++l) {
+                long d = k->count++;
+                if (d >= k->cap)
+                    continue;
+                k->ci[d] = p->ci[l];
+                k->cj[d] = p->cj[l];
+                k->phi[d] = p->phi[l];
+                memcpy(k->nrm + 3 * d, p->nrm + 3 * l, 3 * sizeof(double));
+                memcpy(k->tau_i + 3 * d, p->tau_i + 3 * l, 3 * sizeof(double));
+                memcpy(k->tau_j + 3 * d, p->tau_j + 3 * l, 3 * sizeof(double));
+                memcpy(k->st + 2 * d, p->st + 2 * l, 2 * sizeof(double));
+            }
+            k->nflag_parallel += p->nflag_parallel;
+            k->nflag_zero += p->nflag_zero;
+            free(p->ci);
+            free(p->cj);
+            free(p->phi);
+            free(p->nrm);
+            free(p->tau_i);
+            free(p->tau_j);
+            free(p->st);
         }
     }
-    free(list);
     free(cell);
     free(start);
     free(members);
@@ -403,7 +525,7 @@ long orc_find_contacts(int method, int n, const double *pos,
                        double *tau_i, double *tau_j, double *st,
                        long *flags_out)
 {
-    contact_sink k = {cap, 0, ci, cj, phi, nrm, tau_i, tau_j, st, 0, 0};
+    contact_sink k = {cap, 0, ci, cj, phi, nrm, tau_i, tau_j, st, 0, 0, 0};
     if (periodic)
         walls = 0;
     if (method == 0)
@@ -497,14 +619,75 @@ typedef struct {
     const int *ci, *cj;
     const double *nrm, *tau_i, *tau_j, *axis, *mob;
     double *F, *U; /* scratch [n][6] */
+    long *inc_ptr, *inc; /* T > 1: contacts of each particle, 2 l + side (0: i, 1: j) */
 } mvop_ctx;
+
+/* For T > 1 threads: each particle's contacts in increasing contact order. */
+static void mvop_incidence(mvop_ctx *c)
+{
+    c->inc_ptr = calloc((size_t)c->n + 1, sizeof(long));
+    c->inc = malloc(sizeof(long) * 2 * (size_t)(c->nc > 0 ? c->nc : 1));
+    for (long l = 0; l < c->nc; ++l) {
+        c->inc_ptr[c->ci[l] + 1]++;
+        if (c->cj[l] >= 0) c->inc_ptr[c->cj[l] + 1]++;
+    }
+    for (int k = 0; k < c->n; ++k)
+        c->inc_ptr[k + 1] += c->inc_ptr[k];
+    long *fill = malloc(sizeof(long) * (size_t)(c->n > 0 ? c->n : 1));
+    memcpy(fill, c->inc_ptr, sizeof(long) * (size_t)c->n);
+    for (long l = 0; l < c->nc; ++l) {
+        c->inc[fill[c->ci[l]]++] = 2 * l;
+        if (c->cj[l] >= 0) c->inc[fill[c->cj[l]]++] = 2 * l + 1;
+    }
+    free(fill);
+}
+
+/* F = D x gathered per particle: the same operations, in the same order per
+ * particle, as orc_D_apply's scatter in contact order. */
+static void d_apply_gather(const mvop_ctx *c, const double *x, double *F)
+{
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+    for (int k = 0; k < c->n; ++k) {
+        double f[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (long e = c->inc_ptr[k]; e < c->inc_ptr[k + 1]; ++e) {
+            long l = c->inc[e] / 2;
+            if (c->inc[e] % 2 == 0) {
+                for (int a = 0; a < 3; ++a) {
+                    f[a] -= c->nrm[3 * l + a] * x[l];
+                    f[3 + a] -= c->tau_i[3 * l + a] * x[l];
+                }
+            } else {
+                for (int a = 0; a < 3; ++a) {
+                    f[a] += c->nrm[3 * l + a] * x[l];
+                    f[3 + a] += c->tau_j[3 * l + a] * x[l];
+                }
+            }
+        }
+        memcpy(F + 6 * (size_t)k, f, sizeof(f));
+    }
+}
 
 /* out = M x = D^T Mob D x (one "MVOP" in the paper's accounting). */
 static void mvop(mvop_ctx *c, const double *x, double *out)
 {
-    orc_D_apply(c->n, c->nc, c->ci, c->cj, c->nrm, c->tau_i, c->tau_j, x, c->F);
-    orc_mobility(c->n, c->axis, c->mob, c->F, c->U);
-    orc_DT_apply(c->nc, c->ci, c->cj, c->nrm, c->tau_i, c->tau_j, c->U, out);
+    if (g_threads == 1) {
+        orc_D_apply(c->n, c->nc, c->ci, c->cj, c->nrm, c->tau_i, c->tau_j, x, c->F);
+        orc_mobility(c->n, c->axis, c->mob, c->F, c->U);
+        orc_DT_apply(c->nc, c->ci, c->cj, c->nrm, c->tau_i, c->tau_j, c->U, out);
+        return;
+    }
+    d_apply_gather(c, x, c->F);
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+    for (int k = 0; k < c->n; ++k)
+        orc_mobility(1, c->axis + 3 * k, c->mob + 4 * k, c->F + 6 * k, c->U + 6 * k);
+    long T = g_threads;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+    for (long t = 0; t < T; ++t) {
+        long l0, l1;
+        thread_range(c->nc, (int)t, (int)T, &l0, &l1);
+        orc_DT_apply(l1 - l0, c->ci + l0, c->cj + l0, c->nrm + 3 * l0, c->tau_i + 3 * l0,
+                     c->tau_j + 3 * l0, c->U, out + l0);
+    }
 }
 
 void orc_mvop(int n, long nc, const int *ci, const int *cj, const double *nrm,
@@ -513,10 +696,14 @@ void orc_mvop(int n, long nc, const int *ci, const int *cj, const double *nrm,
 {
     mvop_ctx c = {n, nc, ci, cj, nrm, tau_i, tau_j, axis, mob,
                   malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1)),
-                  malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1))};
+                  malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1)), NULL, NULL};
+    if (g_threads > 1)
+        mvop_incidence(&c);
     mvop(&c, x, out);
     free(c.F);
     free(c.U);
+    free(c.inc_ptr);
+    free(c.inc);
 }
 
 /* Diagonal of M: M_ll = D_l^T Mob D_l. */
@@ -548,14 +735,57 @@ void orc_M_diag(long nc, const int *ci, const int *cj, const double *nrm,
 /* ||min(gamma, g)||_2 (Eq. mmapnorm) as the absolute stopping test.    */
 /* ------------------------------------------------------------------ */
 
+/* The sums over contacts of the solver, sums[0..2] over l of
+ *   what 0: min(a_l, b_l)^2 (and nothing else)
+ *   what 1: a_l a_l, a_l b_l
+ *   what 2: s_l s_l, s_l y_l, y_l y_l with s = a - c, y = b - d
+ * as T partial sums over contiguous ranges of l added in range order (one
+ * range, the plain left-to-right sum, when T = 1). */
+static void contact_sums(int what, long nc, const double *a, const double *b,
+                         const double *c, const double *d, double *sums)
+{
+    double part[ORC_MAX_THREADS][3];
+    int T = g_threads;
+#pragma omp parallel num_threads(T)
+    {
+        int t = omp_get_thread_num(), nt = omp_get_num_threads();
+#pragma omp single
+        T = nt;
+        long l0, l1;
+        thread_range(nc, t, nt, &l0, &l1);
+        double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+        for (long l = l0; l < l1; ++l) {
+            if (what == 0) {
+                double m = a[l] < b[l] ? a[l] : b[l];
+                x0 += m * m;
+            } else if (what == 1) {
+                x0 += a[l] * a[l];
+                x1 += a[l] * b[l];
+            } else {
+                double s = a[l] - c[l];
+                double y = b[l] - d[l];
+                x0 += s * s;
+                x1 += s * y;
+                x2 += y * y;
+            }
+        }
+        part[t][0] = x0;
+        part[t][1] = x1;
+        part[t][2] = x2;
+    }
+    for (int k = 0; k < 3; ++k) {
+        double acc = part[0][k];
+        for (int t = 1; t < T; ++t)
+            acc += part[t][k];
+        sums[k] = acc;
+    }
+}
+
 static double residual(long nc, const double *gamma, const double *g)
 {
-    double acc = 0.0;
-    for (long l = 0; l < nc; ++l) {
-        double m = gamma[l] < g[l] ? gamma[l] : g[l];
-        acc += m * m;
-    }
-    return sqrt(acc);
+    double sums[3];
+    contact_sums(0, nc, gamma, g, NULL, NULL, sums);
+    return sqrt(sums[0]);
 }
 
 /* bb: 1 = BB1 every step, 2 = BB2 every step, 3 = BB1 on odd j and BB2 on
@@ -573,7 +803,9 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
     size_t sz = sizeof(double) * (size_t)(nc > 0 ? nc : 1);
     mvop_ctx c = {n, nc, ci, cj, nrm, tau_i, tau_j, axis, mob,
                   malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1)),
-                  malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1))};
+                  malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1)), NULL, NULL};
+    if (g_threads > 1)
+        mvop_incidence(&c);
     double *gamma_prev = malloc(sz), *g_prev = malloc(sz), *tmp = malloc(sz);
     int status = 0, iters = 0, mvops = 0;
     long ndegen = 0;
@@ -582,6 +814,7 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
     /* g0 = M gamma0 + q */
     mvop(&c, gamma, g);
     mvops++;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (long l = 0; l < nc; ++l)
         g[l] += q[l];
     res = residual(nc, gamma, g);
@@ -596,11 +829,9 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
     mvop(&c, g, tmp);
     mvops++;
     {
-        double num = 0.0, den = 0.0;
-        for (long l = 0; l < nc; ++l) {
-            num += g[l] * g[l];
-            den += g[l] * tmp[l];
-        }
+        double sums[3];
+        contact_sums(1, nc, g, tmp, NULL, NULL, sums);
+        double num = sums[0], den = sums[1];
         if (den > 0.0 && isfinite(den) && isfinite(num)) {
             alpha = num / den;
         } else {
@@ -617,6 +848,7 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
         memcpy(gamma_prev, gamma, sz);
         memcpy(g_prev, g, sz);
         /* descent step, then projection onto gamma >= 0 */
+#pragma omp parallel for num_threads(g_threads) schedule(static)
         for (long l = 0; l < nc; ++l) {
             double v = gamma_prev[l] - alpha * g_prev[l];
             gamma[l] = v < 0.0 ? 0.0 : v;
@@ -624,6 +856,7 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
         /* new gradient g = M gamma + q */
         mvop(&c, gamma, g);
         mvops++;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
         for (long l = 0; l < nc; ++l)
             g[l] += q[l];
         iters = j;
@@ -638,14 +871,9 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
             break;
         }
         /* BB step size from s = gamma_j - gamma_{j-1}, y = g_j - g_{j-1} */
-        double ss = 0.0, sy = 0.0, yy = 0.0;
-        for (long l = 0; l < nc; ++l) {
-            double s = gamma[l] - gamma_prev[l];
-            double y = g[l] - g_prev[l];
-            ss += s * s;
-            sy += s * y;
-            yy += y * y;
-        }
+        double sums[3];
+        contact_sums(2, nc, gamma, g, gamma_prev, g_prev, sums);
+        double ss = sums[0], sy = sums[1], yy = sums[2];
         int use_bb2 = (bb == 2) || (bb == 3 && (j % 2 == 0));
         double num = use_bb2 ? sy : ss;
         double den = use_bb2 ? yy : sy;
@@ -671,6 +899,8 @@ done:;
     free(tmp);
     free(c.F);
     free(c.U);
+    free(c.inc_ptr);
+    free(c.inc);
     return status;
 }
 

@@ -125,11 +125,16 @@ SIGNATURES = {
     "sc_build_contacts": (ctypes.c_int, [P(sc_particles), P(sc_box), ctypes.c_double,
                                          c_dp, ctypes.c_double, P(sc_contacts), c_dp,
                                          ctypes.c_size_t, c_dp]),
+    "sc_canonical_order": (ctypes.c_int, [ctypes.c_int32, P(sc_contacts), c_dp, c_dp,
+                                          ctypes.c_size_t, c_dp]),
     "sc_mvop": (ctypes.c_int, [P(sc_particles), P(sc_contacts), c_dp, c_dp, c_dp,
                                ctypes.c_size_t, c_dp]),
     "sc_solve_lcp": (ctypes.c_int, [P(sc_particles), P(sc_contacts), P(sc_solve_opts),
                                     c_dp, c_dp, c_dp, c_dp, P(sc_stats), c_dp,
                                     ctypes.c_size_t, c_dp]),
+    "sc_solve_lcp_async": (ctypes.c_int, [P(sc_particles), P(sc_contacts),
+                                          P(sc_solve_opts), c_dp, c_dp, c_dp, c_dp, c_dp,
+                                          c_dp, ctypes.c_size_t, c_dp]),
     "sc_solve_lcp_adjoint": (ctypes.c_int, [P(sc_particles), P(sc_box), P(sc_contacts),
                                             c_dp, ctypes.c_double, c_dp, c_dp, c_dp,
                                             c_dp, c_dp, P(sc_adjoint_opts), P(sc_stats),
@@ -167,6 +172,7 @@ SIGNATURES = {
     "sc_solve_lcp_rpy": (ctypes.c_int, [P(sc_particles), P(sc_contacts), c_dp,
                                         P(sc_solve_opts), c_dp, c_dp, c_dp, c_dp, P(sc_stats),
                                         c_dp, ctypes.c_size_t, c_dp]),
+    "sc_release": (ctypes.c_int, []),
     "sc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sc_version": (ctypes.c_int, []),
 }

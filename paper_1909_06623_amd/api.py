@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import sys
 from typing import Optional
 
 import torch
@@ -28,6 +29,16 @@ def _check(fn, rc, allow=(A.SC_OK,)):
     if rc not in allow:
         raise A.ScError(fn, rc)
     return rc
+
+
+def require_solution(fn, st):
+    """Raise ScError unless a solve's status is SC_OK or SC_NOT_CONVERGED
+    (the iteration cap: the outputs hold the last iterate). A timed-out
+    barrier or a non-finite iterate leaves nothing fit to move particles
+    with or to differentiate."""
+    if st["status"] not in (A.SC_OK, A.SC_NOT_CONVERGED):
+        raise A.ScError(fn, st["status"])
+    return st
 
 
 def _dev(t, dtype=torch.float64):
@@ -208,11 +219,24 @@ class Contacts:
     def tau_j(self):
         return self.frame[: self.count, 6:9]
 
-    def canonical_order(self):
-        """Permutation that sorts the contacts by (ci, cj) (the order of a
-        plain enumeration of pairs i < j)."""
-        key = self.i.to(torch.int64) * (1 << 32) + self.j.to(torch.int64)
-        return torch.argsort(key)
+    def canonical_order(self, workspace: Optional["Workspace"] = None):
+        """Permutation (int64 indices into the solver order) that lists the
+        contacts by (ci, cj), the order of a plain enumeration of pairs
+        i < j; computed by the library (sc_canonical_order)."""
+        perm = torch.empty(max(1, self.count), dtype=torch.int32, device="cuda")
+        ws = workspace or default_workspace()
+        wsp, wsn = ws.get(self.n, self.capacity)
+        cc = self.c()
+        _check("sc_canonical_order",
+               A.lib().sc_canonical_order(self.n, ctypes.byref(cc), _ptr(perm), wsp, wsn,
+                                          _stream()))
+        return perm[: self.count].to(torch.int64)
+
+
+def release():
+    """Wait for the device, then free the host resources the library keeps
+    for this thread between calls (sc_release). Call before exiting."""
+    _check("sc_release", A.lib().sc_release())
 
 
 def apply_mobility(particles: Particles, f: torch.Tensor) -> torch.Tensor:
@@ -298,6 +322,37 @@ def solve_lcp(particles: Particles, contacts: Contacts, tol: float = 1e-6,
                                                       A.SC_ERR_NONFINITE, A.SC_ERR_TIMEOUT)
     _check("sc_solve_lcp", rc, allow)
     return gamma[:nc], g[:nc], st.as_dict(), f_c, u_c
+
+
+STATS_BYTES = ctypes.sizeof(A.sc_stats)
+
+
+def stats_from_device(buf: torch.Tensor) -> dict:
+    """An sc_stats written to device memory (a uint8 tensor of STATS_BYTES),
+    read back as a dict (synchronises with the copy)."""
+    st = A.sc_stats.from_buffer_copy(bytes(buf.cpu().numpy().tobytes()))
+    return st.as_dict()
+
+
+def solve_lcp_async(particles: Particles, contacts: Contacts, gamma: torch.Tensor,
+                    g: torch.Tensor, stats: torch.Tensor, tol: float = 1e-6,
+                    max_iter: int = 100000, bb: int = 1, warm_start: bool = False,
+                    f_c: Optional[torch.Tensor] = None, u_c: Optional[torch.Tensor] = None,
+                    op: int = 0, spin_limit: int = 0, workspace: Optional[Workspace] = None):
+    """BBPGD through sc_solve_lcp_async: enqueues the solve on the current
+    stream and returns at once (capturable with torch.cuda.graph). gamma, g
+    (and f_c, u_c) are the caller's buffers; ``stats`` is a device uint8
+    tensor of STATS_BYTES that receives the sc_stats (``stats_from_device``).
+    Raises only on argument or launch errors."""
+    opts = A.sc_solve_opts(float(tol), int(max_iter), int(bb), 1 if warm_start else 0,
+                           0, 0, 0, int(op), 0, 0, int(spin_limit))
+    ws = workspace or default_workspace()
+    wsp, wsn = ws.get(particles.n, contacts.capacity)
+    pc, cc = particles.c(), contacts.c()
+    _check("sc_solve_lcp_async",
+           A.lib().sc_solve_lcp_async(ctypes.byref(pc), ctypes.byref(cc), ctypes.byref(opts),
+                                      _ptr(gamma), _ptr(g), _ptr(f_c), _ptr(u_c), _ptr(stats),
+                                      wsp, wsn, _stream()))
 
 
 def solve_lcp_adjoint(particles: Particles, box: Box, contacts: Contacts,
@@ -738,6 +793,10 @@ class Batch:
             self._h = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be gone: leave
+        # the plan to the process's end instead of calling into it
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -20,6 +20,10 @@ Orientations, radii and mobility coefficients receive no gradient, and U_nc
 none in ``collision_solve`` (the dry mobility does not depend on the
 centres). The contact set is piecewise constant in the centres; the
 gradient is that of the active branch.
+
+A forward solve that ends with an error status (a barrier time-out, a
+non-finite iterate) raises ScError before anything is saved for backward,
+and so does a backward whose conjugate-gradient solve misses its tolerance.
 """
 from __future__ import annotations
 
@@ -30,8 +34,9 @@ from typing import Optional
 import torch
 from torch.autograd.function import once_differentiable
 
-from .api import (RPY, Box, Contacts, Particles, build_contacts, solve_lcp, solve_lcp_adjoint,
-                  solve_lcp_adjoint_mob, solve_lcp_mob, solve_lcp_rpy)
+from . import _abi as A
+from .api import (RPY, Box, Contacts, Particles, build_contacts, require_solution, solve_lcp,
+                  solve_lcp_adjoint, solve_lcp_adjoint_mob, solve_lcp_mob, solve_lcp_rpy)
 
 
 # Largest system whose RPY solve runs as one persistent launch.
@@ -54,6 +59,7 @@ class _CollisionSolve(torch.autograd.Function):
         con = build_contacts(P, box, delta, u_nc, dt)
         gamma, g, st, f_c, u_c = solve_lcp(P, con, tol=tol, want_fc=True, **kw)
         info.contacts, info.stats = con, st
+        require_solution("sc_solve_lcp", st)
         ctx.state = (P, box, con, u_nc, dt, adjoint_tol, info, kw)
         ctx.save_for_backward(gamma)
         return gamma, f_c
@@ -67,6 +73,7 @@ class _CollisionSolve(torch.autograd.Function):
                                           dL_df=dL_df, tol=adjoint_tol,
                                           **_adjoint_kw(kw))
         info.dL_dq, info.adjoint_stats = dq, sta
+        _require_adjoint("sc_solve_lcp_adjoint", sta)
         return dpos, None, None, None, None, None, None, None, None, None
 
 
@@ -78,6 +85,7 @@ class _LcpSolve(torch.autograd.Function):
         con.q[: con.count] = q.detach().to(torch.float64)
         gamma, g, st, _, _ = solve_lcp(particles, con, tol=tol, **kw)
         info.contacts, info.stats = con, st
+        require_solution("sc_solve_lcp", st)
         ctx.state = (particles, box, con, u_nc, dt, adjoint_tol, info, kw)
         ctx.save_for_backward(gamma)
         return gamma
@@ -90,6 +98,7 @@ class _LcpSolve(torch.autograd.Function):
         dq, dpos, sta = solve_lcp_adjoint(P, box, con, u_nc, dt, gamma, dL_dgamma=dL_dgamma,
                                           tol=adjoint_tol, **_adjoint_kw(kw))
         info.dL_dq, info.adjoint_stats = dq, sta
+        _require_adjoint("sc_solve_lcp_adjoint", sta)
         return dq, None, None, None, None, None, None, None, None, None
 
 
@@ -106,6 +115,7 @@ class _HydroCollisionSolve(torch.autograd.Function):
         solve = solve_lcp_rpy if P.n <= PERSISTENT_RPY_MAX_N else solve_lcp_mob
         gamma, g, st, f_c, u_c = solve(P, con, R, tol=tol, want_fc=True)
         info.contacts, info.stats = con, st
+        require_solution(solve.__name__, st)
         ctx.state = (P, box, con, R, f_ext, u_nc, dt, adjoint_tol, info)
         ctx.save_for_backward(gamma)
         return gamma, f_c
@@ -119,7 +129,15 @@ class _HydroCollisionSolve(torch.autograd.Function):
                                               dL_dgamma=dL_dgamma, dL_df=dL_df,
                                               tol=adjoint_tol)
         info.dL_dq, info.adjoint_stats = dq, sta
+        _require_adjoint("sc_solve_lcp_adjoint_mob", sta)
         return dpos, None, None, None, None, None, None, None, None, None, None
+
+
+def _require_adjoint(fn, st):
+    """The gradient is only that of the solve when the adjoint's CG met its
+    tolerance: any other status (the iteration cap included) raises."""
+    if st["status"] != A.SC_OK:
+        raise A.ScError(fn, st["status"])
 
 
 def _adjoint_kw(kw):

@@ -314,6 +314,9 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     A.tol = opts->tol;
     A.max_iter = opts->max_iter;
     void *args[] = {&A};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!thread_events(&e0, &e1)) return SC_ERR_HIP;
+    SC_HIP_TRY(hipEventRecord(e0, s));
     if (use_mat) {
         SC_HIP_TRY(launch_cg_mat(mat_view(nc, mb), gamma, zrec, pv, x, part, sync, ctrl,
                                  opts->tol, opts->max_iter, spw, opts->lds_entries_per_wave,
@@ -322,6 +325,7 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
         SC_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G),
                                               dim3(block), args, 0, s));
     }
+    SC_HIP_TRY(hipEventRecord(e1, s));
     // dL/dq = -w on A; V_w = Mob D w; U_c = Mob D gamma; geometric terms
     k_neg_masked<<<grid_for(nc), kBlock, 0, s>>>(nc, gamma, x, dL_dq);
     ChainView Cv = chain_view(p, c, pl, Vw), Cc = chain_view(p, c, pl, Uc);
@@ -336,6 +340,9 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     SC_HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(CgCtrl), hipMemcpyDeviceToHost, s));
     SC_HIP_TRY(hipStreamSynchronize(s));
     SC_HIP_TRY(hipGetLastError());
+    float cg_ms = 0.0f;
+    SC_HIP_TRY(hipEventElapsedTime(&cg_ms, e0, e1));
+    st->kernel_ms = cg_ms;
     st->status = hc.status;
     st->iters = hc.iters;
     st->mvops = hc.iters + 1;

@@ -1,5 +1,5 @@
 // sc_api.hip -- library-level entry points: workspace sizing, error text,
-// version.
+// release of per-thread host resources, version.
 #include "sc_common.hpp"
 
 extern "C" size_t sc_workspace_bytes(int32_t n, int32_t capacity) {
@@ -26,4 +26,11 @@ extern "C" const char *sc_strerror(int code) {
     }
 }
 
-extern "C" int sc_version(void) { return 320; }
+extern "C" int sc_release(void) {
+    if (hipDeviceSynchronize() != hipSuccess) return SC_ERR_HIP;
+    sc::release_solve_host();
+    sc::release_mob_host();
+    return SC_OK;
+}
+
+extern "C" int sc_version(void) { return 330; }

@@ -56,6 +56,22 @@ size_t solve_ws_bytes(int32_t n, int32_t cap);
 size_t adjoint_ws_bytes(int32_t n, int32_t cap);
 size_t cell_budget(int32_t n);
 
+// Host resources a thread keeps between calls (sc_release frees them): the
+// solve's timing events (sc_solve.hip) and the general-mobility solves'
+// pinned control-block slots (sc_mobsolve.hip).
+void release_solve_host();
+// The calling thread's two timing events (created on first use, destroyed by
+// sc_release); false if they cannot be created.
+bool thread_events(hipEvent_t *t0, hipEvent_t *t1);
+void release_mob_host();
+
+// sc_solve_lcp on a given workspace (defined in sc_solve.hip); `timed`
+// records HIP events around the persistent kernel (st->kernel_ms), else no
+// event is created and kernel_ms is 0.
+int solve_lcp_on(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *opts,
+                 double *gamma, double *g, double *f_c, double *u_c, sc_stats *st, void *ws,
+                 size_t ws_bytes, void *stream, bool timed);
+
 // Device-wide exclusive scan of n int32 values: out[k] = sum_{m<k} in[m] and
 // out[n] = total. `tmp` needs scan_tmp_ints(n) ints. in may equal out.
 int scan_tmp_ints(int n);

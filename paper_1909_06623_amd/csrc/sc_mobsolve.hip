@@ -1120,8 +1120,10 @@ size_t rpy_pers_ws_bytes(int32_t n, int32_t cap) {
 constexpr size_t kPinnedSlot = 128;
 static_assert(sizeof(MsCtrl) <= kPinnedSlot && sizeof(CgMobCtrl) <= kPinnedSlot, "pinned slot");
 
+thread_local char *tl_pinned = nullptr;
+
 char *pinned_slots() {
-    thread_local char *p = nullptr;
+    char *&p = tl_pinned;
     if (!p && hipHostMalloc(reinterpret_cast<void **>(&p), 2 * kPinnedSlot,
                             hipHostMallocDefault) != hipSuccess)
         p = nullptr;
@@ -1169,6 +1171,13 @@ size_t ms_ws_bytes(int32_t n, int32_t cap) {
 }
 
 }  // namespace
+
+// Frees the calling thread's pinned control-block slots (allocated again on
+// the next solve that needs them).
+void release_mob_host() {
+    if (tl_pinned) (void)hipHostFree(tl_pinned);
+    tl_pinned = nullptr;
+}
 
 }  // namespace sc
 
@@ -1623,7 +1632,7 @@ extern "C" int sc_solve_lcp_rpy(const sc_particles *p, const sc_contacts *c, con
     st->kernel_ms = ms;
     st->grid = G;
     st->block = kPB;
-    st->lanes_per_particle = 1;   // one thread forms a source's F in the pair phase
+    st->lanes_per_particle = kPLanes;   // threads forming one source's F in the pair phase
     st->op = SC_OP_RPY;
     return hc.status;
 }

@@ -12,6 +12,7 @@
 // fixed order and takes the same decision: stop, or the next BB step size.
 // No floating-point atomics are used, so the iterates are
 // bitwise reproducible for a given launch shape.
+#include <cstddef>
 #include <cstring>
 
 #include "sc_chain.hpp"
@@ -244,8 +245,10 @@ struct Timing {
     bool ok = false;
 };
 
+thread_local Timing tl_timing;
+
 Timing &timing() {
-    thread_local Timing tm;
+    Timing &tm = tl_timing;
     if (!tm.ok) {
         if (hipEventCreate(&tm.t0) != hipSuccess || hipEventCreate(&tm.t1) != hipSuccess)
             return tm;
@@ -294,6 +297,23 @@ int max_coresident(const void *fn, int block, size_t dyn, int *cus) {
 }
 
 }  // namespace
+
+bool thread_events(hipEvent_t *t0, hipEvent_t *t1) {
+    Timing &tm = timing();
+    if (!tm.ok) return false;
+    *t0 = tm.t0;
+    *t1 = tm.t1;
+    return true;
+}
+
+// Destroys the calling thread's timing events (recreated on the next timed
+// solve).
+void release_solve_host() {
+    Timing &tm = tl_timing;
+    if (tm.t0) (void)hipEventDestroy(tm.t0);
+    if (tm.t1) (void)hipEventDestroy(tm.t1);
+    tm = Timing{};
+}
 
 // At most one workgroup per CU: with two 1024-thread workgroups per CU the
 // occupancy query allowed the launch, yet the start-up barrier of one
@@ -389,36 +409,175 @@ extern "C" int sc_mvop(const sc_particles *p, const sc_contacts *c, const double
     return SC_OK;
 }
 
-extern "C" int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
-                            const sc_solve_opts *opts, double *gamma, double *g, double *f_c,
-                            double *u_c, sc_stats *st, void *ws, size_t ws_bytes,
-                            void *stream_) {
+namespace {
+
+// Checked arguments, carved workspace and launch choice of one solve.
+struct Prepared {
     Plan pl;
-    int rc = check_common(p, c, pl);
+    bool use_mat = false;
+    MatBufs mb{};
+    double *zbuf = nullptr, *gam1 = nullptr, *g1 = nullptr, *U = nullptr, *part = nullptr;
+    GridSync *sync = nullptr;
+    Ctrl *ctrl = nullptr;
+    int lpp = 4, spw = 1, block = 1024, G = 1, cache_used = 0;
+    BbKernel kern = nullptr;
+    SolveArgs A{};
+};
+
+int prepare(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *opts,
+            double *gamma, double *g, void *ws, size_t ws_bytes, Prepared &P) {
+    int rc = check_common(p, c, P.pl);
     if (rc) return rc;
-    if (!opts || !st) return SC_ERR_INVALID;
+    if (!opts) return SC_ERR_INVALID;
     if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->bb < 1 || opts->bb > 3 ||
         !lanes_ok(opts->lanes_per_particle) || !spw_ok(opts->slices_per_wave) ||
         opts->lds_entries_per_wave < -1 || opts->grid < 0 || opts->spin_limit < 0 ||
         !block_ok(opts->block) || opts->op < 0 ||
         opts->op > SC_OP_MATRIX || (opts->op == SC_OP_MATRIX && !c->mat_ready))
         return SC_ERR_INVALID;
-    hipStream_t s = static_cast<hipStream_t>(stream_);
     const int n = p->n, nc = c->count;
-    *st = sc_stats{};
-    const bool use_mat = opts->op == SC_OP_MATRIX || (opts->op == SC_OP_AUTO && c->mat_ready);
-    MatBufs mb{};
-    if (use_mat && !carve_matrix(c->mat, c->mat_bytes, nc, c->nnz, mb)) return SC_ERR_INVALID;
+    P.use_mat = opts->op == SC_OP_MATRIX || (opts->op == SC_OP_AUTO && c->mat_ready);
+    if (P.use_mat && !carve_matrix(c->mat, c->mat_bytes, nc, c->nnz, P.mb)) return SC_ERR_INVALID;
     if (nc > 0 && (!gamma || !g)) return SC_ERR_INVALID;
     if (!ws_ok(ws, ws_bytes, solve_ws_bytes(n, c->capacity))) return SC_ERR_WORKSPACE;
     Carver cv{static_cast<char *>(ws), ws_bytes};
-    double *zbuf = cv.take<double>(4 * static_cast<size_t>(c->capacity));
-    double *gam1 = zbuf, *g1 = zbuf + c->capacity;
-    double *U = cv.take<double>(8 * static_cast<size_t>(n));
-    double *part = cv.take<double>(2 * kPartHalf);
-    GridSync *sync = cv.take<GridSync>(1);
-    Ctrl *ctrl = cv.take<Ctrl>(1);
+    P.zbuf = cv.take<double>(4 * static_cast<size_t>(c->capacity));
+    P.gam1 = P.zbuf;
+    P.g1 = P.zbuf + c->capacity;
+    P.U = cv.take<double>(8 * static_cast<size_t>(n));
+    P.part = cv.take<double>(2 * kPartHalf);
+    P.sync = cv.take<GridSync>(1);
+    P.ctrl = cv.take<Ctrl>(1);
     if (!cv.ok) return SC_ERR_WORKSPACE;
+    P.lpp = opts->lanes_per_particle ? opts->lanes_per_particle : 4;
+    P.spw = opts->slices_per_wave ? opts->slices_per_wave : 1;
+    P.block = opts->block ? opts->block : 1024;
+    P.kern = bb_kernel(P.lpp, P.block);
+    SolveArgs &A = P.A;
+    A.C = chain_view(p, c, P.pl, P.U);
+    A.q = c->q;
+    A.gam[0] = gamma;
+    A.gam[1] = P.gam1;
+    A.gg[0] = g;
+    A.gg[1] = P.g1;
+    A.part = P.part;
+    A.sync = P.sync;
+    A.ctrl = P.ctrl;
+    A.tol = opts->tol;
+    A.max_iter = opts->max_iter;
+    A.bb = opts->bb;
+    return SC_OK;
+}
+
+// The persistent solve kernel (assembled M or the chain) on `s`.
+hipError_t launch_solver(Prepared &P, const sc_contacts *c, const sc_solve_opts *opts,
+                         double *gamma, double *g, hipStream_t s) {
+    if (P.use_mat)
+        return launch_bbpgd_mat(mat_view(c->count, P.mb), c->q, gamma, g, P.zbuf, P.part,
+                                P.sync, P.ctrl, opts->tol, opts->max_iter, opts->bb, P.spw,
+                                opts->lds_entries_per_wave, P.block, opts->grid, s, &P.G,
+                                &P.cache_used);
+    P.G = persistent_grid(reinterpret_cast<const void *>(P.kern), P.block, opts->grid);
+    if (P.G < 1) return hipErrorInvalidConfiguration;
+    void *args[] = {&P.A};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(P.kern), dim3(P.G),
+                                      dim3(P.block), args, 0, s);
+}
+
+void fill_launch_stats(const Prepared &P, sc_stats *st) {
+    st->grid = P.G;
+    st->block = P.block;
+    st->lanes_per_particle = P.use_mat ? 0 : P.lpp;
+    st->slices_per_wave = P.use_mat ? P.spw : 0;
+    st->lds_entries_per_wave = P.cache_used;
+    st->op = P.use_mat ? SC_OP_MATRIX : SC_OP_CHAIN;
+}
+
+// ---- device-side bookkeeping of the non-synchronising solve ----
+
+// Clears the barrier block and the control block (the spin limit set), and
+// gamma_0 for a cold start: one launch in place of the memsets, so that the
+// sequence can be captured into a graph.
+__global__ void k_async_reset(double *gamma, int nc, int zero_gamma, unsigned *sync_words,
+                              int n_sync_words, unsigned spin_limit, unsigned *ctrl_words,
+                              int n_ctrl_words) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    const int lim = static_cast<int>(offsetof(GridSync, limit) / sizeof(unsigned));
+    for (int w = t; w < n_sync_words; w += stride) sync_words[w] = w == lim ? spin_limit : 0u;
+    for (int w = t; w < n_ctrl_words; w += stride) ctrl_words[w] = 0u;
+    if (zero_gamma)
+        for (int l = t; l < nc; l += stride) gamma[l] = 0.0;
+}
+
+// The chain solve leaves its last iterate in buffer (iters & 1).
+__global__ void k_async_last_iterate(const Ctrl *ctrl, int nc, const double *gam1,
+                                     const double *g1, double *gamma, double *g) {
+    if (!(ctrl->iters & 1)) return;
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < nc; l += gridDim.x * blockDim.x) {
+        gamma[l] = gam1[l];
+        g[l] = g1[l];
+    }
+}
+
+__global__ void k_fill_zero(double *a, long long count) {
+    for (long long k = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; k < count;
+         k += static_cast<long long>(gridDim.x) * blockDim.x)
+        a[k] = 0.0;
+}
+
+// sc_stats on the device from the control block (launch fields from the host).
+__global__ void k_async_stats(const Ctrl *ctrl, const int *n_active, sc_stats launch,
+                              sc_stats *st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    sc_stats o = launch;
+    if (ctrl) {
+        o.status = ctrl->status;
+        o.iters = ctrl->iters;
+        o.mvops = ctrl->mvops;
+        o.residual = ctrl->res;
+        o.alpha = ctrl->alpha;
+        o.n_degenerate = ctrl->ndegen;
+        o.n_active = *n_active;
+    }
+    *st = o;
+}
+
+// Inside a stream capture the persistent kernel's node must carry the
+// cooperative attribute (a captured launch does not keep it): the node just
+// captured is the stream's only current dependency.
+int mark_cooperative_if_captured(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    SC_HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusActive) return SC_OK;
+    const hipGraphNode_t *deps = nullptr;
+    size_t nd = 0;
+    SC_HIP_TRY(hipStreamGetCaptureInfo_v2(s, &cs, nullptr, nullptr, &deps, &nd));
+    if (nd != 1 || !deps) return SC_ERR_HIP;
+    hipGraphNodeType ty;
+    SC_HIP_TRY(hipGraphNodeGetType(deps[0], &ty));
+    if (ty != hipGraphNodeTypeKernel) return SC_ERR_HIP;
+    hipKernelNodeAttrValue v{}, chk{};
+    v.cooperative = 1;
+    SC_HIP_TRY(hipGraphKernelNodeSetAttribute(deps[0], hipKernelNodeAttributeCooperative, &v));
+    SC_HIP_TRY(hipGraphKernelNodeGetAttribute(deps[0], hipKernelNodeAttributeCooperative, &chk));
+    return chk.cooperative == 1 ? SC_OK : SC_ERR_HIP;
+}
+
+}  // namespace
+
+// The body of sc_solve_lcp on a given workspace. `timed`: measure the
+// persistent kernel with HIP events (created once per host thread); without
+// it st->kernel_ms is 0 and no event is created.
+int sc::solve_lcp_on(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *opts,
+                     double *gamma, double *g, double *f_c, double *u_c, sc_stats *st, void *ws,
+                     size_t ws_bytes, void *stream_, bool timed) {
+    if (!st) return SC_ERR_INVALID;
+    Prepared P;
+    int rc = prepare(p, c, opts, gamma, g, ws, ws_bytes, P);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream_);
+    const int n = p->n, nc = c->count;
+    *st = sc_stats{};
 
     if (nc == 0) {
         // no constraints: the zero force solves the (empty) LCP after one product
@@ -429,66 +588,37 @@ extern "C" int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
         st->mvops = 1;
         return SC_OK;
     }
-    Timing &tm = timing();
-    if (!tm.ok) return SC_ERR_HIP;
-
-    const int lpp = opts->lanes_per_particle ? opts->lanes_per_particle : 4;
-    const int spw = opts->slices_per_wave ? opts->slices_per_wave : 1;
-    int cache_used = 0;
-    const int block = opts->block ? opts->block : 1024;
-    BbKernel kern = bb_kernel(lpp, block);
-    int G = use_mat ? 1 : persistent_grid(reinterpret_cast<const void *>(kern), block, opts->grid);
-    if (G < 1) return SC_ERR_HIP;
-
-    SolveArgs A;
-    A.C = chain_view(p, c, pl, U);
-    A.q = c->q;
-    A.gam[0] = gamma;
-    A.gam[1] = gam1;
-    A.gg[0] = g;
-    A.gg[1] = g1;
-    A.part = part;
-    A.sync = sync;
-    A.ctrl = ctrl;
-    A.tol = opts->tol;
-    A.max_iter = opts->max_iter;
-    A.bb = opts->bb;
-
-    if (!opts->warm_start) SC_HIP_TRY(hipMemsetAsync(gamma, 0, sizeof(double) * nc, s));
-    SC_HIP_TRY(hipMemsetAsync(sync, 0, sizeof(GridSync), s));
-    if (opts->spin_limit > 0)
-        SC_HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(&sync->limit[0]),
-                                     opts->spin_limit, 1, s));
-    SC_HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), s));
-    void *args[] = {&A};
-    SC_HIP_TRY(hipEventRecord(tm.t0, s));
-    if (use_mat) {
-        SC_HIP_TRY(launch_bbpgd_mat(mat_view(nc, mb), c->q, gamma, g, zbuf, part, sync, ctrl,
-                                    opts->tol, opts->max_iter, opts->bb, spw,
-                                    opts->lds_entries_per_wave, block, opts->grid, s, &G,
-                                    &cache_used));
-    } else {
-        SC_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G),
-                                              dim3(block), args, 0, s));
+    Timing *tm = nullptr;
+    if (timed) {
+        tm = &timing();
+        if (!tm->ok) return SC_ERR_HIP;
     }
-    SC_HIP_TRY(hipEventRecord(tm.t1, s));
+    if (!opts->warm_start) SC_HIP_TRY(hipMemsetAsync(gamma, 0, sizeof(double) * nc, s));
+    SC_HIP_TRY(hipMemsetAsync(P.sync, 0, sizeof(GridSync), s));
+    if (opts->spin_limit > 0)
+        SC_HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(&P.sync->limit[0]),
+                                     opts->spin_limit, 1, s));
+    SC_HIP_TRY(hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl), s));
+    if (tm) SC_HIP_TRY(hipEventRecord(tm->t0, s));
+    SC_HIP_TRY(launch_solver(P, c, opts, gamma, g, s));
+    if (tm) SC_HIP_TRY(hipEventRecord(tm->t1, s));
     Ctrl hc;
-    SC_HIP_TRY(hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    SC_HIP_TRY(hipMemcpyAsync(&hc, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     SC_HIP_TRY(hipStreamSynchronize(s));
     float kernel_ms = 0.0f;
-    SC_HIP_TRY(hipEventElapsedTime(&kernel_ms, tm.t0, tm.t1));
+    if (tm) SC_HIP_TRY(hipEventElapsedTime(&kernel_ms, tm->t0, tm->t1));
     // the chain solve leaves the last iterate in buffer (iters & 1); the
     // matrix solve writes gamma and g itself
-    if (!use_mat && (hc.iters & 1)) {
-        SC_HIP_TRY(hipMemcpyAsync(gamma, gam1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
-        SC_HIP_TRY(hipMemcpyAsync(g, g1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+    if (!P.use_mat && (hc.iters & 1)) {
+        SC_HIP_TRY(hipMemcpyAsync(gamma, P.gam1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+        SC_HIP_TRY(hipMemcpyAsync(g, P.g1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
     }
-    int *nact = reinterpret_cast<int *>(part);
+    int *nact = reinterpret_cast<int *>(P.part);
     SC_HIP_TRY(hipMemsetAsync(nact, 0, sizeof(int), s));
     int b = grid_for(nc);
     if (b > kMaxReduceBlocks) b = kMaxReduceBlocks;
     k_count_active<<<b, kBlock, 0, s>>>(nc, gamma, nact);
-    if (f_c || u_c) launch_mob_d(A.C, gamma, pl.order, f_c, u_c, s);
+    if (f_c || u_c) launch_mob_d(P.A.C, gamma, P.pl.order, f_c, u_c, s);
     int hact = 0;
     SC_HIP_TRY(hipMemcpyAsync(&hact, nact, sizeof(int), hipMemcpyDeviceToHost, s));
     SC_HIP_TRY(hipStreamSynchronize(s));
@@ -501,11 +631,56 @@ extern "C" int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
     st->alpha = hc.alpha;
     st->n_degenerate = hc.ndegen;
     st->kernel_ms = kernel_ms;
-    st->grid = G;
-    st->block = block;
-    st->lanes_per_particle = use_mat ? 0 : lpp;
-    st->slices_per_wave = use_mat ? spw : 0;
-    st->lds_entries_per_wave = cache_used;
-    st->op = use_mat ? SC_OP_MATRIX : SC_OP_CHAIN;
+    fill_launch_stats(P, st);
     return hc.status;
+}
+
+extern "C" int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
+                            const sc_solve_opts *opts, double *gamma, double *g, double *f_c,
+                            double *u_c, sc_stats *st, void *ws, size_t ws_bytes,
+                            void *stream) {
+    return solve_lcp_on(p, c, opts, gamma, g, f_c, u_c, st, ws, ws_bytes, stream, true);
+}
+
+extern "C" int sc_solve_lcp_async(const sc_particles *p, const sc_contacts *c,
+                                  const sc_solve_opts *opts, double *gamma, double *g,
+                                  double *f_c, double *u_c, sc_stats *st_dev, void *ws,
+                                  size_t ws_bytes, void *stream_) {
+    if (!st_dev) return SC_ERR_INVALID;
+    Prepared P;
+    int rc = prepare(p, c, opts, gamma, g, ws, ws_bytes, P);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream_);
+    const int n = p->n, nc = c->count;
+    sc_stats launch{};
+    if (nc == 0) {
+        const long long m = 6LL * n;
+        if (f_c && m) k_fill_zero<<<grid_for(m), kBlock, 0, s>>>(f_c, m);
+        if (u_c && m) k_fill_zero<<<grid_for(m), kBlock, 0, s>>>(u_c, m);
+        launch.status = SC_OK;
+        launch.mvops = 1;
+        k_async_stats<<<1, 64, 0, s>>>(nullptr, nullptr, launch, st_dev);
+        SC_HIP_TRY(hipGetLastError());
+        return SC_OK;
+    }
+    const int nsync = static_cast<int>(sizeof(GridSync) / sizeof(unsigned));
+    const int nctrl = static_cast<int>(sizeof(Ctrl) / sizeof(unsigned));
+    int rb = grid_for(nc);
+    if (rb > kMaxReduceBlocks) rb = kMaxReduceBlocks;
+    k_async_reset<<<rb, kBlock, 0, s>>>(gamma, nc, opts->warm_start ? 0 : 1,
+                                        reinterpret_cast<unsigned *>(P.sync), nsync,
+                                        static_cast<unsigned>(opts->spin_limit),
+                                        reinterpret_cast<unsigned *>(P.ctrl), nctrl);
+    SC_HIP_TRY(hipGetLastError());
+    SC_HIP_TRY(launch_solver(P, c, opts, gamma, g, s));
+    rc = mark_cooperative_if_captured(s);
+    if (rc != SC_OK) return rc;
+    if (!P.use_mat)
+        k_async_last_iterate<<<rb, kBlock, 0, s>>>(P.ctrl, nc, P.gam1, P.g1, gamma, g);
+    k_count_active<<<rb, kBlock, 0, s>>>(nc, gamma, &P.ctrl->n_active);
+    if (f_c || u_c) launch_mob_d(P.A.C, gamma, P.pl.order, f_c, u_c, s);
+    fill_launch_stats(P, &launch);
+    k_async_stats<<<1, 64, 0, s>>>(P.ctrl, &P.ctrl->n_active, launch, st_dev);
+    SC_HIP_TRY(hipGetLastError());
+    return SC_OK;
 }

@@ -14,7 +14,8 @@ import torch
 
 from . import _abi as A
 from .api import (RPY, Box, Contacts, Particles, Workspace, _check, _dev, _ptr, _stream,
-                  apply_mobility, build_contacts, solve_lcp, solve_lcp_mob, solve_lcp_rpy)
+                  apply_mobility, build_contacts, require_solution, solve_lcp, solve_lcp_mob,
+                  solve_lcp_rpy)
 
 
 def quat_from_axis(axis: torch.Tensor) -> torch.Tensor:
@@ -64,14 +65,18 @@ class TimeStepper:
     which the steps update in place. ``persistent``: with an RPY mobility,
     solve in one persistent launch (solve_lcp_rpy) instead of a launch per
     phase; None chooses by size: persistent up to PERSISTENT_RPY_MAX_N
-    particles (measured faster there, slower beyond)."""
+    particles (measured faster there, slower beyond). ``spin_limit`` is
+    passed to the persistent solves (> 0 forces their barrier time-out, for
+    tests). A step whose solve ends with an error status (a barrier time-out,
+    a non-finite iterate) raises ScError before anything moves."""
 
     PERSISTENT_RPY_MAX_N = 2048
 
     def __init__(self, particles: Particles, box: Box, delta: float, dt: float,
                  f_ext: torch.Tensor, tol: float = 1e-6, warm_start: bool = True,
                  max_iter: int = 100000, hydro_radius: Optional[torch.Tensor] = None,
-                 mu: float = 1.0, mobility=None, persistent: Optional[bool] = None):
+                 mu: float = 1.0, mobility=None, persistent: Optional[bool] = None,
+                 spin_limit: int = 0):
         self.P = particles
         self.box = box
         self.delta = float(delta)
@@ -92,6 +97,7 @@ class TimeStepper:
         if persistent is None:
             persistent = particles.n <= self.PERSISTENT_RPY_MAX_N
         self.persistent = bool(persistent) and isinstance(self.rpy, RPY)
+        self.spin_limit = int(spin_limit)
 
     def step(self) -> StepInfo:
         P = self.P
@@ -103,15 +109,20 @@ class TimeStepper:
             gamma0 = map_gamma(P.n, self.prev, self.prev_gamma, con)
         if self.rpy is None:
             gamma, g, st, f_c, u_c = solve_lcp(P, con, tol=self.tol, max_iter=self.max_iter,
-                                               gamma0=gamma0, want_fc=True, workspace=self.ws)
+                                               gamma0=gamma0, want_fc=True, workspace=self.ws,
+                                               spin_limit=self.spin_limit)
+            solver = "sc_solve_lcp"
         elif self.persistent:
             gamma, g, st, f_c, u_c = solve_lcp_rpy(P, con, self.rpy, tol=self.tol,
                                                    max_iter=self.max_iter, gamma0=gamma0,
-                                                   want_fc=True)
+                                                   want_fc=True, spin_limit=self.spin_limit)
+            solver = "sc_solve_lcp_rpy"
         else:
             gamma, g, st, f_c, u_c = solve_lcp_mob(P, con, self.rpy, tol=self.tol,
                                                    max_iter=self.max_iter, gamma0=gamma0,
                                                    want_fc=True)
+            solver = "sc_solve_lcp_mob"
+        require_solution(solver, st)
         advance(P, self.quat, u_nc, u_c, self.dt)
         self.prev, self.prev_gamma = con, gamma
         return StepInfo(con, gamma, st, u_c)

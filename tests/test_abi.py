@@ -185,3 +185,31 @@ def test_mobility_entry_points_reject_bad_arguments_without_device_work():
     c.capacity, c.count = 0, 0
     assert L.sc_solve_rpy_work_bytes(-1, 10) == 0 and L.sc_solve_rpy_work_bytes(10, -1) == 0
     assert L.sc_solve_rpy_work_bytes(1000, 3000) >= 2 * 8 * 3000 + 6 * 8 * 1000
+
+
+def test_stream_ordered_entry_points_reject_bad_calls_without_device_work():
+    """sc_canonical_order and sc_solve_lcp_async check their arguments on
+    the host before anything is enqueued."""
+    from paper_1909_06623_amd import _abi as A
+    L = A.lib()
+    assert L.sc_canonical_order(3, None, None, None, 0, None) == A.SC_ERR_INVALID
+    c = A.sc_contacts()
+    c.capacity, c.count = 5, 10
+    assert L.sc_canonical_order(3, ctypes.byref(c), None, None, 0, None) == A.SC_ERR_INVALID
+    c.count = 2  # no plan buffer
+    assert L.sc_canonical_order(3, ctypes.byref(c), None, None, 0, None) == A.SC_ERR_INVALID
+    assert L.sc_canonical_order(-1, ctypes.byref(c), None, None, 0, None) == A.SC_ERR_INVALID
+    p0 = A.sc_particles(0, 0, 0, 0, 0, 0, 0)
+    c.count = 0
+    opts = A.sc_solve_opts(1e-6, 100, 1, 0, 0)
+    # no device stats record
+    assert L.sc_solve_lcp_async(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(opts), None,
+                                None, None, None, None, None, 0, None) == A.SC_ERR_INVALID
+    bad = A.sc_solve_opts(0.0, 100, 1, 0, 0)
+    assert L.sc_solve_lcp_async(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(bad), None,
+                                None, None, None, ctypes.c_void_p(256), None, 0,
+                                None) == A.SC_ERR_INVALID
+    bad = A.sc_solve_opts(1e-6, 100, 4, 0, 0)
+    assert L.sc_solve_lcp_async(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(bad), None,
+                                None, None, None, ctypes.c_void_p(256), None, 0,
+                                None) == A.SC_ERR_INVALID

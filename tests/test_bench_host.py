@@ -24,18 +24,22 @@ def test_bytes_models():
     assert bench.operator_bytes(3, 10) == 12 * 10 + 44 * 3
 
 
-def test_traffic_record_guard(tmp_path, monkeypatch):
+def test_traffic_record_guard(tmp_path):
     rec = {"iters": 1304, "bytes_per_launch": 123, "kernel_sha256": bench.kernel_digest()}
     f = tmp_path / "t.json"
     f.write_text(json.dumps(rec))
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.measured_traffic(1304) == 123
-    assert bench.measured_traffic(1305) is None          # another launch
+    assert bench.measured_traffic(1304, str(f)) == 123
+    assert bench.measured_traffic(1305, str(f)) is None   # another launch
     rec["kernel_sha256"] = "0" * 64                      # other kernel sources
     f.write_text(json.dumps(rec))
-    assert bench.measured_traffic(1304) is None
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
-    assert bench.measured_traffic(1304) is None
+    assert bench.measured_traffic(1304, str(f)) is None
+    assert bench.measured_traffic(1304, str(tmp_path / "missing.json")) is None
+
+
+def test_host_cpu_report():
+    model, nproc, usable = bench.host_cpu()
+    assert isinstance(model, str) and model
+    assert 1 <= usable <= nproc
 
 
 def test_more_than_one_gpu_is_refused():

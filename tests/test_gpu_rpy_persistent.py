@@ -80,6 +80,7 @@ def test_persistent_rpy_solve_edge_cases():
     P, R, con = _setup(s)
     gam, g, st, _, _ = sc.solve_lcp_rpy(P, con, R, tol=1e-10)
     assert st["status"] == 0
+    assert st["op"] == A.SC_OP_RPY and st["lanes_per_particle"] == 4  # threads per source's F
     # warm start at the solution: one product, no step
     gam2, g2, st2, _, _ = sc.solve_lcp_rpy(P, con, R, tol=1e-6, gamma0=gam)
     assert (st2["status"], st2["iters"], st2["mvops"]) == (0, 0, 1)
@@ -147,7 +148,7 @@ def test_persistent_rpy_solve_with_walls_matches_oracle():
 
 @pytest.mark.parametrize("n", [4000, 20000])
 def test_persistent_rpy_solve_with_multi_tile_units_properties(n):
-    """Sizes whose pair units span several 512-source LDS tiles (the tile
+    """Sizes whose pair units span several 256-source LDS tiles (the tile
     prefetch path), too large for the oracle's dense M: KKT, the per-phase
     solve's point, F_c = D gamma against the oracle's D on the oracle's
     contact list, and sampled rows of U_c against the oracle's pair formula."""
