@@ -264,6 +264,27 @@ int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
                  double *f_c, double *u_c, sc_stats *st, void *ws,
                  size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * sc_solve_lcp with the same arguments, kernels and results, except that its
+ * workspace is a library-owned device array of SC_NOALLOC_SCRATCH_BYTES bytes
+ * instead of a caller buffer, and st->kernel_ms is 0 (no HIP events are
+ * created). The array is static device memory of the library: each GPU the
+ * library runs on holds one copy until the process ends. The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); its device
+ * address is looked up on the first call on each device. Every call on one
+ * GPU shares that GPU's array, which keeps the last call's contents (what
+ * must start at zero is cleared by the call): calls that overlap on one GPU,
+ * on any streams, race and give undefined results. Returns
+ * SC_ERR_WORKSPACE, before any device work, when the solve needs more than
+ * the array holds (about 32 capacity + 64 n + 72 KiB bytes, so for example
+ * n = 100,000 particles with capacity up to about 1.8 million contacts);
+ * otherwise as sc_solve_lcp. Synchronises `stream`. */
+#define SC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int sc_solve_lcp_noalloc(const sc_particles *p, const sc_contacts *c,
+                         const sc_solve_opts *opts, double *gamma, double *g, double *f_c,
+                         double *u_c, sc_stats *st, void *stream);
+
 /* sc_solve_lcp (Algorithm 1, section 3.3.1) without any host
  * synchronisation, for stream-ordered pipelines and HIP graph capture: the
  * same checks, kernels and results, but the call only enqueues work on

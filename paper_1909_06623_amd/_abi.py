@@ -19,6 +19,8 @@ SC_ERR_HIP = -5
 SC_ERR_WORKSPACE = -6
 SC_ERR_TIMEOUT = -7
 
+SC_NOALLOC_SCRATCH_BYTES = 64 << 20
+
 SC_OP_AUTO = 0
 SC_OP_CHAIN = 1
 SC_OP_MATRIX = 2
@@ -132,6 +134,9 @@ SIGNATURES = {
     "sc_solve_lcp": (ctypes.c_int, [P(sc_particles), P(sc_contacts), P(sc_solve_opts),
                                     c_dp, c_dp, c_dp, c_dp, P(sc_stats), c_dp,
                                     ctypes.c_size_t, c_dp]),
+    "sc_solve_lcp_noalloc": (ctypes.c_int, [P(sc_particles), P(sc_contacts),
+                                            P(sc_solve_opts), c_dp, c_dp, c_dp, c_dp,
+                                            P(sc_stats), c_dp]),
     "sc_solve_lcp_async": (ctypes.c_int, [P(sc_particles), P(sc_contacts),
                                           P(sc_solve_opts), c_dp, c_dp, c_dp, c_dp, c_dp,
                                           c_dp, ctypes.c_size_t, c_dp]),

@@ -324,6 +324,25 @@ def solve_lcp(particles: Particles, contacts: Contacts, tol: float = 1e-6,
     return gamma[:nc], g[:nc], st.as_dict(), f_c, u_c
 
 
+def solve_lcp_noalloc(particles: Particles, contacts: Contacts, gamma: torch.Tensor,
+                      g: torch.Tensor, tol: float = 1e-6, max_iter: int = 100000, bb: int = 1,
+                      warm_start: bool = False, f_c: Optional[torch.Tensor] = None,
+                      u_c: Optional[torch.Tensor] = None, op: int = 0):
+    """BBPGD as solve_lcp, through sc_solve_lcp_noalloc: the library's own
+    device scratch array stands in for the workspace and nothing is
+    allocated by the call. gamma and g (and f_c, u_c if given) are the
+    caller's output buffers (gamma holds gamma_0 when ``warm_start``).
+    Returns (return code, stats dict); the caller checks the code."""
+    opts = A.sc_solve_opts(float(tol), int(max_iter), int(bb), 1 if warm_start else 0,
+                           0, 0, 0, int(op), 0, 0, 0)
+    st = A.sc_stats()
+    pc, cc = particles.c(), contacts.c()
+    rc = A.lib().sc_solve_lcp_noalloc(ctypes.byref(pc), ctypes.byref(cc), ctypes.byref(opts),
+                                      _ptr(gamma), _ptr(g), _ptr(f_c), _ptr(u_c),
+                                      ctypes.byref(st), _stream())
+    return rc, st.as_dict()
+
+
 STATS_BYTES = ctypes.sizeof(A.sc_stats)
 
 

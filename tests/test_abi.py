@@ -213,3 +213,19 @@ def test_stream_ordered_entry_points_reject_bad_calls_without_device_work():
     assert L.sc_solve_lcp_async(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(bad), None,
                                 None, None, None, ctypes.c_void_p(256), None, 0,
                                 None) == A.SC_ERR_INVALID
+
+
+def test_noalloc_solve_rejects_oversized_systems_on_the_host():
+    """The allocation-free solve refuses, before any device work, a system
+    whose workspace exceeds its static scratch array."""
+    from paper_1909_06623_amd import _abi as A
+    L = A.lib()
+    p = A.sc_particles(100000, 0, 0, 0, 0, 0, 0)
+    c = A.sc_contacts()
+    c.capacity, c.count = 4_000_000, 0
+    opts = A.sc_solve_opts(1e-6, 100, 1, 0, 0)
+    st = A.sc_stats()
+    assert L.sc_solve_lcp_noalloc(ctypes.byref(p), ctypes.byref(c), ctypes.byref(opts), None,
+                                  None, None, None, ctypes.byref(st), None) == A.SC_ERR_WORKSPACE
+    assert L.sc_solve_lcp_noalloc(None, ctypes.byref(c), ctypes.byref(opts), None, None, None,
+                                  None, ctypes.byref(st), None) == A.SC_ERR_INVALID
