@@ -646,7 +646,7 @@ static void mvop_incidence(mvop_ctx *c)
  * particle, as orc_D_apply's scatter in contact order. */
 static void d_apply_gather(const mvop_ctx *c, const double *x, double *F)
 {
-#pragma omp parallel for num_threads(g_threads) schedule(static)
+#pragma omp parallel for if (g_threads > 1) num_threads(g_threads) schedule(static)
     for (int k = 0; k < c->n; ++k) {
         double f[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (long e = c->inc_ptr[k]; e < c->inc_ptr[k + 1]; ++e) {
@@ -677,11 +677,11 @@ static void mvop(mvop_ctx *c, const double *x, double *out)
         return;
     }
     d_apply_gather(c, x, c->F);
-#pragma omp parallel for num_threads(g_threads) schedule(static)
+#pragma omp parallel for if (g_threads > 1) num_threads(g_threads) schedule(static)
     for (int k = 0; k < c->n; ++k)
         orc_mobility(1, c->axis + 3 * k, c->mob + 4 * k, c->F + 6 * k, c->U + 6 * k);
     long T = g_threads;
-#pragma omp parallel for num_threads(g_threads) schedule(static)
+#pragma omp parallel for if (g_threads > 1) num_threads(g_threads) schedule(static)
     for (long t = 0; t < T; ++t) {
         long l0, l1;
         thread_range(c->nc, (int)t, (int)T, &l0, &l1);
@@ -746,7 +746,7 @@ static void contact_sums(int what, long nc, const double *a, const double *b,
 {
     double part[ORC_MAX_THREADS][3];
     int T = g_threads;
-#pragma omp parallel num_threads(T)
+#pragma omp parallel if (T > 1) num_threads(T)
     {
         int t = omp_get_thread_num(), nt = omp_get_num_threads();
 #pragma omp single
@@ -814,7 +814,7 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
     /* g0 = M gamma0 + q */
     mvop(&c, gamma, g);
     mvops++;
-#pragma omp parallel for num_threads(g_threads) schedule(static)
+#pragma omp parallel for if (g_threads > 1) num_threads(g_threads) schedule(static)
     for (long l = 0; l < nc; ++l)
         g[l] += q[l];
     res = residual(nc, gamma, g);
@@ -848,7 +848,7 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
         memcpy(gamma_prev, gamma, sz);
         memcpy(g_prev, g, sz);
         /* descent step, then projection onto gamma >= 0 */
-#pragma omp parallel for num_threads(g_threads) schedule(static)
+#pragma omp parallel for if (g_threads > 1) num_threads(g_threads) schedule(static)
         for (long l = 0; l < nc; ++l) {
             double v = gamma_prev[l] - alpha * g_prev[l];
             gamma[l] = v < 0.0 ? 0.0 : v;
@@ -856,7 +856,7 @@ int orc_bbpgd(int n, long nc, const int *ci, const int *cj, const double *nrm,
         /* new gradient g = M gamma + q */
         mvop(&c, gamma, g);
         mvops++;
-#pragma omp parallel for num_threads(g_threads) schedule(static)
+#pragma omp parallel for if (g_threads > 1) num_threads(g_threads) schedule(static)
         for (long l = 0; l < nc; ++l)
             g[l] += q[l];
         iters = j;

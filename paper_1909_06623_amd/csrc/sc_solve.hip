@@ -18,6 +18,7 @@
 #include "sc_chain.hpp"
 #include "sc_common.hpp"
 #include "sc_matrix.hpp"
+#include "sc_matrix_pass.hpp"
 #include "sc_plan.hpp"
 #include "sc_sync.hpp"
 
@@ -30,18 +31,16 @@ using Ctrl = SolveCtrl;
 struct SolveArgs {
     ChainView C;
     const double *q;
-    double *gam[2];
-    double *gg[2];
+    double *gamma;         // in: gamma_0 (if warm); out: the last iterate
+    double *g;             // out: M gamma + q
+    GG *z[2];              // (gamma_j, g_j) records, alternating per iteration
     double *part;          // [G][4]
     GridSync *sync;
     Ctrl *ctrl;
     double tol;
     int max_iter, bb;
+    int warm;
 };
-
-// Projection onto gamma >= 0 (negative components set to zero), written so that a
-// NaN propagates instead of being clamped away.
-__device__ __forceinline__ double project(double v) { return v < 0.0 ? 0.0 : v; }
 
 __device__ __forceinline__ double m_diag(const ChainView &C, int l) {
     // M_ll = D_l^T Mob D_l
@@ -55,6 +54,12 @@ __device__ __forceinline__ double m_diag(const ChainView &C, int l) {
     return dot(n, ui) + dot(ti, wi) + dot(n, uj) + dot(tj, wj);
 }
 
+// Matrix-free BBPGD. The iterate lives in (gamma, g) records, one 16-byte
+// record per contact, so that pass A forms every projected step
+// gamma_j = max(0, gamma_{j-1} - alpha g_{j-1}) from one gather and stores
+// nothing, and pass B, which evaluates the same expression for its own
+// contacts (the same bits), writes each contact's new record in one
+// coalesced store.
 template <int LPP, int BS>
 __global__ void __launch_bounds__(BS) k_bbpgd(SolveArgs A) {
     GridBarrier bar;
@@ -65,18 +70,23 @@ __global__ void __launch_bounds__(BS) k_bbpgd(SolveArgs A) {
     chunk(C.nc, l0, l1);
 
     double alpha = 0.0, res = 0.0;
-    int iters = 0, mvops = 0, status = SC_NOT_CONVERGED, ndegen = 0;
+    int iters = 0, mvops = 0, status = SC_NOT_CONVERGED, ndegen = 0, last = 0;
     bool ok = true;
+    const double *x0 = A.warm ? A.gamma : nullptr;
 
     // g0 = M gamma0 + q
-    pass_a<LPP, BS>(C, k0, k1, [&](int code, int) { return A.gam[0][code >> 1]; });
+    pass_a<LPP, BS>(C, k0, k1, [&](int code, int) {
+        return x0 ? ld_global(x0 + (code >> 1)) : 0.0;
+    });
     ok = bar.sync();
     {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        GG *z0 = A.z[0];
         for (int l = l0 + threadIdx.x; l < l1; l += BS) {
             const double gl = dt_u(C, l) + A.q[l];
-            A.gg[0][l] = gl;
-            const double gm = A.gam[0][l];
+            const double gm = x0 ? x0[l] : 0.0;
+            __builtin_nontemporal_store(gm, &gmem(z0)[l].gam);
+            __builtin_nontemporal_store(gl, &gmem(z0)[l].g);
             const double m = gm < gl ? gm : gl;
             acc[0] += m * m;
             acc[1] += gl * gl;
@@ -97,11 +107,12 @@ __global__ void __launch_bounds__(BS) k_bbpgd(SolveArgs A) {
         status = SC_OK;  // gamma0 already satisfies the tolerance
     } else {
         // initial step size alpha0 = g0^T g0 / g0^T M g0
-        pass_a<LPP, BS>(C, k0, k1, [&](int code, int) { return A.gg[0][code >> 1]; });
+        const GG *z0 = A.z[0];
+        pass_a<LPP, BS>(C, k0, k1, [&](int code, int) { return ld_gg(z0 + (code >> 1)).g; });
         ok = bar.sync();
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int l = l0 + threadIdx.x; l < l1; l += BS) {
-            acc[0] += A.gg[0][l] * dt_u(C, l);
+            acc[0] += z0[l].g * dt_u(C, l);
             acc[1] = fmax(acc[1], m_diag(C, l));
         }
         write_partial<4, BS, 1>(A.part, acc);
@@ -116,27 +127,25 @@ __global__ void __launch_bounds__(BS) k_bbpgd(SolveArgs A) {
         }
         if (!ok) status = SC_ERR_TIMEOUT;
         for (int j = 1; ok && j <= A.max_iter; ++j) {
-            const int cur = (j - 1) & 1, nxt = j & 1;
-            const double *gc = A.gam[cur], *gr = A.gg[cur];
-            double *gn = A.gam[nxt];
-            // pass A: projected step on the fly, owner stores it
+            const GG *zc = A.z[(j - 1) & 1];
+            GG *zn = A.z[j & 1];
+            // pass A: the projected step formed per incidence from one record
             pass_a<LPP, BS>(C, k0, k1, [&](int code, int) {
-                const int l = code >> 1;
-                const double w = project(gc[l] - alpha * gr[l]);
-                if (code & 1) gn[l] = w;
-                return w;
+                const GG zm = ld_gg(zc + (code >> 1));
+                return project(zm.gam - alpha * zm.g);
             });
             ok = bar.sync();
-            // pass B: new gradient, residual and BB sums
+            // pass B: new records, residual and BB sums
             double acc2[4] = {0.0, 0.0, 0.0, 0.0};
-            double *gnew = A.gg[nxt];
             for (int l = l0 + threadIdx.x; l < l1; l += BS) {
+                const GG zl = ld_gg(zc + l);
+                const double gm = project(zl.gam - alpha * zl.g);
                 const double gl = dt_u(C, l) + A.q[l];
-                gnew[l] = gl;
-                const double gm = gn[l];
+                __builtin_nontemporal_store(gm, &gmem(zn)[l].gam);
+                __builtin_nontemporal_store(gl, &gmem(zn)[l].g);
                 const double m = gm < gl ? gm : gl;
-                const double s = gm - gc[l];
-                const double y = gl - gr[l];
+                const double s = gm - zl.gam;
+                const double y = gl - zl.g;
                 acc2[0] += m * m;
                 acc2[1] += s * s;
                 acc2[2] += s * y;
@@ -146,6 +155,7 @@ __global__ void __launch_bounds__(BS) k_bbpgd(SolveArgs A) {
             ok = ok && bar.sync();
             grid_reduce<4, BS>(A.part, tot);
             iters = j;
+            last = j & 1;
             ++mvops;
             res = sqrt(tot[0]);
             if (!ok) {
@@ -168,6 +178,13 @@ __global__ void __launch_bounds__(BS) k_bbpgd(SolveArgs A) {
             else
                 ++ndegen;
         }
+    }
+    // every workgroup copies out its own contacts of the last iterate
+    const GG *zf = A.z[last];
+    for (int l = l0 + threadIdx.x; l < l1; l += BS) {
+        const GG zl = zf[l];
+        A.gamma[l] = zl.gam;
+        A.g[l] = zl.g;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         Ctrl &c = *A.ctrl;
@@ -416,7 +433,7 @@ struct Prepared {
     Plan pl;
     bool use_mat = false;
     MatBufs mb{};
-    double *zbuf = nullptr, *gam1 = nullptr, *g1 = nullptr, *U = nullptr, *part = nullptr;
+    double *zbuf = nullptr, *U = nullptr, *part = nullptr;
     GridSync *sync = nullptr;
     Ctrl *ctrl = nullptr;
     int lpp = 4, spw = 1, block = 1024, G = 1, cache_used = 0;
@@ -442,8 +459,6 @@ int prepare(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *op
     if (!ws_ok(ws, ws_bytes, solve_ws_bytes(n, c->capacity))) return SC_ERR_WORKSPACE;
     Carver cv{static_cast<char *>(ws), ws_bytes};
     P.zbuf = cv.take<double>(4 * static_cast<size_t>(c->capacity));
-    P.gam1 = P.zbuf;
-    P.g1 = P.zbuf + c->capacity;
     P.U = cv.take<double>(8 * static_cast<size_t>(n));
     P.part = cv.take<double>(2 * kPartHalf);
     P.sync = cv.take<GridSync>(1);
@@ -456,10 +471,11 @@ int prepare(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *op
     SolveArgs &A = P.A;
     A.C = chain_view(p, c, P.pl, P.U);
     A.q = c->q;
-    A.gam[0] = gamma;
-    A.gam[1] = P.gam1;
-    A.gg[0] = g;
-    A.gg[1] = P.g1;
+    A.gamma = gamma;
+    A.g = g;
+    A.z[0] = reinterpret_cast<GG *>(P.zbuf);
+    A.z[1] = reinterpret_cast<GG *>(P.zbuf) + c->capacity;
+    A.warm = opts->warm_start ? 1 : 0;
     A.part = P.part;
     A.sync = P.sync;
     A.ctrl = P.ctrl;
@@ -507,16 +523,6 @@ __global__ void k_async_reset(double *gamma, int nc, int zero_gamma, unsigned *s
     for (int w = t; w < n_ctrl_words; w += stride) ctrl_words[w] = 0u;
     if (zero_gamma)
         for (int l = t; l < nc; l += stride) gamma[l] = 0.0;
-}
-
-// The chain solve leaves its last iterate in buffer (iters & 1).
-__global__ void k_async_last_iterate(const Ctrl *ctrl, int nc, const double *gam1,
-                                     const double *g1, double *gamma, double *g) {
-    if (!(ctrl->iters & 1)) return;
-    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < nc; l += gridDim.x * blockDim.x) {
-        gamma[l] = gam1[l];
-        g[l] = g1[l];
-    }
 }
 
 __global__ void k_fill_zero(double *a, long long count) {
@@ -607,12 +613,6 @@ int sc::solve_lcp_on(const sc_particles *p, const sc_contacts *c, const sc_solve
     SC_HIP_TRY(hipStreamSynchronize(s));
     float kernel_ms = 0.0f;
     if (tm) SC_HIP_TRY(hipEventElapsedTime(&kernel_ms, tm->t0, tm->t1));
-    // the chain solve leaves the last iterate in buffer (iters & 1); the
-    // matrix solve writes gamma and g itself
-    if (!P.use_mat && (hc.iters & 1)) {
-        SC_HIP_TRY(hipMemcpyAsync(gamma, P.gam1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
-        SC_HIP_TRY(hipMemcpyAsync(g, P.g1, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
-    }
     int *nact = reinterpret_cast<int *>(P.part);
     SC_HIP_TRY(hipMemsetAsync(nact, 0, sizeof(int), s));
     int b = grid_for(nc);
@@ -675,8 +675,6 @@ extern "C" int sc_solve_lcp_async(const sc_particles *p, const sc_contacts *c,
     SC_HIP_TRY(launch_solver(P, c, opts, gamma, g, s));
     rc = mark_cooperative_if_captured(s);
     if (rc != SC_OK) return rc;
-    if (!P.use_mat)
-        k_async_last_iterate<<<rb, kBlock, 0, s>>>(P.ctrl, nc, P.gam1, P.g1, gamma, g);
     k_count_active<<<rb, kBlock, 0, s>>>(nc, gamma, &P.ctrl->n_active);
     if (f_c || u_c) launch_mob_d(P.A.C, gamma, P.pl.order, f_c, u_c, s);
     fill_launch_stats(P, &launch);
