@@ -16,7 +16,7 @@
  *     Structs themselves are passed by host pointer.
  *   - The caller owns every buffer. No entry point allocates device memory:
  *     scratch comes from a caller-provided workspace of at least
- *     sc_workspace_bytes(n, capacity) bytes, 256-byte aligned.
+ *     sc_workspace_bytes(n, capacity, what) bytes, 256-byte aligned.
  *   - `stream` is a hipStream_t (NULL = the null stream). Work is enqueued on
  *     it in order. Entry points that must report a count or a status to the
  *     host (build_contacts, solve_lcp, solve_lcp_adjoint) synchronise that
@@ -186,9 +186,16 @@ typedef struct sc_adjoint_opts {
 
 /* ---------------------------------------------------------------- calls */
 
-/* Bytes of workspace any entry point needs for n particles and `capacity`
- * contact rows. Pure host arithmetic. */
-size_t sc_workspace_bytes(int32_t n, int32_t capacity);
+/* What a workspace is for (sc_workspace_bytes' `what`). */
+#define SC_WS_ALL      0    /* any entry point below */
+#define SC_WS_BUILD    1    /* sc_build_contacts, sc_canonical_order */
+#define SC_WS_SOLVE    2    /* sc_solve_lcp, sc_solve_lcp_async, sc_mvop */
+#define SC_WS_ADJOINT  3    /* sc_solve_lcp_adjoint */
+
+/* Bytes of workspace the entry points named by `what` need for n particles
+ * and `capacity` contact rows (SC_WS_ALL: the largest of them). Pure host
+ * arithmetic; 0 for negative sizes or an unknown `what`. */
+size_t sc_workspace_bytes(int32_t n, int32_t capacity, int32_t what);
 
 /* Bytes of the plan buffer of sc_contacts for n particles and `capacity`
  * contact rows. Pure host arithmetic. */
@@ -225,7 +232,7 @@ int sc_build_contacts(const sc_particles *p, const sc_box *box, double delta,
  * so that ci[perm[t]], cj[perm[t]] enumerate the pairs as a plain loop over
  * i < j would. n: the particles c was built for (sc_build_contacts' plan is
  * read). perm: device int32 [c->count], OUT. ws: device workspace of at
- * least sc_workspace_bytes(n, c->capacity) bytes, 256-byte aligned.
+ * least sc_workspace_bytes(n, c->capacity, SC_WS_BUILD) bytes, 256-byte aligned.
  * Deterministic (no sort, no atomics). Enqueues only; returns SC_OK,
  * SC_ERR_INVALID, SC_ERR_WORKSPACE or SC_ERR_HIP. */
 int sc_canonical_order(int32_t n, const sc_contacts *c, int32_t *perm, void *ws,
@@ -277,9 +284,10 @@ int sc_solve_lcp(const sc_particles *p, const sc_contacts *c,
  * must start at zero is cleared by the call): calls that overlap on one GPU,
  * on any streams, race and give undefined results. Returns
  * SC_ERR_WORKSPACE, before any device work, when the solve needs more than
- * the array holds (about 32 capacity + 64 n + 72 KiB bytes, so for example
- * n = 100,000 particles with capacity up to about 1.8 million contacts);
- * otherwise as sc_solve_lcp. Synchronises `stream`. */
+ * the array holds, i.e. when sc_workspace_bytes(n, capacity, SC_WS_SOLVE)
+ * (about 32 capacity + 64 n + 72 KiB) exceeds SC_NOALLOC_SCRATCH_BYTES, so
+ * for example n = 100,000 particles with capacity up to about 1.8 million
+ * contacts; otherwise as sc_solve_lcp. Synchronises `stream`. */
 #define SC_NOALLOC_SCRATCH_BYTES (64u << 20)
 int sc_solve_lcp_noalloc(const sc_particles *p, const sc_contacts *c,
                          const sc_solve_opts *opts, double *gamma, double *g, double *f_c,

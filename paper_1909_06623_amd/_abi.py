@@ -21,6 +21,11 @@ SC_ERR_TIMEOUT = -7
 
 SC_NOALLOC_SCRATCH_BYTES = 64 << 20
 
+SC_WS_ALL = 0
+SC_WS_BUILD = 1
+SC_WS_SOLVE = 2
+SC_WS_ADJOINT = 3
+
 SC_OP_AUTO = 0
 SC_OP_CHAIN = 1
 SC_OP_MATRIX = 2
@@ -119,7 +124,7 @@ MOBILITY_GRAD_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int3
 
 P = ctypes.POINTER
 SIGNATURES = {
-    "sc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "sc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "sc_plan_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "sc_matrix_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64]),
     "sc_assemble_matrix": (ctypes.c_int, [P(sc_particles), P(sc_contacts), c_dp]),

@@ -109,7 +109,7 @@ class Workspace:
         self.size = 0
 
     def get(self, n, capacity):
-        need = int(A.lib().sc_workspace_bytes(int(n), int(capacity)))
+        need = int(A.lib().sc_workspace_bytes(int(n), int(capacity), A.SC_WS_ALL))
         if self.buf is None or self.size < need:
             self.buf = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
             addr = self.buf.data_ptr()

@@ -2,13 +2,21 @@
 // release of per-thread host resources, version.
 #include "sc_common.hpp"
 
-extern "C" size_t sc_workspace_bytes(int32_t n, int32_t capacity) {
+extern "C" size_t sc_workspace_bytes(int32_t n, int32_t capacity, int32_t what) {
     if (n < 0 || capacity < 0) return 0;
-    size_t a = sc::contacts_ws_bytes(n, capacity);
-    size_t b = sc::solve_ws_bytes(n, capacity);
-    size_t c = sc::adjoint_ws_bytes(n, capacity);
-    size_t m = a > b ? a : b;
-    return m > c ? m : c;
+    const size_t a = sc::contacts_ws_bytes(n, capacity);
+    const size_t b = sc::solve_ws_bytes(n, capacity);
+    const size_t c = sc::adjoint_ws_bytes(n, capacity);
+    switch (what) {
+    case SC_WS_ALL: {
+        const size_t m = a > b ? a : b;
+        return m > c ? m : c;
+    }
+    case SC_WS_BUILD: return a;
+    case SC_WS_SOLVE: return b;
+    case SC_WS_ADJOINT: return c;
+    default: return 0;
+    }
 }
 
 extern "C" const char *sc_strerror(int code) {

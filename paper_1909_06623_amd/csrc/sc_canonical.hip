@@ -52,7 +52,7 @@ extern "C" int sc_canonical_order(int32_t n, const sc_contacts *c, int32_t *perm
     if (c->count == 0 || n == 0) return SC_OK;
     if (!perm || !c->ci || !c->cj) return SC_ERR_INVALID;
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 ||
-        ws_bytes < sc_workspace_bytes(n, c->capacity))
+        ws_bytes < sc_workspace_bytes(n, c->capacity, SC_WS_BUILD))
         return SC_ERR_WORKSPACE;
     sc::Carver cv{static_cast<char *>(ws), ws_bytes};
     int32_t *cnt = cv.take<int32_t>(static_cast<size_t>(n) + 1);

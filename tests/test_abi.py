@@ -43,11 +43,16 @@ def test_strerror_and_version():
 def test_workspace_bytes_monotone():
     from paper_1909_06623_amd import _abi as A
     L = A.lib()
-    a = L.sc_workspace_bytes(1000, 5000)
-    b = L.sc_workspace_bytes(2000, 5000)
-    c = L.sc_workspace_bytes(2000, 10000)
+    a = L.sc_workspace_bytes(1000, 5000, A.SC_WS_ALL)
+    b = L.sc_workspace_bytes(2000, 5000, A.SC_WS_ALL)
+    c = L.sc_workspace_bytes(2000, 10000, A.SC_WS_ALL)
     assert 0 < a < b < c
-    assert L.sc_workspace_bytes(-1, 10) == 0
+    assert L.sc_workspace_bytes(-1, 10, A.SC_WS_ALL) == 0
+    # per purpose: each no larger than the whole, the whole the largest of them
+    parts = [L.sc_workspace_bytes(2000, 10000, w)
+             for w in (A.SC_WS_BUILD, A.SC_WS_SOLVE, A.SC_WS_ADJOINT)]
+    assert all(0 < x <= c for x in parts) and max(parts) == c
+    assert L.sc_workspace_bytes(2000, 10000, 9) == 0
 
 
 def test_invalid_arguments_rejected_without_device_work():
