@@ -91,6 +91,48 @@ def large(sc, W, torch, np, steps=3):
             "rods_per_s": s.n / (kernel_ms * 1e-3), "roofline": roof}
 
 
+def spheres1000(sc, W, torch, np, steps):
+    """The 1000-sphere suspension (radius 0.5, volume fraction 0.3, delta
+    0.1, dt 1e-3): contact build + BBPGD to 1e-6 per step, as the main leg;
+    latency-bound at this size (a few hundred contacts per workgroup)."""
+    s = W.workload(1)
+    P = sc.Particles.from_suspension(s)
+    box = sc.Box(tuple(s.box))
+    u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
+    ws = sc.Workspace()
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, workspace=ws)
+    cap = con.capacity
+    for _ in range(3):
+        sc.build_contacts(P, box, s.delta, u_nc, s.dt, capacity=cap, workspace=ws)
+        sc.solve_lcp(P, con, tol=s.tol, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = []
+    for _ in range(steps):
+        con = sc.build_contacts(P, box, s.delta, u_nc, s.dt, capacity=cap, workspace=ws)
+        sts.append(sc.solve_lcp(P, con, tol=s.tol, workspace=ws)[2])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    st = sts[-1]
+    products = st["iters"] + 2
+    kernel_ms = float(np.mean([x["kernel_ms"] for x in sts]))
+    bytes_iter = iteration_bytes(con.count, s.n, rods=False)
+    gbs = bytes_iter * products / (kernel_ms * 1e-3) / 1e9
+    return {"workload": "1000 spheres R=0.5, volume fraction 0.3, periodic box 12.04, delta 0.1, "
+                        "dt 1e-3, BBPGD (BB1) to 1e-6",
+            "n": s.n, "n_contacts": con.count, "iters": st["iters"], "status": st["status"],
+            "ms_per_step": ms, "particles_per_s": s.n / (ms * 1e-3), "solve_kernel_ms": kernel_ms,
+            "us_per_product": 1e3 * kernel_ms / products,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_bbpgd_mat (persistent BBPGD solve)",
+                         "bytes_model": "120 n_c + 56 N bytes per product (spheres), (iterations "
+                                        "+ 2) products per launch",
+                         "bytes_per_product": bytes_iter, "launch_ms": kernel_ms,
+                         "note": "0.2 MB per product: bound by the per-iteration barrier and "
+                                 "reduction latency, not by memory"}}
+
+
 def timestepping(sc, W, torch, np, steps):
     """Euler time steps (contacts rebuilt, LCP solved, centres and
     quaternions advanced) of the 100,000-rod suspension, with and without
@@ -626,6 +668,7 @@ def main():
 
     batch = None if args.no_batch else batched(sc, W, torch, np, args.batch_count)
     big = None if args.no_large else large(sc, W, torch, np, args.large_steps)
+    sph = spheres1000(sc, W, torch, np, 20)
     tsl = None if args.no_timestep else timestepping(sc, W, torch, np, args.timestep_steps)
     hyd = None if args.no_hydro else hydro(sc, W, torch, np, args.hydro_steps)
 
@@ -687,6 +730,7 @@ def main():
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],
         "batched": batch,
         "large": big,
+        "spheres1000": sph,
         "timestep": tsl,
         "hydro": hyd,
     }

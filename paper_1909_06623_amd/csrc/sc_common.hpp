@@ -71,6 +71,10 @@ void release_mob_host();
 int solve_lcp_on(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *opts,
                  double *gamma, double *g, double *f_c, double *u_c, sc_stats *st, void *ws,
                  size_t ws_bytes, void *stream, bool timed);
+// sc_solve_lcp's argument checks without the workspace (no device call):
+// SC_OK or SC_ERR_INVALID.
+int check_solve_args(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *opts,
+                     const double *gamma, const double *g, const sc_stats *st);
 
 // Device-wide exclusive scan of n int32 values: out[k] = sum_{m<k} in[m] and
 // out[n] = total. `tmp` needs scan_tmp_ints(n) ints. in may equal out.

@@ -754,8 +754,8 @@ __global__ void k_rpy_grad_finish(int n, int splits, const double *part, double 
 int rpy_splits(int n) {
     const int bx = grid_for(n, kRpyTargets);
     int s = (kRpyTargetBlocks + bx - 1) / bx;
-    const int smax = (n + kRpyMinSources - 1) / kRpyMinSources;
-    if (s > smax) s = smax;
+    const long long smax = (static_cast<long long>(n) + kRpyMinSources - 1) / kRpyMinSources;
+    if (s > smax) s = static_cast<int>(smax);
     if (s > kRpyMaxSplits) s = kRpyMaxSplits;
     return s < 1 ? 1 : s;
 }
@@ -1095,7 +1095,7 @@ __global__ void __launch_bounds__(kPB) k_bbpgd_rpy(RpyPersArgs A) {
 // units per workgroup up to 2000 spheres); never more than rpy_splits(n),
 // whose partial sums the sc_rpy workspace holds.
 int rpy_pers_splits(int n, int grid) {
-    const int bx = (n + kRpyTargets - 1) / kRpyTargets;
+    const int bx = grid_for(n, kRpyTargets);
     int s = (grid + bx - 1) / bx;
     const int smax = rpy_splits(n);
     if (s > smax) s = smax;

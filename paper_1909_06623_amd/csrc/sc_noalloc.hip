@@ -41,6 +41,9 @@ extern "C" int sc_solve_lcp_noalloc(const sc_particles *p, const sc_contacts *c,
                                     double *f_c, double *u_c, sc_stats *st, void *stream) {
     if (!p || !c || p->n < 0 || c->capacity < 0) return SC_ERR_INVALID;
     if (sc::solve_ws_bytes(p->n, c->capacity) > SC_NOALLOC_SCRATCH_BYTES) return SC_ERR_WORKSPACE;
+    // every argument is checked before the first HIP call (the symbol lookup)
+    const int bad = sc::check_solve_args(p, c, opts, gamma, g, st);
+    if (bad) return bad;
     void *ws = nullptr;
     const int rc = scratch_ptr(&ws);
     if (rc != SC_OK) return rc;

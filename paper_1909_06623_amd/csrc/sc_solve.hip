@@ -441,9 +441,11 @@ struct Prepared {
     SolveArgs A{};
 };
 
-int prepare(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *opts,
-            double *gamma, double *g, void *ws, size_t ws_bytes, Prepared &P) {
-    int rc = check_common(p, c, P.pl);
+// The solve's argument checks (everything but the workspace): the plan and
+// the assembled matrix are carved, the product chosen. Host arithmetic only.
+int check_args(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *opts,
+               const double *gamma, const double *g, Plan &pl, bool &use_mat, MatBufs &mb) {
+    int rc = check_common(p, c, pl);
     if (rc) return rc;
     if (!opts) return SC_ERR_INVALID;
     if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->bb < 1 || opts->bb > 3 ||
@@ -452,10 +454,18 @@ int prepare(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *op
         !block_ok(opts->block) || opts->op < 0 ||
         opts->op > SC_OP_MATRIX || (opts->op == SC_OP_MATRIX && !c->mat_ready))
         return SC_ERR_INVALID;
-    const int n = p->n, nc = c->count;
-    P.use_mat = opts->op == SC_OP_MATRIX || (opts->op == SC_OP_AUTO && c->mat_ready);
-    if (P.use_mat && !carve_matrix(c->mat, c->mat_bytes, nc, c->nnz, P.mb)) return SC_ERR_INVALID;
-    if (nc > 0 && (!gamma || !g)) return SC_ERR_INVALID;
+    use_mat = opts->op == SC_OP_MATRIX || (opts->op == SC_OP_AUTO && c->mat_ready);
+    if (use_mat && !carve_matrix(c->mat, c->mat_bytes, c->count, c->nnz, mb))
+        return SC_ERR_INVALID;
+    if (c->count > 0 && (!gamma || !g)) return SC_ERR_INVALID;
+    return SC_OK;
+}
+
+int prepare(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *opts,
+            double *gamma, double *g, void *ws, size_t ws_bytes, Prepared &P) {
+    int rc = check_args(p, c, opts, gamma, g, P.pl, P.use_mat, P.mb);
+    if (rc) return rc;
+    const int n = p->n;
     if (!ws_ok(ws, ws_bytes, solve_ws_bytes(n, c->capacity))) return SC_ERR_WORKSPACE;
     Carver cv{static_cast<char *>(ws), ws_bytes};
     P.zbuf = cv.take<double>(4 * static_cast<size_t>(c->capacity));
@@ -570,6 +580,16 @@ int mark_cooperative_if_captured(hipStream_t s) {
 }
 
 }  // namespace
+
+int sc::check_solve_args(const sc_particles *p, const sc_contacts *c,
+                         const sc_solve_opts *opts, const double *gamma, const double *g,
+                         const sc_stats *st) {
+    if (!st) return SC_ERR_INVALID;
+    Plan pl;
+    bool use_mat = false;
+    MatBufs mb{};
+    return check_args(p, c, opts, gamma, g, pl, use_mat, mb);
+}
 
 // The body of sc_solve_lcp on a given workspace. `timed`: measure the
 // persistent kernel with HIP events (created once per host thread); without
