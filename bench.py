@@ -387,7 +387,8 @@ def batched(sc, W, torch, np, count):
 
     # solve + adjoint only, contacts prebuilt
     items = [(P, con, box, u_nc, s.dt) for (s, P, box, u_nc), (con, _) in zip(inst, singles)]
-    bs = sc.Batch(items, tol=tol, team=info["team"], adjoint=1, adjoint_tol=atol)
+    bs = sc.Batch(items, tol=tol, team=info["team"], adjoint=1, adjoint_tol=atol,
+                  adjoint_team=info["team_adjoint"])
     solve_ms = graph_ms(bs)
 
     def solve_one(P, con, box, u_nc, dt):
@@ -457,7 +458,9 @@ def batched(sc, W, torch, np, count):
             "solve_adjoint_batch_ms": solve_ms,
             "solve_adjoint_one_at_a_time_ms": single_solve_ms,
             "solve_adjoint_speedup": single_solve_ms / solve_ms,
-            "team": info["team"], "tune_ms": info["tune_ms"], "tune_s": tune_s,
+            "team": info["team"], "tune_ms": info["tune_ms"],
+            "team_adjoint": info["team_adjoint"], "tune_adjoint_ms": info["tune_adjoint_ms"],
+            "tune_s": tune_s,
             "all_converged": all(x["status"] == 0 for x in st),
             "adjoint_all_converged": all(x["status"] == 0 for x in adj),
             "adjoint_cg_iters_sum": sum(x["iters"] for x in adj),

@@ -383,12 +383,18 @@ typedef struct sc_batch_opts {
     int32_t adjoint_max_iter;
     int32_t build;          /* 1: each solve first builds every instance's contacts
                                and M on the device (see sc_batch_item) */
+    int32_t adjoint_team;   /* workgroups per instance of the adjoint launch (same
+                               values as team); 0 = as team, or with team == 0 tuned
+                               on its own (the autotuner times the two launches
+                               apart and keeps the fastest size of each) */
 } sc_batch_opts;
 
 typedef struct sc_batch_info {
-    int32_t team, block, grid;      /* launch used */
+    int32_t team, block, grid;      /* launch used (team: the forward launch's) */
     int32_t lds_entries_per_wave;   /* entries of M per wave kept in LDS */
-    float tune_ms[6];               /* autotuner: batch time for team 1, 2, ..., 32 */
+    float tune_ms[6];               /* autotuner: build + forward time for team 1, 2, ..., 32 */
+    int32_t team_adjoint;           /* team size of the adjoint launch */
+    float tune_adjoint_ms[6];       /* autotuner: adjoint launch time for team 1, ..., 32 */
 } sc_batch_info;
 
 typedef struct sc_batch sc_batch;   /* opaque plan (host memory) */

@@ -665,7 +665,8 @@ class Batch:
 
     ``items``: list of (Particles, Contacts) with assembled M, or, with
     ``adjoint``, (Particles, Contacts, Box, u_nc, dt). ``team``: 0 autotunes
-    the number of workgroups per instance. After ``solve()`` /
+    the number of workgroups per instance; ``adjoint_team``: that of the
+    adjoint launch (0: as ``team``, or tuned on its own when ``team`` is 0). After ``solve()`` /
     ``graph_solve()``, ``gamma[k]`` and ``g[k]`` hold each solution and, with
     ``adjoint`` (1: loss 1/2 ||D gamma||^2 + dL_dgamma . gamma, 2: the linear
     term only), ``dL_dq[k]`` and ``dL_dpos[k]`` its gradients.
@@ -681,7 +682,8 @@ class Batch:
 
     def __init__(self, items, tol=1e-6, max_iter=100000, bb=1, team=0, block=0,
                  gamma0=None, adjoint=0, dL_dgamma=None, adjoint_tol=1e-10,
-                 adjoint_max_iter=100000, build=False, capacity=None, nnz_capacity=None):
+                 adjoint_max_iter=100000, build=False, capacity=None, nnz_capacity=None,
+                 adjoint_team=0):
         self._keep = []
         self.gamma, self.g, self.dL_dq, self.dL_dpos = [], [], [], []
         self.build = bool(build)
@@ -746,7 +748,7 @@ class Batch:
         opts = A.sc_batch_opts(float(tol), int(max_iter), int(bb),
                                1 if gamma0 is not None else 0, int(team), int(block),
                                self.adjoint, float(adjoint_tol), int(adjoint_max_iter),
-                               1 if self.build else 0)
+                               1 if self.build else 0, int(adjoint_team))
         need = int(A.lib().sc_batch_workspace_bytes(self.count, arr, ctypes.byref(opts)))
         if need == 0:
             raise RuntimeError("sc_batch_workspace_bytes: invalid arguments")
@@ -801,7 +803,8 @@ class Batch:
                                                         _stream()))
         inf = {"team": info.team, "block": info.block, "grid": info.grid,
                "lds_entries_per_wave": info.lds_entries_per_wave,
-               "tune_ms": list(info.tune_ms)}
+               "tune_ms": list(info.tune_ms), "team_adjoint": info.team_adjoint,
+               "tune_adjoint_ms": list(info.tune_adjoint_ms)}
         sts = [st[k].as_dict() for k in range(self.count)]
         adjs = [adj[k].as_dict() for k in range(self.count)] if self.adjoint else None
         return sts, adjs, inf

@@ -256,6 +256,10 @@ hipError_t batch_cache(const void *fn, int block, int *per_block, size_t *dyn) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(*dyn));
 }
 
+bool team_ok(int t) {
+    return t == 0 || t == 1 || t == 2 || t == 4 || t == 8 || t == 16 || t == 32;
+}
+
 // rows an instance's solve buffers hold: its contacts, or in build mode its
 // capacity
 size_t rows(const sc_contacts &c, bool build) {
@@ -282,6 +286,7 @@ struct sc_batch {
     BatchArgs args{};
     int nteams_max = 0;
     int team = 1, block = 1024, grid = 0;
+    int team_adj = 1;                  // team size of the adjoint launch
     size_t dyn = 0;
     const void *fn = nullptr, *fn_adj = nullptr;
     bool build = false;
@@ -291,7 +296,8 @@ struct sc_batch {
     int *order = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    float tune_ms[6] = {0, 0, 0, 0, 0, 0};
+    float tune_ms[6] = {0, 0, 0, 0, 0, 0};      // autotuner: build + forward per team size
+    float tune_adj_ms[6] = {0, 0, 0, 0, 0, 0};  // autotuner: adjoint launch per team size
 };
 
 namespace {
@@ -316,7 +322,8 @@ size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nteams, boo
     return b + 256;
 }
 
-int enqueue(sc_batch *b, hipStream_t s) {
+// `mid` (optional) is recorded between the forward and the adjoint launch.
+int enqueue(sc_batch *b, hipStream_t s, hipEvent_t mid = nullptr) {
     const int nteams = b->nteams_max;
     if (b->build) {
         const int rc = batch_build_enqueue(b->bld, s);
@@ -329,8 +336,10 @@ int enqueue(sc_batch *b, hipStream_t s) {
     a.team = b->team;
     void *args[] = {&a};
     SC_HIP_TRY(hipLaunchCooperativeKernel(b->fn, dim3(b->grid), dim3(b->block), args, b->dyn, s));
+    if (mid) SC_HIP_TRY(hipEventRecord(mid, s));
     if (b->args.adjoint) {
         BatchArgs c = a;
+        c.team = b->team_adj;
         c.ctl = b->args.ctl + 1;
         c.tsync = b->args.tsync + b->nteams_max;
         void *cargs[] = {&c};
@@ -357,8 +366,7 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     if (!out || !opts || count < 0 || (count > 0 && !items)) return SC_ERR_INVALID;
     *out = nullptr;
     if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->bb < 1 || opts->bb > 3 ||
-        !(opts->team == 0 || opts->team == 1 || opts->team == 2 || opts->team == 4 ||
-          opts->team == 8 || opts->team == 16 || opts->team == 32) ||
+        !team_ok(opts->team) || !team_ok(opts->adjoint_team) ||
         !block_ok(opts->block) || opts->adjoint < 0 || opts->adjoint > 2 ||
         (opts->adjoint && (!(opts->adjoint_tol > 0.0) || opts->adjoint_max_iter < 0)) ||
         opts->build < 0 || opts->build > 1)
@@ -505,34 +513,35 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     }
     if (opts->team > 0) {
         b->team = opts->team;
+        b->team_adj = opts->adjoint_team > 0 ? opts->adjoint_team : opts->team;
     } else {
-        // autotuner: solve the batch once per team size, keep the fastest
-        hipEvent_t e0, e1;
-        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-            delete b;
-            return SC_ERR_HIP;
-        }
-        const int sizes[6] = {1, 2, 4, 8, 16, 32};
-        float best = -1.0f;
+        // autotuner: solve the batch once per team size (forward and adjoint
+        // launches with that size, timed apart), keep the fastest of each.
+        // The adjoint is latency-bound (a few dozen CG iterations per
+        // instance), so its best team can differ from the forward's.
+        hipEvent_t e[3] = {nullptr, nullptr, nullptr};
         int rc = SC_OK;
+        for (auto &ev : e)
+            if (rc == SC_OK && hipEventCreate(&ev) != hipSuccess) rc = SC_ERR_HIP;
+        const int sizes[6] = {1, 2, 4, 8, 16, 32};
         for (int i = 0; i < 6 && rc == SC_OK; ++i) {
-            b->team = sizes[i];
-            rc = hipEventRecord(e0, s) == hipSuccess ? enqueue(b, s) : SC_ERR_HIP;
-            if (rc == SC_OK && (hipEventRecord(e1, s) != hipSuccess ||
-                                hipEventSynchronize(e1) != hipSuccess ||
-                                hipEventElapsedTime(&b->tune_ms[i], e0, e1) != hipSuccess))
+            b->team = b->team_adj = sizes[i];
+            rc = hipEventRecord(e[0], s) == hipSuccess ? enqueue(b, s, e[1]) : SC_ERR_HIP;
+            if (rc == SC_OK && (hipEventRecord(e[2], s) != hipSuccess ||
+                                hipEventSynchronize(e[2]) != hipSuccess ||
+                                hipEventElapsedTime(&b->tune_ms[i], e[0], e[1]) != hipSuccess ||
+                                hipEventElapsedTime(&b->tune_adj_ms[i], e[1], e[2]) != hipSuccess))
                 rc = SC_ERR_HIP;
-            if (rc == SC_OK && (best < 0.0f || b->tune_ms[i] < best)) best = b->tune_ms[i];
         }
-        int pick = 1;
-        for (int i = 0; i < 6; ++i)
-            if (b->tune_ms[i] == best) {
-                pick = sizes[i];
-                break;
-            }
-        b->team = pick;
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        int pf = 0, pa = 0;
+        for (int i = 1; i < 6; ++i) {
+            if (b->tune_ms[i] < b->tune_ms[pf]) pf = i;
+            if (b->tune_adj_ms[i] < b->tune_adj_ms[pa]) pa = i;
+        }
+        b->team = sizes[pf];
+        b->team_adj = !adj ? b->team : opts->adjoint_team > 0 ? opts->adjoint_team : sizes[pa];
+        for (auto &ev : e)
+            if (ev) (void)hipEventDestroy(ev);
         if (rc != SC_OK) {
             delete b;
             return rc;
@@ -629,6 +638,8 @@ extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_stats *adj,
         info->grid = b->grid;
         info->lds_entries_per_wave = b->args.cache / (b->block / kWave);
         for (int i = 0; i < 6; ++i) info->tune_ms[i] = b->tune_ms[i];
+        info->team_adjoint = b->team_adj;
+        for (int i = 0; i < 6; ++i) info->tune_adjoint_ms[i] = b->tune_adj_ms[i];
     }
     if (b->count == 0) return SC_OK;
     std::vector<SolveCtrl> h(static_cast<size_t>(b->count));
@@ -659,7 +670,7 @@ extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_stats *adj,
             adj[k].mvops = hc[k].iters + 1;
             adj[k].residual = hc[k].res;
             adj[k].alpha = hc[k].alpha;
-            adj[k].grid = b->team;
+            adj[k].grid = b->team_adj;
             adj[k].block = b->block;
             adj[k].op = SC_OP_MATRIX;
             adj[k].n_active = -1;

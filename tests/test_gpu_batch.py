@@ -112,18 +112,21 @@ def test_batch_empty_and_contactless():
     assert st[0]["mvops"] == 1
 
 
-@pytest.mark.parametrize("team", [1, 8])
-def test_batch_adjoint_matches_single_instance_and_oracle(team):
+@pytest.mark.parametrize("team,adjoint_team", [(1, 0), (8, 0), (8, 2)])
+def test_batch_adjoint_matches_single_instance_and_oracle(team, adjoint_team):
     """Forward + adjoint of L = 1/2 ||D gamma||^2 for every instance in one
     persistent launch: the gradients equal the single-instance adjoint of the
     batch's own solution (both are the same implicit solve), and agree with
     the oracle's adjoint on rod instances whose active sets match."""
     import paper_1909_06623_amd as sc
     sus, items = _instances(10, 1500, seed=W.SEED_BASE + 703, full=True)
-    _say(f"batch adjoint team={team}: {len(items)} instances")
-    b = sc.Batch(items, tol=1e-10, team=team, adjoint=1, adjoint_tol=1e-12)
+    _say(f"batch adjoint team={team} adjoint_team={adjoint_team}: {len(items)} instances")
+    b = sc.Batch(items, tol=1e-10, team=team, adjoint=1, adjoint_tol=1e-12,
+                 adjoint_team=adjoint_team)
     b.solve()
     st, adj, info = b.stats()
+    assert info["team"] == team and info["team_adjoint"] == (adjoint_team or team)
+    assert all(x["grid"] == (adjoint_team or team) for x in adj)
     assert all(x["status"] == 0 for x in st)
     assert all(x["status"] == 0 for x in adj), [x["status"] for x in adj]
     checked = 0
@@ -160,6 +163,35 @@ def test_batch_adjoint_matches_single_instance_and_oracle(team):
     torch.cuda.synchronize()
     assert all(torch.equal(a, x) for a, x in zip(d1, b.dL_dpos))
     b.close()
+
+
+def test_batch_autotune_picks_each_launch_and_reproduces():
+    """With team = 0 and the adjoint on, the autotuner times the forward and
+    the adjoint launch apart for every team size and keeps the fastest of
+    each; a batch created with the two picked sizes gives bitwise the same
+    solutions and gradients."""
+    import paper_1909_06623_amd as sc
+    sus, items = _instances(6, 1200, seed=W.SEED_BASE + 705, full=True)
+    _say(f"batch adjoint autotune: {len(items)} instances")
+    b = sc.Batch(items, tol=1e-10, team=0, adjoint=1, adjoint_tol=1e-12)
+    b.solve()
+    st, adj, info = b.stats()
+    sizes = (1, 2, 4, 8, 16, 32)
+    assert info["team"] in sizes and info["team_adjoint"] in sizes
+    assert all(t > 0 for t in info["tune_ms"]) and all(t > 0 for t in info["tune_adjoint_ms"])
+    assert info["tune_ms"][sizes.index(info["team"])] == min(info["tune_ms"])
+    assert info["tune_adjoint_ms"][sizes.index(info["team_adjoint"])] == \
+        min(info["tune_adjoint_ms"])
+    assert all(x["status"] == 0 for x in st) and all(x["status"] == 0 for x in adj)
+    f = sc.Batch(items, tol=1e-10, team=info["team"], adjoint=1, adjoint_tol=1e-12,
+                 adjoint_team=info["team_adjoint"])
+    f.solve()
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(b.gamma, f.gamma))
+    assert all(torch.equal(x, y) for x, y in zip(b.dL_dq, f.dL_dq))
+    assert all(torch.equal(x, y) for x, y in zip(b.dL_dpos, f.dL_dpos))
+    b.close()
+    f.close()
 
 
 def test_batch_status_paths_eager_and_graph():
