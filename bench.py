@@ -387,8 +387,8 @@ def batched(sc, W, torch, np, count):
 
     # solve + adjoint only, contacts prebuilt
     items = [(P, con, box, u_nc, s.dt) for (s, P, box, u_nc), (con, _) in zip(inst, singles)]
-    bs = sc.Batch(items, tol=tol, team=info["team"], adjoint=1, adjoint_tol=atol,
-                  adjoint_team=info["team_adjoint"])
+    pol = sc.Batch.tuned_policy(info)
+    bs = sc.Batch(items, tol=tol, adjoint=1, adjoint_tol=atol, **pol)
     solve_ms = graph_ms(bs)
 
     def solve_one(P, con, box, u_nc, dt):
@@ -405,7 +405,8 @@ def batched(sc, W, torch, np, count):
     # kernel times of the persistent batched kernels: eager solves on the
     # current stream bracketed by HIP events, forward alone (a batch without
     # the adjoint) and forward + adjoint; the difference is the adjoint launch
-    bf = sc.Batch([(P, con) for P, con, _, _, _ in items], tol=tol, team=info["team"])
+    bf = sc.Batch([(P, con) for P, con, _, _, _ in items], tol=tol, team=pol["team"],
+                  nnz_per_workgroup=pol["nnz_per_workgroup"])
 
     def event_ms(b, reps=3):
         b.solve()
@@ -458,9 +459,13 @@ def batched(sc, W, torch, np, count):
             "solve_adjoint_batch_ms": solve_ms,
             "solve_adjoint_one_at_a_time_ms": single_solve_ms,
             "solve_adjoint_speedup": single_solve_ms / solve_ms,
-            "team": info["team"], "tune_ms": info["tune_ms"],
-            "team_adjoint": info["team_adjoint"], "tune_adjoint_ms": info["tune_adjoint_ms"],
-            "tune_s": tune_s,
+            "policy": pol,
+            "team_sizes": {str(t): sum(1 for x in st if x["grid"] == t) for t in (1, 2, 4, 8, 16, 32)},
+            "adjoint_team_sizes": {str(t): sum(1 for x in adj if x["grid"] == t)
+                                   for t in (1, 2, 4, 8, 16, 32)},
+            "tune_policies": [f"classes nnz/workgroup {4096 << i}" for i in range(6)]
+            + [f"team {1 << i}" for i in range(6)], "tune_ms": info["tune_ms"],
+            "tune_adjoint_ms": info["tune_adjoint_ms"], "tune_s": tune_s,
             "all_converged": all(x["status"] == 0 for x in st),
             "adjoint_all_converged": all(x["status"] == 0 for x in adj),
             "adjoint_cg_iters_sum": sum(x["iters"] for x in adj),

@@ -373,8 +373,8 @@ typedef struct sc_batch_opts {
     int32_t bb;             /* 1 = BB1, 2 = BB2, 3 = alternating */
     int32_t warm_start;     /* 1: gamma holds gamma_0 on entry */
     int32_t team;           /* workgroups per instance, all on one XCD: 1, 2, 4, 8,
-                               16 or 32; 0 = autotune (solves the batch once per size
-                               and keeps the fastest; overwrites gamma and g) */
+                               16 or 32 for every instance; 0 = size classes (see
+                               nnz_per_workgroup) */
     int32_t block;          /* threads per workgroup: 0 (1024), 256, 512 or 1024 */
     int32_t adjoint;        /* 0: solve only; 1: then the adjoint of
                                L = 1/2 ||D gamma||^2 + dL_dgamma . gamma; 2: of the
@@ -383,18 +383,33 @@ typedef struct sc_batch_opts {
     int32_t adjoint_max_iter;
     int32_t build;          /* 1: each solve first builds every instance's contacts
                                and M on the device (see sc_batch_item) */
-    int32_t adjoint_team;   /* workgroups per instance of the adjoint launch (same
-                               values as team); 0 = as team, or with team == 0 tuned
-                               on its own (the autotuner times the two launches
-                               apart and keeps the fastest size of each) */
+    int32_t adjoint_team;   /* the adjoint launch's team (values as team); with
+                               adjoint_nnz_per_workgroup also 0: the forward's policy,
+                               tuned on its own when the forward's is tuned */
+    int32_t nnz_per_workgroup; /* team == 0: instance k runs on t_k workgroups, the
+                               smallest power of two with t_k * nnz_per_workgroup >=
+                               its nonzeros of M, at most 32 (teams of 32 per XCD
+                               halve as the queue, largest first, reaches smaller
+                               classes); 0 with team == 0 = autotune: the batch is
+                               solved once with classes for each of 4096, 8192, ...,
+                               131072 and once with each single team size, and the
+                               fastest policy kept, for the forward and the adjoint
+                               launch apart (overwrites gamma and g) */
+    int32_t adjoint_nnz_per_workgroup; /* the same for the adjoint launch (0: see
+                               adjoint_team) */
 } sc_batch_opts;
 
 typedef struct sc_batch_info {
-    int32_t team, block, grid;      /* launch used (team: the forward launch's) */
+    int32_t team, block, grid;      /* launch used (team: the forward launch's team size,
+                                       or 32 with size classes) */
     int32_t lds_entries_per_wave;   /* entries of M per wave kept in LDS */
-    float tune_ms[6];               /* autotuner: build + forward time for team 1, 2, ..., 32 */
-    int32_t team_adjoint;           /* team size of the adjoint launch */
-    float tune_adjoint_ms[6];       /* autotuner: adjoint launch time for team 1, ..., 32 */
+    float tune_ms[12];              /* autotuner: build + forward time for size classes
+                                       with nnz_per_workgroup = 4096, 8192, ..., 131072,
+                                       then for one team size 1, 2, ..., 32 (0: skipped) */
+    int32_t team_adjoint;           /* the adjoint launch's team size (32 with classes) */
+    float tune_adjoint_ms[12];      /* autotuner: adjoint launch time, same policies */
+    int32_t nnz_per_workgroup;      /* size classes' target used (0: one team size) */
+    int32_t adjoint_nnz_per_workgroup;
 } sc_batch_info;
 
 typedef struct sc_batch sc_batch;   /* opaque plan (host memory) */
@@ -406,8 +421,9 @@ size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *items,
 
 /* Plans a batch of `count` LCPs (Algorithm 1 per instance, section 3.3.1): checks
  * every item, writes the instance table and the work order (by nonzeros,
- * largest first) into ws, and picks the team size (autotuning if
- * opts->team == 0). *out receives a plan to free with sc_batch_destroy.
+ * largest first) into ws, and sets each launch's team policy (autotuning
+ * if opts->team and opts->nnz_per_workgroup are 0). *out receives a plan
+ * to free with sc_batch_destroy.
  * Synchronises `stream`. */
 int sc_batch_create(int32_t count, const sc_batch_item *items, const sc_batch_opts *opts,
                     void *ws, size_t ws_bytes, void *stream, sc_batch **out);
@@ -427,7 +443,7 @@ int sc_batch_solve(sc_batch *b, void *stream);
 int sc_batch_graph_launch(sc_batch *b, void *stream);
 
 /* Per-instance results of the last solve (st: host array of count; grid
- * holds the team size), of its adjoint (adj: host array of count or NULL;
+ * holds the instance's team size), of its adjoint (adj: host array of count or NULL;
  * iters = CG iterations, residual = relative CG residual) and the launch
  * used (info may be NULL). Synchronises `stream`. */
 int sc_batch_stats(const sc_batch *b, sc_stats *st, sc_stats *adj, sc_batch_info *info,

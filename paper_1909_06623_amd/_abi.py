@@ -99,14 +99,17 @@ class sc_batch_opts(ctypes.Structure):
                 ("team", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("adjoint", ctypes.c_int32), ("adjoint_tol", ctypes.c_double),
                 ("adjoint_max_iter", ctypes.c_int32), ("build", ctypes.c_int32),
-                ("adjoint_team", ctypes.c_int32)]
+                ("adjoint_team", ctypes.c_int32), ("nnz_per_workgroup", ctypes.c_int32),
+                ("adjoint_nnz_per_workgroup", ctypes.c_int32)]
 
 
 class sc_batch_info(ctypes.Structure):
     _fields_ = [("team", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("lds_entries_per_wave", ctypes.c_int32),
-                ("tune_ms", ctypes.c_float * 6), ("team_adjoint", ctypes.c_int32),
-                ("tune_adjoint_ms", ctypes.c_float * 6)]
+                ("tune_ms", ctypes.c_float * 12), ("team_adjoint", ctypes.c_int32),
+                ("tune_adjoint_ms", ctypes.c_float * 12),
+                ("nnz_per_workgroup", ctypes.c_int32),
+                ("adjoint_nnz_per_workgroup", ctypes.c_int32)]
 
 
 class sc_rpy(ctypes.Structure):

@@ -664,9 +664,13 @@ class Batch:
     workgroups per instance at a time, instances taken largest first).
 
     ``items``: list of (Particles, Contacts) with assembled M, or, with
-    ``adjoint``, (Particles, Contacts, Box, u_nc, dt). ``team``: 0 autotunes
-    the number of workgroups per instance; ``adjoint_team``: that of the
-    adjoint launch (0: as ``team``, or tuned on its own when ``team`` is 0). After ``solve()`` /
+    ``adjoint``, (Particles, Contacts, Box, u_nc, dt). ``team`` > 0 runs
+    every instance on that many workgroups; with ``team`` = 0 each instance
+    gets the smallest power of two t with t * ``nnz_per_workgroup`` >= its
+    nonzeros of M (at most 32), and with both 0 the target is autotuned.
+    ``adjoint_team`` / ``adjoint_nnz_per_workgroup`` do the same for the
+    adjoint launch (both 0: the forward's policy, tuned on its own when the
+    forward's is). After ``solve()`` /
     ``graph_solve()``, ``gamma[k]`` and ``g[k]`` hold each solution and, with
     ``adjoint`` (1: loss 1/2 ||D gamma||^2 + dL_dgamma . gamma, 2: the linear
     term only), ``dL_dq[k]`` and ``dL_dpos[k]`` its gradients.
@@ -683,7 +687,7 @@ class Batch:
     def __init__(self, items, tol=1e-6, max_iter=100000, bb=1, team=0, block=0,
                  gamma0=None, adjoint=0, dL_dgamma=None, adjoint_tol=1e-10,
                  adjoint_max_iter=100000, build=False, capacity=None, nnz_capacity=None,
-                 adjoint_team=0):
+                 adjoint_team=0, nnz_per_workgroup=0, adjoint_nnz_per_workgroup=0):
         self._keep = []
         self.gamma, self.g, self.dL_dq, self.dL_dpos = [], [], [], []
         self.build = bool(build)
@@ -748,7 +752,8 @@ class Batch:
         opts = A.sc_batch_opts(float(tol), int(max_iter), int(bb),
                                1 if gamma0 is not None else 0, int(team), int(block),
                                self.adjoint, float(adjoint_tol), int(adjoint_max_iter),
-                               1 if self.build else 0, int(adjoint_team))
+                               1 if self.build else 0, int(adjoint_team),
+                               int(nnz_per_workgroup), int(adjoint_nnz_per_workgroup))
         need = int(A.lib().sc_batch_workspace_bytes(self.count, arr, ctypes.byref(opts)))
         if need == 0:
             raise RuntimeError("sc_batch_workspace_bytes: invalid arguments")
@@ -771,6 +776,16 @@ class Batch:
         nnzc = (int(nnz_capacity[k]) if nnz_capacity is not None
                 else int(1.5 * c0.nnz) + 16 * (cap - c0.count) + 1024)
         return cap, nnzc
+
+    @staticmethod
+    def tuned_policy(info):
+        """The keyword arguments that recreate the team policies an autotuned
+        batch picked (from ``stats()``'s info): size classes (team 0 and a
+        nonzeros-per-workgroup target) or one team size, for each launch."""
+        f, a = info["nnz_per_workgroup"], info["adjoint_nnz_per_workgroup"]
+        return {"team": 0 if f > 0 else info["team"], "nnz_per_workgroup": f,
+                "adjoint_team": 0 if a > 0 else info["team_adjoint"],
+                "adjoint_nnz_per_workgroup": a}
 
     def counts(self):
         """Build mode: (contacts, nonzeros of M, build status) per instance for
@@ -804,7 +819,9 @@ class Batch:
         inf = {"team": info.team, "block": info.block, "grid": info.grid,
                "lds_entries_per_wave": info.lds_entries_per_wave,
                "tune_ms": list(info.tune_ms), "team_adjoint": info.team_adjoint,
-               "tune_adjoint_ms": list(info.tune_adjoint_ms)}
+               "tune_adjoint_ms": list(info.tune_adjoint_ms),
+               "nnz_per_workgroup": info.nnz_per_workgroup,
+               "adjoint_nnz_per_workgroup": info.adjoint_nnz_per_workgroup}
         sts = [st[k].as_dict() for k in range(self.count)]
         adjs = [adj[k].as_dict() for k in range(self.count)] if self.adjoint else None
         return sts, adjs, inf

@@ -1,14 +1,21 @@
 // sc_batch.hip -- many independent collision LCPs (each with its own
 // assembled M) solved by Algorithm 1 in one persistent launch (gfx950).
 //
-// The grid (one workgroup per CU) splits into teams of `team` workgroups
-// that share one XCD, so a team barrier stays inside one L2 and needs no
-// write-back. Team leaders take instances from a work queue ordered by
-// nonzeros, largest first (greedy list scheduling); every member then runs
-// Algorithm 1 on its nnz-balanced share of the instance's slices, with the
-// instance's M partly resident in LDS, exactly as the single-instance
-// solver does over the whole grid. An instance's arithmetic depends only on
-// the team size, not on which team takes it, so results are reproducible.
+// The grid (one workgroup per CU) splits into teams of workgroups that share
+// one XCD, so a team barrier stays inside one L2 and needs no write-back.
+// Team leaders take instances from a work queue ordered by nonzeros, largest
+// first (greedy list scheduling); every member then runs Algorithm 1 on its
+// nnz-balanced share of the instance's slices, with the instance's M partly
+// resident in LDS, exactly as the single-instance solver does over the whole
+// grid. Either every instance gets the same team size, or each queue
+// position k has a size class t_k (a power of two that grows with the
+// instance's nonzeros, non-increasing along the queue): teams start as large
+// as the classes allow and, when the instance a team takes belongs to a
+// smaller class, halve until they fit it, the lower half keeping the
+// instance and the upper half going back to the queue. So the largest
+// instances, which set the critical path, get many workgroups and the many
+// small ones few. An instance's arithmetic depends only on its team size, not
+// on which team takes it, so results are reproducible.
 // With the adjoint enabled, the team then differentiates the instance's
 // converged solution (the implicit adjoint on its active set, not in the
 // paper): F_c = D gamma and U_c, the masked right-hand side, the CG on M_AA
@@ -40,6 +47,9 @@ namespace {
 
 constexpr int kMaxTeam = 32;            // workgroups of one XCD (256 CUs / 8)
 constexpr int kTeamPartHalf = 4 * kMaxTeam;
+constexpr int kXcdCount = 8;             // XCDs of the device the grid spans
+constexpr long long kTuneTarget0 = 4096;  // autotuner: nonzeros per workgroup 4096 * 2^i
+constexpr int kTunePolicies = 12;         // 6 size-class targets, 6 single team sizes
 
 struct BatchDesc {
     MatView M;
@@ -71,11 +81,12 @@ struct alignas(256) BatchCtl {
 struct BatchArgs {
     const BatchDesc *items;
     const int *order;       // queue position -> instance, by nonzeros, descending
+    const int *tcls;        // queue position -> team size of that instance
     SolveCtrl *ctrl;        // [count], per instance
     BatchCtl *ctl;
-    TeamSync *tsync;        // [teams]
-    double *part;           // [teams][2 * kTeamPartHalf]
-    int count, team, warm, cache;
+    TeamSync *tsync;        // [team-tree nodes]
+    double *part;           // [team-tree nodes][2 * kTeamPartHalf]
+    int count, team, warm, cache;  // team: the initial team size
     double tol;
     int max_iter, bb;
     int adjoint, adj_max_iter;  // adjoint: 0 none, 1 dL/dF = D gamma (+ dL/dgamma), 2 dL/dgamma
@@ -83,16 +94,33 @@ struct BatchArgs {
     CgCtrl *cgctrl;             // [count]
 };
 
+// Team size of an instance with `nnz` nonzeros: the smallest power of two
+// t with t * target >= nnz, within [1, tmax]; tmax when target <= 0 (one
+// size for every instance).
+__device__ int team_class(long long nnz, long long target, int tmax) {
+    if (target <= 0) return tmax;
+    const long long need = (nnz + target - 1) / target;
+    int t = 1;
+    while (t < tmax && t < need) t <<= 1;
+    return t;
+}
+
 // Clears the queue, barrier counters and per-instance results (an instance
-// no team reached keeps SC_ERR_TIMEOUT).
-__global__ void k_batch_reset(BatchCtl *ctl, TeamSync *ts, int nteams, SolveCtrl *ctrl,
-                              CgCtrl *cg, int count) {
+// no team reached keeps SC_ERR_TIMEOUT), and sets the team size of every
+// queue position for both launches from its nonzeros (qnnz).
+__global__ void k_batch_reset(BatchCtl *ctl, TeamSync *ts, int nnodes, SolveCtrl *ctrl,
+                              CgCtrl *cg, int count, const long long *qnnz, int *tcls,
+                              long long target_f, int tmax_f, long long target_a, int tmax_a) {
     unsigned *c = reinterpret_cast<unsigned *>(ctl);  // one block per stage
     for (int k = threadIdx.x; k < static_cast<int>(2 * sizeof(BatchCtl) / 4); k += blockDim.x)
         c[k] = 0u;
     unsigned *t = reinterpret_cast<unsigned *>(ts);
-    const long long nt = 2LL * nteams * (sizeof(TeamSync) / 4);  // one set per stage
+    const long long nt = 2LL * nnodes * (sizeof(TeamSync) / 4);  // one set per stage
     for (long long k = threadIdx.x; k < nt; k += blockDim.x) t[k] = 0u;
+    for (int k = threadIdx.x; k < count; k += blockDim.x) {
+        tcls[k] = team_class(qnnz[k], target_f, tmax_f);
+        tcls[count + k] = team_class(qnnz[k], target_a, tmax_a);
+    }
     for (int k = threadIdx.x; k < count; k += blockDim.x) {
         ctrl[k] = SolveCtrl{};
         ctrl[k].status = SC_ERR_TIMEOUT;
@@ -106,7 +134,8 @@ __global__ void k_batch_reset(BatchCtl *ctl, TeamSync *ts, int nteams, SolveCtrl
 // After a build: each instance's row and slice counts into its descriptor
 // (none for an instance whose build failed) and the work order by nonzeros,
 // largest first, ties by index (the host's order for prebuilt batches).
-__global__ void k_batch_finalize(BatchDesc *items, const BuildOut *out, int *order, int count) {
+__global__ void k_batch_finalize(BatchDesc *items, const BuildOut *out, int *order,
+                                 long long *qnnz, int count) {
     for (int k = threadIdx.x; k < count; k += blockDim.x) {
         const bool ok = out[k].status == SC_OK;
         BatchDesc &d = items[k];
@@ -122,6 +151,7 @@ __global__ void k_batch_finalize(BatchDesc *items, const BuildOut *out, int *ord
             r += nj > nk || (nj == nk && j < k);
         }
         order[r] = k;
+        qnnz[r] = nk;
     }
 }
 
@@ -173,7 +203,7 @@ template <int R, int BS, int STAGE>
 __global__ void __launch_bounds__(BS) k_bbpgd_batch(BatchArgs A) {
     __shared__ int sh[4];
     BatchCtl *ctl = A.ctl;
-    const int t = A.team;
+    int t = A.team;
     // team formation: slot of this workgroup within its XCD, then teams of t
     // consecutive slots in each XCD (workgroups left over sit out)
     if (threadIdx.x == 0) {
@@ -191,26 +221,49 @@ __global__ void __launch_bounds__(BS) k_bbpgd_batch(BatchArgs A) {
         sh[1] = s % t;                                     // member
     }
     __syncthreads();
-    const int team = sh[0], member = sh[1];
+    const int team0 = sh[0];
+    int member = sh[1];
     __syncthreads();
-    if (team < 0) return;
-    TeamBarrier tb{A.tsync + team, &ctl->err[0], static_cast<unsigned>(t), 0u};
-    double *part = A.part + static_cast<long long>(team) * 2 * kTeamPartHalf;
+    if (team0 < 0) return;
+    // A team is a node of its initial team's binary tree (heap numbering:
+    // 1 is the initial team, 2v and 2v + 1 the halves of v), so every
+    // sub-team has a barrier and partial sums of its own.
+    int node = 1;
+    auto node_id = [&]() { return team0 * 2 * A.team + node; };
+    TeamBarrier tb{A.tsync + node_id(), &ctl->err[0], static_cast<unsigned>(t), 0u};
+    double *part = A.part + static_cast<long long>(node_id()) * 2 * kTeamPartHalf;
     for (;;) {
         if (member == 0 && threadIdx.x == 0) {
             const unsigned k =
                 __hip_atomic_fetch_add(&ctl->next[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             sh[2] = static_cast<int>(k);
             if (t > 1)
-                __hip_atomic_store(&A.tsync[team].item[0], k, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&tb.s->item[0], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         const bool ok = tb.sync();
-        if (threadIdx.x == 0 && t > 1) sh[2] = static_cast<int>(ld_relaxed(&A.tsync[team].item[0]));
+        if (threadIdx.x == 0 && t > 1) sh[2] = static_cast<int>(ld_relaxed(&tb.s->item[0]));
         __syncthreads();
         const int k = sh[2];
         __syncthreads();
         if (!ok || k >= A.count) break;
+        // halve down to the instance's team size: the lower half keeps it,
+        // the upper half (a team of its own) goes back to the queue
+        const int tk = min(A.tcls[k], t);
+        bool handed_on = false;
+        while (t > tk) {
+            const int half = t >> 1;
+            const bool upper = member >= half;
+            node = 2 * node + (upper ? 1 : 0);
+            member -= upper ? half : 0;
+            t = half;
+            tb = TeamBarrier{A.tsync + node_id(), &ctl->err[0], static_cast<unsigned>(t), 0u};
+            part = A.part + static_cast<long long>(node_id()) * 2 * kTeamPartHalf;
+            if (upper) {
+                handed_on = true;
+                break;
+            }
+        }
+        if (handed_on) continue;
         const int item = A.order[k];
         const BatchDesc D = A.items[item];
         const SliceChunk ch = slice_chunk(D.M, member, t);
@@ -284,9 +337,15 @@ struct sc_batch {
     int count = 0;
     std::vector<int32_t> counts;       // rows per instance
     BatchArgs args{};
-    int nteams_max = 0;
+    int nnodes = 0;                    // team-tree nodes per launch (2 per workgroup)
     int team = 1, block = 1024, grid = 0;
     int team_adj = 1;                  // team size of the adjoint launch
+    long long target = 0, target_adj = 0;  // nonzeros per workgroup of the size
+                                           // classes (0: `team` for every instance)
+    int tmax = kMaxTeam;               // initial team size with size classes: the
+                                       // workgroups of one XCD, at most 32
+    long long *qnnz = nullptr;         // [count] nonzeros per queue position
+    int *tcls = nullptr;               // [2][count] team size per queue position
     size_t dyn = 0;
     const void *fn = nullptr, *fn_adj = nullptr;
     bool build = false;
@@ -296,13 +355,13 @@ struct sc_batch {
     int *order = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    float tune_ms[6] = {0, 0, 0, 0, 0, 0};      // autotuner: build + forward per team size
-    float tune_adj_ms[6] = {0, 0, 0, 0, 0, 0};  // autotuner: adjoint launch per team size
+    float tune_ms[kTunePolicies] = {};      // autotuner: build + forward per policy
+    float tune_adj_ms[kTunePolicies] = {};  // autotuner: adjoint launch per policy
 };
 
 namespace {
 
-size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nteams, bool adj,
+size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nnodes, bool adj,
                       bool build) {
     const size_t nd = static_cast<size_t>(std::max(count, 1));
     size_t b = 0;
@@ -311,8 +370,10 @@ size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nteams, boo
         for (int32_t k = 0; k < count; ++k)
             b += 8 * 256 + sizeof(double) * adj_doubles(items[k], build);
     b += align_up(2 * sizeof(BatchCtl), 256);
-    b += align_up(2 * sizeof(TeamSync) * static_cast<size_t>(nteams), 256);
-    b += align_up(sizeof(double) * 2 * kTeamPartHalf * static_cast<size_t>(nteams), 256);
+    b += align_up(2 * sizeof(TeamSync) * static_cast<size_t>(nnodes), 256);
+    b += align_up(sizeof(double) * 2 * kTeamPartHalf * static_cast<size_t>(nnodes), 256);
+    b += align_up(sizeof(long long) * nd, 256);
+    b += align_up(2 * sizeof(int) * nd, 256);
     b += align_up(sizeof(BatchDesc) * nd, 256);
     b += align_up(sizeof(int) * nd, 256);
     b += align_up(sizeof(SolveCtrl) * nd, 256);
@@ -324,24 +385,28 @@ size_t batch_ws_bytes(int32_t count, const sc_batch_item *items, int nteams, boo
 
 // `mid` (optional) is recorded between the forward and the adjoint launch.
 int enqueue(sc_batch *b, hipStream_t s, hipEvent_t mid = nullptr) {
-    const int nteams = b->nteams_max;
     if (b->build) {
         const int rc = batch_build_enqueue(b->bld, s);
         if (rc != SC_OK) return rc;
-        k_batch_finalize<<<1, 1024, 0, s>>>(b->descs, b->bld.out, b->order, b->count);
+        k_batch_finalize<<<1, 1024, 0, s>>>(b->descs, b->bld.out, b->order, b->qnnz, b->count);
     }
-    k_batch_reset<<<1, 256, 0, s>>>(b->args.ctl, b->args.tsync, nteams, b->args.ctrl,
-                                     b->args.adjoint ? b->args.cgctrl : nullptr, b->count);
+    const int t0 = b->target > 0 ? b->tmax : b->team;
+    const int t0a = b->target_adj > 0 ? b->tmax : b->team_adj;
+    k_batch_reset<<<1, 256, 0, s>>>(b->args.ctl, b->args.tsync, b->nnodes, b->args.ctrl,
+                                     b->args.adjoint ? b->args.cgctrl : nullptr, b->count,
+                                     b->qnnz, b->tcls, b->target, t0, b->target_adj, t0a);
     BatchArgs a = b->args;
-    a.team = b->team;
+    a.team = t0;
+    a.tcls = b->tcls;
     void *args[] = {&a};
     SC_HIP_TRY(hipLaunchCooperativeKernel(b->fn, dim3(b->grid), dim3(b->block), args, b->dyn, s));
     if (mid) SC_HIP_TRY(hipEventRecord(mid, s));
     if (b->args.adjoint) {
         BatchArgs c = a;
-        c.team = b->team_adj;
+        c.team = t0a;
+        c.tcls = b->tcls + b->count;
         c.ctl = b->args.ctl + 1;
-        c.tsync = b->args.tsync + b->nteams_max;
+        c.tsync = b->args.tsync + b->nnodes;
         void *cargs[] = {&c};
         SC_HIP_TRY(hipLaunchCooperativeKernel(b->fn_adj, dim3(b->grid), dim3(b->block), cargs,
                                               b->dyn, s));
@@ -358,7 +423,8 @@ extern "C" size_t sc_batch_workspace_bytes(int32_t count, const sc_batch_item *i
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 1024;
-    return batch_ws_bytes(count, items, std::max(cus, 1), opts->adjoint != 0, opts->build != 0);
+    return batch_ws_bytes(count, items, 2 * std::max(cus, 1), opts->adjoint != 0,
+                          opts->build != 0);
 }
 
 extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const sc_batch_opts *opts,
@@ -366,7 +432,9 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     if (!out || !opts || count < 0 || (count > 0 && !items)) return SC_ERR_INVALID;
     *out = nullptr;
     if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->bb < 1 || opts->bb > 3 ||
-        !team_ok(opts->team) || !team_ok(opts->adjoint_team) ||
+        !team_ok(opts->team) || !team_ok(opts->adjoint_team) || opts->nnz_per_workgroup < 0 ||
+        opts->adjoint_nnz_per_workgroup < 0 || (opts->team > 0 && opts->nnz_per_workgroup > 0) ||
+        (opts->adjoint_team > 0 && opts->adjoint_nnz_per_workgroup > 0) ||
         !block_ok(opts->block) || opts->adjoint < 0 || opts->adjoint > 2 ||
         (opts->adjoint && (!(opts->adjoint_tol > 0.0) || opts->adjoint_max_iter < 0)) ||
         opts->build < 0 || opts->build > 1)
@@ -436,21 +504,25 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     }
     b->grid = std::min(persistent_grid(b->fn, b->block, 0, b->dyn),
                        persistent_grid(b->fn_adj, b->block, 0, b->dyn));
-    b->nteams_max = b->grid;
+    b->nnodes = 2 * b->grid;
+    // size classes start from teams of one XCD's workgroups (a power of two)
+    while (b->tmax > 1 && b->tmax * kXcdCount > b->grid) b->tmax >>= 1;
     if (b->grid < 1) {
         delete b;
         return SC_ERR_HIP;
     }
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 ||
-        ws_bytes < batch_ws_bytes(count, items, b->nteams_max, adj, build)) {
+        ws_bytes < batch_ws_bytes(count, items, b->nnodes, adj, build)) {
         delete b;
         return SC_ERR_WORKSPACE;
     }
     Carver cv{static_cast<char *>(ws), ws_bytes};
     BatchArgs &a = b->args;
     a.ctl = cv.take<BatchCtl>(2);
-    a.tsync = cv.take<TeamSync>(2 * static_cast<size_t>(b->nteams_max));
-    a.part = cv.take<double>(2 * kTeamPartHalf * static_cast<size_t>(b->nteams_max));
+    a.tsync = cv.take<TeamSync>(2 * static_cast<size_t>(b->nnodes));
+    a.part = cv.take<double>(2 * kTeamPartHalf * static_cast<size_t>(b->nnodes));
+    b->qnnz = cv.take<long long>(static_cast<size_t>(std::max(count, 1)));
+    b->tcls = cv.take<int>(2 * static_cast<size_t>(std::max(count, 1)));
     BatchDesc *d_descs = cv.take<BatchDesc>(static_cast<size_t>(std::max(count, 1)));
     int *d_order = cv.take<int>(static_cast<size_t>(std::max(count, 1)));
     a.ctrl = cv.take<SolveCtrl>(static_cast<size_t>(std::max(count, 1)));
@@ -490,6 +562,8 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     std::vector<int> order(static_cast<size_t>(count));
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nnz[x] > nnz[y]; });
+    std::vector<long long> qnnz(static_cast<size_t>(count));
+    for (int32_t r = 0; r < count; ++r) qnnz[r] = nnz[order[r]];
     a.items = d_descs;
     a.order = d_order;
     a.count = count;
@@ -506,40 +580,61 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
                            s) != hipSuccess ||
             hipMemcpyAsync(d_order, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s) !=
                 hipSuccess ||
+            hipMemcpyAsync(b->qnnz, qnnz.data(), sizeof(long long) * count,
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             delete b;
             return SC_ERR_HIP;
         }
     }
-    if (opts->team > 0) {
-        b->team = opts->team;
-        b->team_adj = opts->adjoint_team > 0 ? opts->adjoint_team : opts->team;
-    } else {
-        // autotuner: solve the batch once per team size (forward and adjoint
-        // launches with that size, timed apart), keep the fastest of each.
-        // The adjoint is latency-bound (a few dozen CG iterations per
-        // instance), so its best team can differ from the forward's.
+    // the forward's policy: one team size, size classes, or tuned classes
+    b->team = opts->team > 0 ? opts->team : b->tmax;
+    b->target = opts->team > 0 ? 0 : opts->nnz_per_workgroup;
+    const bool tune = opts->team == 0 && opts->nnz_per_workgroup == 0;
+    // the adjoint's: its own if given, else the forward's (tuned with it)
+    const bool adj_own = opts->adjoint_team > 0 || opts->adjoint_nnz_per_workgroup > 0;
+    b->team_adj = opts->adjoint_team > 0 ? opts->adjoint_team : adj_own ? b->tmax : b->team;
+    b->target_adj = opts->adjoint_team > 0 ? 0 : adj_own ? opts->adjoint_nnz_per_workgroup
+                                                         : b->target;
+    if (tune) {
+        // autotuner: solve the batch once per policy (size classes for
+        // 4096 * 2^i nonzeros per workgroup, then one team size 1, 2, ..., 32),
+        // the forward and adjoint launches timed apart, and keep the fastest
+        // policy of each launch. Team sizes above one XCD's workgroups cannot
+        // form and are skipped.
         hipEvent_t e[3] = {nullptr, nullptr, nullptr};
         int rc = SC_OK;
         for (auto &ev : e)
             if (rc == SC_OK && hipEventCreate(&ev) != hipSuccess) rc = SC_ERR_HIP;
-        const int sizes[6] = {1, 2, 4, 8, 16, 32};
-        for (int i = 0; i < 6 && rc == SC_OK; ++i) {
-            b->team = b->team_adj = sizes[i];
+        auto cfg_team = [&](int i) { return i < 6 ? b->tmax : 1 << (i - 6); };
+        auto cfg_target = [&](int i) { return i < 6 ? kTuneTarget0 << i : 0LL; };
+        int pf = -1, pa = -1;
+        for (int i = 0; i < kTunePolicies && rc == SC_OK; ++i) {
+            if (cfg_team(i) > b->tmax) continue;
+            b->team = cfg_team(i);
+            b->target = cfg_target(i);
+            if (!adj_own) {
+                b->team_adj = b->team;
+                b->target_adj = b->target;
+            }
             rc = hipEventRecord(e[0], s) == hipSuccess ? enqueue(b, s, e[1]) : SC_ERR_HIP;
             if (rc == SC_OK && (hipEventRecord(e[2], s) != hipSuccess ||
                                 hipEventSynchronize(e[2]) != hipSuccess ||
                                 hipEventElapsedTime(&b->tune_ms[i], e[0], e[1]) != hipSuccess ||
                                 hipEventElapsedTime(&b->tune_adj_ms[i], e[1], e[2]) != hipSuccess))
                 rc = SC_ERR_HIP;
+            if (pf < 0 || b->tune_ms[i] < b->tune_ms[pf]) pf = i;
+            if (pa < 0 || b->tune_adj_ms[i] < b->tune_adj_ms[pa]) pa = i;
         }
-        int pf = 0, pa = 0;
-        for (int i = 1; i < 6; ++i) {
-            if (b->tune_ms[i] < b->tune_ms[pf]) pf = i;
-            if (b->tune_adj_ms[i] < b->tune_adj_ms[pa]) pa = i;
+        if (rc == SC_OK && pf < 0) rc = SC_ERR_HIP;
+        if (rc == SC_OK) {
+            b->team = cfg_team(pf);
+            b->target = cfg_target(pf);
+            if (!adj_own) {
+                b->team_adj = adj ? cfg_team(pa) : b->team;
+                b->target_adj = adj ? cfg_target(pa) : b->target;
+            }
         }
-        b->team = sizes[pf];
-        b->team_adj = !adj ? b->team : opts->adjoint_team > 0 ? opts->adjoint_team : sizes[pa];
         for (auto &ev : e)
             if (ev) (void)hipEventDestroy(ev);
         if (rc != SC_OK) {
@@ -637,13 +732,22 @@ extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_stats *adj,
         info->block = b->block;
         info->grid = b->grid;
         info->lds_entries_per_wave = b->args.cache / (b->block / kWave);
-        for (int i = 0; i < 6; ++i) info->tune_ms[i] = b->tune_ms[i];
+        for (int i = 0; i < kTunePolicies; ++i) info->tune_ms[i] = b->tune_ms[i];
         info->team_adjoint = b->team_adj;
-        for (int i = 0; i < 6; ++i) info->tune_adjoint_ms[i] = b->tune_adj_ms[i];
+        for (int i = 0; i < kTunePolicies; ++i) info->tune_adjoint_ms[i] = b->tune_adj_ms[i];
+        info->nnz_per_workgroup = static_cast<int32_t>(b->target);
+        info->adjoint_nnz_per_workgroup = static_cast<int32_t>(b->target_adj);
     }
     if (b->count == 0) return SC_OK;
     std::vector<SolveCtrl> h(static_cast<size_t>(b->count));
     SC_HIP_TRY(hipMemcpyAsync(h.data(), b->args.ctrl, sizeof(SolveCtrl) * b->count,
+                              hipMemcpyDeviceToHost, s));
+    // team size per instance: the class of its queue position (capped by the
+    // initial team size, as the kernel does)
+    std::vector<int> cls(2 * static_cast<size_t>(b->count)), ord(static_cast<size_t>(b->count));
+    SC_HIP_TRY(hipMemcpyAsync(cls.data(), b->tcls, sizeof(int) * 2 * b->count,
+                              hipMemcpyDeviceToHost, s));
+    SC_HIP_TRY(hipMemcpyAsync(ord.data(), b->order, sizeof(int) * b->count,
                               hipMemcpyDeviceToHost, s));
     std::vector<CgCtrl> hc(static_cast<size_t>(b->count));
     if (adj && b->args.adjoint)
@@ -654,6 +758,14 @@ extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_stats *adj,
         SC_HIP_TRY(hipMemcpyAsync(ho.data(), b->bld.out, sizeof(BuildOut) * b->count,
                                   hipMemcpyDeviceToHost, s));
     SC_HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int> tf(static_cast<size_t>(b->count)), ta(static_cast<size_t>(b->count));
+    const int t0 = b->target > 0 ? b->tmax : b->team;
+    const int t0a = b->target_adj > 0 ? b->tmax : b->team_adj;
+    for (int r = 0; r < b->count; ++r) {
+        if (ord[r] < 0 || ord[r] >= b->count) return SC_ERR_HIP;
+        tf[ord[r]] = std::min(cls[r], t0);
+        ta[ord[r]] = std::min(cls[b->count + r], t0a);
+    }
     // an instance whose build failed reports the build's status
     for (int k = 0; k < static_cast<int>(ho.size()); ++k)
         if (ho[k].status != SC_OK) {
@@ -670,7 +782,7 @@ extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_stats *adj,
             adj[k].mvops = hc[k].iters + 1;
             adj[k].residual = hc[k].res;
             adj[k].alpha = hc[k].alpha;
-            adj[k].grid = b->team_adj;
+            adj[k].grid = ta[k];
             adj[k].block = b->block;
             adj[k].op = SC_OP_MATRIX;
             adj[k].n_active = -1;
@@ -685,7 +797,7 @@ extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_stats *adj,
         st.residual = h[k].res;
         st.alpha = h[k].alpha;
         st.n_degenerate = h[k].ndegen;
-        st.grid = b->team;
+        st.grid = tf[k];
         st.block = b->block;
         st.op = SC_OP_MATRIX;
         st.slices_per_wave = 1;

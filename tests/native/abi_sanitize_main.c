@@ -315,6 +315,7 @@ static void gpu_dry(hipStream_t s) {
     OK(sc_build_contacts(&S.p, &box, delta, u_nc, dt, &K.c, K.ws, K.ws_bytes, s));
     const int nc = K.c.count;
     EXPECT(nc > n);
+    printf("[dry] contacts built: %d\n", nc);
     K.c.mat_bytes = sc_matrix_bytes(nc, K.c.nnz);
     K.c.mat = dev_alloc(K.c.mat_bytes);
     OK(sc_assemble_matrix(&S.p, &K.c, s));
@@ -336,6 +337,7 @@ static void gpu_dry(hipStream_t s) {
         SOLVED(sc_solve_lcp(&S.p, &K.c, &o, gamma, g, f_c, u_c, &st, K.ws, K.ws_bytes, s));
         EXPECT(st.status == SC_OK);
     }
+    printf("[dry] matrix solves done\n");
     o.bb = 1;
     o.op = SC_OP_CHAIN;
     SOLVED(sc_solve_lcp(&S.p, &K.c, &o, gamma2, g2, NULL, NULL, &st, K.ws, K.ws_bytes, s));
@@ -362,6 +364,7 @@ static void gpu_dry(hipStream_t s) {
     o.spin_limit = 0;
     SOLVED(sc_solve_lcp(&S.p, &K.c, &o, gamma, g, f_c, u_c, &st, K.ws, K.ws_bytes, s));
 
+    printf("[dry] chain, no-alloc, async and time-out solves done\n");
     /* adjoint of L = 1/2 ||F_c||^2 */
     double *dq = dev_alloc(sizeof(double) * nc), *dpos = dev_alloc(sizeof(double) * 3 * n);
     sc_adjoint_opts ao = {1e-10, 10000, 0, 0, 0, 0, 0, 0};
@@ -371,6 +374,7 @@ static void gpu_dry(hipStream_t s) {
     SOLVED(sc_solve_lcp_adjoint(&S.p, &box, &K.c, u_nc, dt, gamma, gamma, NULL, dq, dpos, &ao,
                                 &st, K.ws, K.ws_bytes, s));
 
+    printf("[dry] adjoints done\n");
     /* the dry mobility through the function interface */
     {
         size_t wb = sc_solve_mob_work_bytes(n, cap), wa = sc_adjoint_mob_work_bytes(n, cap);
@@ -384,6 +388,7 @@ static void gpu_dry(hipStream_t s) {
         HIP(hipFree(w));
     }
 
+    printf("[dry] function-mobility solve and adjoint done\n");
     /* time stepping: warm start across a step */
     OK(sc_quat_from_axis(n, S.axis, S.quat, s));
     OK(sc_advance(n, S.pos, S.quat, S.axis, u_nc, u_c, dt, s));
@@ -421,6 +426,7 @@ static void gpu_dry(hipStream_t s) {
         EXPECT(wb > 0);
         void *w = dev_alloc(wb);
         sc_batch *b = NULL;
+        printf("[dry] time step done; batch of two\n");
         OK(sc_batch_create(2, it, &bo, w, wb, s, &b));
         OK(sc_batch_solve(b, s));
         OK(sc_batch_graph_launch(b, s));
@@ -433,6 +439,7 @@ static void gpu_dry(hipStream_t s) {
         sc_batch_destroy(b);
         HIP(hipFree(w));
 
+        printf("[dry] batch (eager, graph) done\n");
         /* built on the device: its own output buffers */
         contacts_t KB = alloc_contacts(n, cap, (size_t)K.c.nnz * 2);
         sc_batch_item ib = it[0];
@@ -499,7 +506,9 @@ static void gpu_rpy(hipStream_t s) {
     sc_stats st;
     SOLVED(sc_solve_lcp_mob(&S.p, &K.c, &o, sc_rpy_apply, &r, 0, gamma, g, f_c, u_c, &st, w,
                             wmax, s));
+    printf("[rpy] %d contacts; function-mobility solve done\n", nc);
     SOLVED(sc_solve_lcp_rpy(&S.p, &K.c, &r, &o, gamma, g, f_c, u_c, &st, w, wmax, s));
+    printf("[rpy] persistent solve done\n");
     OK(sc_rpy_grad(&r, n, f_c, S.f, gr, s));
     sc_adjoint_opts ao = {1e-10, 10000, 0, 0, 0, 0, 0, 0};
     SOLVED(sc_solve_lcp_adjoint_mob(&S.p, &box, &K.c, u_nc, S.f, dt, gamma, NULL, f_c,

@@ -167,24 +167,27 @@ def test_batch_adjoint_matches_single_instance_and_oracle(team, adjoint_team):
 
 def test_batch_autotune_picks_each_launch_and_reproduces():
     """With team = 0 and the adjoint on, the autotuner times the forward and
-    the adjoint launch apart for every team size and keeps the fastest of
-    each; a batch created with the two picked sizes gives bitwise the same
-    solutions and gradients."""
+    the adjoint launch apart for every nonzeros-per-workgroup target and
+    keeps the fastest of each; a batch created with the two picked targets
+    gives bitwise the same solutions and gradients."""
     import paper_1909_06623_amd as sc
     sus, items = _instances(6, 1200, seed=W.SEED_BASE + 705, full=True)
     _say(f"batch adjoint autotune: {len(items)} instances")
     b = sc.Batch(items, tol=1e-10, team=0, adjoint=1, adjoint_tol=1e-12)
     b.solve()
     st, adj, info = b.stats()
-    sizes = (1, 2, 4, 8, 16, 32)
-    assert info["team"] in sizes and info["team_adjoint"] in sizes
+    # policies: size classes for 4096 * 2^i nonzeros per workgroup, then one
+    # team size 2^i
+    def index(target, team):
+        return [4096 << i for i in range(6)].index(target) if target else 6 + team.bit_length() - 1
+    pol = sc.Batch.tuned_policy(info)
     assert all(t > 0 for t in info["tune_ms"]) and all(t > 0 for t in info["tune_adjoint_ms"])
-    assert info["tune_ms"][sizes.index(info["team"])] == min(info["tune_ms"])
-    assert info["tune_adjoint_ms"][sizes.index(info["team_adjoint"])] == \
-        min(info["tune_adjoint_ms"])
+    assert info["tune_ms"][index(info["nnz_per_workgroup"], info["team"])] == \
+        min(info["tune_ms"])
+    assert info["tune_adjoint_ms"][index(info["adjoint_nnz_per_workgroup"],
+                                         info["team_adjoint"])] == min(info["tune_adjoint_ms"])
     assert all(x["status"] == 0 for x in st) and all(x["status"] == 0 for x in adj)
-    f = sc.Batch(items, tol=1e-10, team=info["team"], adjoint=1, adjoint_tol=1e-12,
-                 adjoint_team=info["team_adjoint"])
+    f = sc.Batch(items, tol=1e-10, adjoint=1, adjoint_tol=1e-12, **pol)
     f.solve()
     torch.cuda.synchronize()
     assert all(torch.equal(x, y) for x, y in zip(b.gamma, f.gamma))
@@ -192,6 +195,56 @@ def test_batch_autotune_picks_each_launch_and_reproduces():
     assert all(torch.equal(x, y) for x, y in zip(b.dL_dpos, f.dL_dpos))
     b.close()
     f.close()
+
+
+def _team_class(nnz, target, tmax=32):
+    t = 1
+    while t < tmax and t * target < nnz:
+        t *= 2
+    return t
+
+
+def test_batch_size_classes_match_oracle_and_single_instances():
+    """Size classes: instance k runs on the smallest power of two t with
+    t * nnz_per_workgroup >= its nonzeros; teams of 32 halve as the queue
+    reaches smaller classes. With a small target the instances spread over
+    several classes; every solution matches the oracle, each instance's team
+    size is its class, the forward and adjoint are bitwise those of a batch
+    that holds that instance alone at the same team size, and a graph replay
+    repeats the eager results bitwise."""
+    import paper_1909_06623_amd as sc
+    sus, items = _instances(12, 2500, seed=W.SEED_BASE + 706, full=True)
+    target = 1500
+    _say(f"batch size classes: {len(items)} instances, target {target}")
+    b = sc.Batch(items, tol=1e-10, team=0, nnz_per_workgroup=target, adjoint=1,
+                 adjoint_tol=1e-12, adjoint_nnz_per_workgroup=4 * target)
+    b.solve()
+    st, adj, info = b.stats()
+    assert info["nnz_per_workgroup"] == target and info["adjoint_nnz_per_workgroup"] == 4 * target
+    want = [_team_class(con.nnz, target) for _, con, _, _, _ in items]
+    want_a = [_team_class(con.nnz, 4 * target) for _, con, _, _, _ in items]
+    assert [x["grid"] for x in st] == want and [x["grid"] for x in adj] == want_a
+    assert len(set(want)) >= 3, want
+    assert all(x["status"] == 0 for x in st) and all(x["status"] == 0 for x in adj)
+    for s, (P, con, _, _, _), gam, g in zip(sus, items, b.gamma, b.g):
+        _check_instance(s, con, gam, g, 1e-6, 1e-9)
+    # each instance alone at its class's team size: bitwise the same
+    for k in (0, len(items) // 2, len(items) - 1):
+        one = sc.Batch([items[k]], tol=1e-10, team=want[k], adjoint=1, adjoint_tol=1e-12,
+                       adjoint_team=want_a[k])
+        one.solve()
+        torch.cuda.synchronize()
+        assert torch.equal(one.gamma[0], b.gamma[k]) and torch.equal(one.dL_dq[0], b.dL_dq[k])
+        assert torch.equal(one.dL_dpos[0], b.dL_dpos[k])
+        one.close()
+    g1 = [x.clone() for x in b.gamma]
+    d1 = [x.clone() for x in b.dL_dpos]
+    b.graph_solve()
+    b.graph_solve()
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, x) for a, x in zip(g1, b.gamma))
+    assert all(torch.equal(a, x) for a, x in zip(d1, b.dL_dpos))
+    b.close()
 
 
 def test_batch_status_paths_eager_and_graph():

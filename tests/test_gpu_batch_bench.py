@@ -1,9 +1,9 @@
 """The batched launch bench.py times, checked instance by instance against
 the oracle: the 512 suspensions of uneven size (N log-uniform in [200,
 20000], spheres and rods), contacts and M built on the device, the team
-size chosen by the autotuner, Algorithm 1 (section 3.3.1) to 1e-6 and the
+policy (size classes or one team size) chosen by the autotuner, Algorithm 1 (section 3.3.1) to 1e-6 and the
 adjoint of L = 1/2 ||D gamma||^2 to a CG tolerance of 1e-8, replayed as one
-HIP graph. An instance's arithmetic depends only on the team size, so these
+HIP graph. An instance's arithmetic depends only on its team size, so these
 are the results the benchmark's replays produce.
 
 Forty instances are compared (the 24 largest and 16 drawn from the rest):
@@ -53,8 +53,9 @@ def test_bench_batched_launch_against_oracle():
     torch.cuda.synchronize()
     st, adj, info = b.stats()
     cnt = b.counts()
-    _say(f"batch: {len(sus)} instances, tuned team {info['team']}, "
-         f"{sum(c for c, _, _ in cnt)} contacts, tune_ms {info['tune_ms']}")
+    _say(f"batch: {len(sus)} instances, tuned policy {sc.Batch.tuned_policy(info)}, "
+         f"{sum(c for c, _, _ in cnt)} contacts, tune_ms {info['tune_ms']}, "
+         f"adjoint {info['tune_adjoint_ms']}")
     assert info["team"] in (1, 2, 4, 8, 16, 32)
     assert all(x["status"] == 0 for x in st), [x["status"] for x in st if x["status"]]
     assert all(x["status"] == 0 for x in adj)
