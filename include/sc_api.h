@@ -375,7 +375,8 @@ typedef struct sc_batch_opts {
     int32_t team;           /* workgroups per instance, all on one XCD: 1, 2, 4, 8,
                                16 or 32 for every instance; 0 = size classes (see
                                nnz_per_workgroup) */
-    int32_t block;          /* threads per workgroup: 0 (1024), 256, 512 or 1024 */
+    int32_t block;          /* threads per workgroup of the forward launch: 0 (1024),
+                               256, 512 or 1024 */
     int32_t adjoint;        /* 0: solve only; 1: then the adjoint of
                                L = 1/2 ||D gamma||^2 + dL_dgamma . gamma; 2: of the
                                linear loss dL_dgamma . gamma only */
@@ -397,6 +398,8 @@ typedef struct sc_batch_opts {
                                launch apart (overwrites gamma and g) */
     int32_t adjoint_nnz_per_workgroup; /* the same for the adjoint launch (0: see
                                adjoint_team) */
+    int32_t adjoint_block;  /* threads per workgroup of the adjoint launch: 0 (512),
+                               256, 512 or 1024 */
 } sc_batch_opts;
 
 typedef struct sc_batch_info {
@@ -410,6 +413,7 @@ typedef struct sc_batch_info {
     float tune_adjoint_ms[12];      /* autotuner: adjoint launch time, same policies */
     int32_t nnz_per_workgroup;      /* size classes' target used (0: one team size) */
     int32_t adjoint_nnz_per_workgroup;
+    int32_t adjoint_block;          /* threads per workgroup of the adjoint launch */
 } sc_batch_info;
 
 typedef struct sc_batch sc_batch;   /* opaque plan (host memory) */

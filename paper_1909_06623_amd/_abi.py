@@ -100,7 +100,7 @@ class sc_batch_opts(ctypes.Structure):
                 ("adjoint", ctypes.c_int32), ("adjoint_tol", ctypes.c_double),
                 ("adjoint_max_iter", ctypes.c_int32), ("build", ctypes.c_int32),
                 ("adjoint_team", ctypes.c_int32), ("nnz_per_workgroup", ctypes.c_int32),
-                ("adjoint_nnz_per_workgroup", ctypes.c_int32)]
+                ("adjoint_nnz_per_workgroup", ctypes.c_int32), ("adjoint_block", ctypes.c_int32)]
 
 
 class sc_batch_info(ctypes.Structure):
@@ -109,7 +109,8 @@ class sc_batch_info(ctypes.Structure):
                 ("tune_ms", ctypes.c_float * 12), ("team_adjoint", ctypes.c_int32),
                 ("tune_adjoint_ms", ctypes.c_float * 12),
                 ("nnz_per_workgroup", ctypes.c_int32),
-                ("adjoint_nnz_per_workgroup", ctypes.c_int32)]
+                ("adjoint_nnz_per_workgroup", ctypes.c_int32),
+                ("adjoint_block", ctypes.c_int32)]
 
 
 class sc_rpy(ctypes.Structure):

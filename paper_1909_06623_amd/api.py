@@ -670,7 +670,8 @@ class Batch:
     nonzeros of M (at most 32), and with both 0 the target is autotuned.
     ``adjoint_team`` / ``adjoint_nnz_per_workgroup`` do the same for the
     adjoint launch (both 0: the forward's policy, tuned on its own when the
-    forward's is). After ``solve()`` /
+    forward's is). ``block`` / ``adjoint_block``: threads per workgroup of
+    each launch (0: 1024 and 512). After ``solve()`` /
     ``graph_solve()``, ``gamma[k]`` and ``g[k]`` hold each solution and, with
     ``adjoint`` (1: loss 1/2 ||D gamma||^2 + dL_dgamma . gamma, 2: the linear
     term only), ``dL_dq[k]`` and ``dL_dpos[k]`` its gradients.
@@ -687,7 +688,8 @@ class Batch:
     def __init__(self, items, tol=1e-6, max_iter=100000, bb=1, team=0, block=0,
                  gamma0=None, adjoint=0, dL_dgamma=None, adjoint_tol=1e-10,
                  adjoint_max_iter=100000, build=False, capacity=None, nnz_capacity=None,
-                 adjoint_team=0, nnz_per_workgroup=0, adjoint_nnz_per_workgroup=0):
+                 adjoint_team=0, nnz_per_workgroup=0, adjoint_nnz_per_workgroup=0,
+                 adjoint_block=0):
         self._keep = []
         self.gamma, self.g, self.dL_dq, self.dL_dpos = [], [], [], []
         self.build = bool(build)
@@ -753,7 +755,8 @@ class Batch:
                                1 if gamma0 is not None else 0, int(team), int(block),
                                self.adjoint, float(adjoint_tol), int(adjoint_max_iter),
                                1 if self.build else 0, int(adjoint_team),
-                               int(nnz_per_workgroup), int(adjoint_nnz_per_workgroup))
+                               int(nnz_per_workgroup), int(adjoint_nnz_per_workgroup),
+                               int(adjoint_block))
         need = int(A.lib().sc_batch_workspace_bytes(self.count, arr, ctypes.byref(opts)))
         if need == 0:
             raise RuntimeError("sc_batch_workspace_bytes: invalid arguments")
@@ -821,7 +824,8 @@ class Batch:
                "tune_ms": list(info.tune_ms), "team_adjoint": info.team_adjoint,
                "tune_adjoint_ms": list(info.tune_adjoint_ms),
                "nnz_per_workgroup": info.nnz_per_workgroup,
-               "adjoint_nnz_per_workgroup": info.adjoint_nnz_per_workgroup}
+               "adjoint_nnz_per_workgroup": info.adjoint_nnz_per_workgroup,
+               "adjoint_block": info.adjoint_block}
         sts = [st[k].as_dict() for k in range(self.count)]
         adjs = [adj[k].as_dict() for k in range(self.count)] if self.adjoint else None
         return sts, adjs, inf

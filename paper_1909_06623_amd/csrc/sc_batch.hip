@@ -339,6 +339,8 @@ struct sc_batch {
     BatchArgs args{};
     int nnodes = 0;                    // team-tree nodes per launch (2 per workgroup)
     int team = 1, block = 1024, grid = 0;
+    int block_adj = 512, cache_adj = 0;  // the adjoint launch's block and LDS entries
+    size_t dyn_adj = 0;
     int team_adj = 1;                  // team size of the adjoint launch
     long long target = 0, target_adj = 0;  // nonzeros per workgroup of the size
                                            // classes (0: `team` for every instance)
@@ -403,13 +405,14 @@ int enqueue(sc_batch *b, hipStream_t s, hipEvent_t mid = nullptr) {
     if (mid) SC_HIP_TRY(hipEventRecord(mid, s));
     if (b->args.adjoint) {
         BatchArgs c = a;
+        c.cache = b->cache_adj;
         c.team = t0a;
         c.tcls = b->tcls + b->count;
         c.ctl = b->args.ctl + 1;
         c.tsync = b->args.tsync + b->nnodes;
         void *cargs[] = {&c};
-        SC_HIP_TRY(hipLaunchCooperativeKernel(b->fn_adj, dim3(b->grid), dim3(b->block), cargs,
-                                              b->dyn, s));
+        SC_HIP_TRY(hipLaunchCooperativeKernel(b->fn_adj, dim3(b->grid), dim3(b->block_adj),
+                                              cargs, b->dyn_adj, s));
     }
     return SC_OK;
 }
@@ -435,7 +438,7 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
         !team_ok(opts->team) || !team_ok(opts->adjoint_team) || opts->nnz_per_workgroup < 0 ||
         opts->adjoint_nnz_per_workgroup < 0 || (opts->team > 0 && opts->nnz_per_workgroup > 0) ||
         (opts->adjoint_team > 0 && opts->adjoint_nnz_per_workgroup > 0) ||
-        !block_ok(opts->block) || opts->adjoint < 0 || opts->adjoint > 2 ||
+        !block_ok(opts->block) || !block_ok(opts->adjoint_block) || opts->adjoint < 0 || opts->adjoint > 2 ||
         (opts->adjoint && (!(opts->adjoint_tol > 0.0) || opts->adjoint_max_iter < 0)) ||
         opts->build < 0 || opts->build > 1)
         return SC_ERR_INVALID;
@@ -488,22 +491,20 @@ extern "C" int sc_batch_create(int32_t count, const sc_batch_item *items, const 
     b->count = count;
     b->build = build;
     b->block = opts->block ? opts->block : 1024;
+    // the adjoint's state does not fit 1024 threads' registers (it spills),
+    // so its launch defaults to 512
+    b->block_adj = opts->adjoint_block ? opts->adjoint_block : 512;
     b->fn = reinterpret_cast<const void *>(batch_kernel<0>(b->block));
-    b->fn_adj = reinterpret_cast<const void *>(batch_kernel<1>(b->block));
-    int per_block = 0, per_adj = 0;
-    size_t dyn_adj = 0;
+    b->fn_adj = reinterpret_cast<const void *>(batch_kernel<1>(b->block_adj));
+    int per_block = 0;
     if (batch_cache(b->fn, b->block, &per_block, &b->dyn) != hipSuccess ||
-        batch_cache(b->fn_adj, b->block, &per_adj, &dyn_adj) != hipSuccess) {
+        batch_cache(b->fn_adj, b->block_adj, &b->cache_adj, &b->dyn_adj) != hipSuccess) {
         delete b;
         return SC_ERR_HIP;
     }
     // both stages use the smaller LDS share, so that one walk serves both
-    if (per_adj < per_block) {
-        per_block = per_adj;
-        b->dyn = dyn_adj;
-    }
     b->grid = std::min(persistent_grid(b->fn, b->block, 0, b->dyn),
-                       persistent_grid(b->fn_adj, b->block, 0, b->dyn));
+                       persistent_grid(b->fn_adj, b->block_adj, 0, b->dyn_adj));
     b->nnodes = 2 * b->grid;
     // size classes start from teams of one XCD's workgroups (a power of two)
     while (b->tmax > 1 && b->tmax * kXcdCount > b->grid) b->tmax >>= 1;
@@ -732,6 +733,7 @@ extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_stats *adj,
         info->block = b->block;
         info->grid = b->grid;
         info->lds_entries_per_wave = b->args.cache / (b->block / kWave);
+        info->adjoint_block = b->block_adj;
         for (int i = 0; i < kTunePolicies; ++i) info->tune_ms[i] = b->tune_ms[i];
         info->team_adjoint = b->team_adj;
         for (int i = 0; i < kTunePolicies; ++i) info->tune_adjoint_ms[i] = b->tune_adj_ms[i];
@@ -783,7 +785,8 @@ extern "C" int sc_batch_stats(const sc_batch *b, sc_stats *stats, sc_stats *adj,
             adj[k].residual = hc[k].res;
             adj[k].alpha = hc[k].alpha;
             adj[k].grid = ta[k];
-            adj[k].block = b->block;
+            adj[k].block = b->block_adj;
+            adj[k].lds_entries_per_wave = b->cache_adj / (b->block_adj / kWave);
             adj[k].op = SC_OP_MATRIX;
             adj[k].n_active = -1;
         }

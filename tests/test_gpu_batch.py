@@ -112,8 +112,8 @@ def test_batch_empty_and_contactless():
     assert st[0]["mvops"] == 1
 
 
-@pytest.mark.parametrize("team,adjoint_team", [(1, 0), (8, 0), (8, 2)])
-def test_batch_adjoint_matches_single_instance_and_oracle(team, adjoint_team):
+@pytest.mark.parametrize("team,adjoint_team,adjoint_block", [(1, 0, 0), (8, 0, 0), (8, 2, 1024)])
+def test_batch_adjoint_matches_single_instance_and_oracle(team, adjoint_team, adjoint_block):
     """Forward + adjoint of L = 1/2 ||D gamma||^2 for every instance in one
     persistent launch: the gradients equal the single-instance adjoint of the
     batch's own solution (both are the same implicit solve), and agree with
@@ -122,11 +122,13 @@ def test_batch_adjoint_matches_single_instance_and_oracle(team, adjoint_team):
     sus, items = _instances(10, 1500, seed=W.SEED_BASE + 703, full=True)
     _say(f"batch adjoint team={team} adjoint_team={adjoint_team}: {len(items)} instances")
     b = sc.Batch(items, tol=1e-10, team=team, adjoint=1, adjoint_tol=1e-12,
-                 adjoint_team=adjoint_team)
+                 adjoint_team=adjoint_team, adjoint_block=adjoint_block)
     b.solve()
     st, adj, info = b.stats()
     assert info["team"] == team and info["team_adjoint"] == (adjoint_team or team)
+    assert info["block"] == 1024 and info["adjoint_block"] == (adjoint_block or 512)
     assert all(x["grid"] == (adjoint_team or team) for x in adj)
+    assert all(x["block"] == (adjoint_block or 512) for x in adj)
     assert all(x["status"] == 0 for x in st)
     assert all(x["status"] == 0 for x in adj), [x["status"] for x in adj]
     checked = 0
