@@ -122,15 +122,16 @@ def spheres1000(sc, W, torch, np, steps):
                         "dt 1e-3, BBPGD (BB1) to 1e-6",
             "n": s.n, "n_contacts": con.count, "iters": st["iters"], "status": st["status"],
             "ms_per_step": ms, "particles_per_s": s.n / (ms * 1e-3), "solve_kernel_ms": kernel_ms,
-            "us_per_product": 1e3 * kernel_ms / products,
+            "us_per_product": 1e3 * kernel_ms / products, "grid": st["grid"],
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbs / HBM_PEAK_GBS, "traffic": None,
                          "kernel": "k_bbpgd_mat (persistent BBPGD solve)",
                          "bytes_model": "120 n_c + 56 N bytes per product (spheres), (iterations "
                                         "+ 2) products per launch",
                          "bytes_per_product": bytes_iter, "launch_ms": kernel_ms,
-                         "note": "0.2 MB per product: bound by the per-iteration barrier and "
-                                 "reduction latency, not by memory"}}
+                         "note": "0.25 MB per product: bound by the per-iteration latency "
+                                 "(gathers, barrier, reduction), not by memory; the grid is "
+                                 "chosen from nnz(M)"}}
 
 
 def timestepping(sc, W, torch, np, steps):

@@ -138,9 +138,11 @@ typedef struct sc_solve_opts {
     int32_t warm_start;     /* 1: gamma holds gamma_0 on entry; 0: gamma_0 = 0 */
     int32_t lanes_per_particle; /* chain product: 0 (default 4), 1, 2, 4 or 8 lanes sharing
                                    a particle's incidence list */
-    int32_t grid;           /* workgroups of the persistent kernel (0 = one per CU;
-                               clamped to at most one per CU and to what is
-                               co-resident) */
+    int32_t grid;           /* workgroups of the persistent kernel (0 = chosen: for the
+                               assembled M about sqrt(nnz) / 5, a multiple of 8, which
+                               is every CU from about 1.5 million nonzeros; for the
+                               chain one per CU; clamped to at most one per CU and
+                               to what is co-resident) */
     int32_t block;          /* threads per workgroup: 0 (default 1024), 256, 512 or 1024 */
     int32_t op;             /* product M x: SC_OP_AUTO (assembled M when ready, else the
                                matrix-free chain), SC_OP_CHAIN or SC_OP_MATRIX */

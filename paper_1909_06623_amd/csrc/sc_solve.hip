@@ -12,6 +12,8 @@
 // fixed order and takes the same decision: stop, or the next BB step size.
 // No floating-point atomics are used, so the iterates are
 // bitwise reproducible for a given launch shape.
+#include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstring>
 
@@ -496,12 +498,27 @@ int prepare(const sc_particles *p, const sc_contacts *c, const sc_solve_opts *op
 }
 
 // The persistent solve kernel (assembled M or the chain) on `s`.
+// Workgroups of the persistent assembled-M solve when the caller leaves the
+// grid open. A product costs the latency of its dependent steps (column
+// gathers, the grid barrier, the reduction), which grows with the number of
+// workgroups, plus the work per workgroup, which shrinks with it. Measured on
+// gfx950 the best count grows about as sqrt(nnz) / 5: 16 at 8,000 nonzeros,
+// 32 at 30,000-100,000, 64-128 at 300,000, 128 at 650,000, every CU from
+// about 1.5 million; up to 26% per product below a full grid on the small
+// systems. A multiple of 8 (one per XCD), clamped to the CUs by
+// persistent_grid.
+int matrix_grid(long long nnz) {
+    const long long k = std::llround(std::sqrt(static_cast<double>(nnz > 0 ? nnz : 0)) / 40.0);
+    return static_cast<int>(8 * std::min(std::max(k, 1LL), 1LL << 20));
+}
+
 hipError_t launch_solver(Prepared &P, const sc_contacts *c, const sc_solve_opts *opts,
                          double *gamma, double *g, hipStream_t s) {
     if (P.use_mat)
         return launch_bbpgd_mat(mat_view(c->count, P.mb), c->q, gamma, g, P.zbuf, P.part,
                                 P.sync, P.ctrl, opts->tol, opts->max_iter, opts->bb, P.spw,
-                                opts->lds_entries_per_wave, P.block, opts->grid, s, &P.G,
+                                opts->lds_entries_per_wave, P.block,
+                                opts->grid > 0 ? opts->grid : matrix_grid(c->nnz), s, &P.G,
                                 &P.cache_used);
     P.G = persistent_grid(reinterpret_cast<const void *>(P.kern), P.block, opts->grid);
     if (P.G < 1) return hipErrorInvalidConfiguration;
