@@ -280,6 +280,33 @@ def test_matrix_launch_shapes_agree(spw):
                                atol=1e-12 * np.abs(want).max())
 
 
+def test_matrix_default_grid_follows_the_size_of_m():
+    """With the grid left open the assembled-M solve takes 8 round(sqrt(nnz)
+    / 40) workgroups (at least 8, at most one per CU), and the solve it runs
+    converges to the same point as the full grid's: g = M gamma + q and
+    F_c = D gamma agree with the oracle's at the tolerance's error bound."""
+    sc = _sc()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for s in (W.workload(1), W.rods(4000, seed=44), W.rods_and_spheres(2500, 500, seed=45)):
+        _say(f"default grid: {s.name}")
+        P, box, u_nc, con = _setup_gpu(s)
+        want = 8 * max(1, int(round(np.sqrt(con.nnz) / 40.0)))
+        want = min(want, cus - cus % 8)
+        gam, g, st, f_c, _ = sc.solve_lcp(P, con, tol=1e-9, want_fc=True, op=2)
+        gam2, g2, st2, f_c2, _ = sc.solve_lcp(P, con, tol=1e-9, want_fc=True, op=2, grid=cus)
+        assert st["grid"] == want and st2["grid"] == cus - cus % 8
+        assert st["status"] == 0 and st2["status"] == 0
+        c, u_orc, q_orc = O.setup(s)
+        pm = _perm(con)
+        go, gg, sto = O.bbpgd(s, c, q_orc, tol=1e-9)
+        F = O.D_apply(s.n, c, go)
+        for g_, f_ in ((g, f_c), (g2, f_c2)):
+            np.testing.assert_allclose(g_.cpu().numpy()[pm], gg, rtol=0,
+                                       atol=1e-6 * max(1.0, np.abs(gg).max()))
+            np.testing.assert_allclose(f_.cpu().numpy(), F, rtol=0,
+                                       atol=1e-6 * max(1.0, np.abs(F).max()))
+
+
 def test_matrix_tiny_systems():
     """Fewer rows than one slice (most workgroups own no slice)."""
     sc = _sc()
