@@ -234,3 +234,43 @@ def test_noalloc_solve_rejects_oversized_systems_on_the_host():
                                   None, None, None, ctypes.byref(st), None) == A.SC_ERR_WORKSPACE
     assert L.sc_solve_lcp_noalloc(None, ctypes.byref(c), ctypes.byref(opts), None, None, None,
                                   None, ctypes.byref(st), None) == A.SC_ERR_INVALID
+
+
+def test_batch_options_rejected_on_the_host():
+    """sc_batch_create checks its team policy options before any device work:
+    a team size and a size-class target for the same launch, negative
+    targets, team and block sizes outside their sets."""
+    from paper_1909_06623_amd import _abi as A
+    L = A.lib()
+
+    def opts(**kw):
+        o = A.sc_batch_opts()
+        o.tol, o.max_iter, o.bb = 1e-6, 100, 1
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    out = ctypes.c_void_p(1)
+    for bad in (dict(team=4, nnz_per_workgroup=1000),
+                dict(adjoint_team=2, adjoint_nnz_per_workgroup=10),
+                dict(nnz_per_workgroup=-1), dict(adjoint_nnz_per_workgroup=-5), dict(team=3),
+                dict(adjoint_team=64), dict(block=300), dict(adjoint_block=768), dict(bb=4),
+                dict(tol=0.0)):
+        o = opts(**bad)
+        assert L.sc_batch_create(0, None, ctypes.byref(o), None, 0, None,
+                                 ctypes.byref(out)) == A.SC_ERR_INVALID, bad
+        assert out.value is None, bad
+
+
+def test_tuned_policy_recreates_each_launch():
+    """Batch.tuned_policy turns an autotuned batch's info into the options
+    that recreate it: size classes when a target was picked, else the team."""
+    from paper_1909_06623_amd.api import Batch
+    info = {"team": 32, "nnz_per_workgroup": 32768, "team_adjoint": 8,
+            "adjoint_nnz_per_workgroup": 0}
+    assert Batch.tuned_policy(info) == {"team": 0, "nnz_per_workgroup": 32768,
+                                        "adjoint_team": 8, "adjoint_nnz_per_workgroup": 0}
+    info = {"team": 16, "nnz_per_workgroup": 0, "team_adjoint": 32,
+            "adjoint_nnz_per_workgroup": 16384}
+    assert Batch.tuned_policy(info) == {"team": 16, "nnz_per_workgroup": 0,
+                                        "adjoint_team": 0, "adjoint_nnz_per_workgroup": 16384}
