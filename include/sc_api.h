@@ -192,7 +192,7 @@ typedef struct sc_adjoint_opts {
 #define SC_WS_ALL      0    /* any entry point below */
 #define SC_WS_BUILD    1    /* sc_build_contacts, sc_canonical_order */
 #define SC_WS_SOLVE    2    /* sc_solve_lcp, sc_solve_lcp_async, sc_mvop */
-#define SC_WS_ADJOINT  3    /* sc_solve_lcp_adjoint */
+#define SC_WS_ADJOINT  3    /* sc_solve_lcp_adjoint, sc_polish_lcp */
 
 /* Bytes of workspace the entry points named by `what` need for n particles
  * and `capacity` contact rows (SC_WS_ALL: the largest of them). Pure host
@@ -329,6 +329,28 @@ int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
                          const double *dL_df, double *dL_dq, double *dL_dpos,
                          const sc_adjoint_opts *opts, sc_stats *st, void *ws,
                          size_t ws_bytes, void *stream);
+
+/* Active-set polish of a solve (not in the paper; it makes a converged
+ * iterate of Algorithm 1 exact on its active set, section 3.2's LCP): with
+ * A = {gamma > 0} of the input, solves M_AA gamma_A = -q_A by conjugate
+ * gradients (to ||r|| <= opts->tol ||q_A||, at most opts->max_iter
+ * iterations; the other fields of opts choose the product as for the
+ * adjoint), sets gamma = 0 off A and g = M gamma + q, then moves the
+ * violators (gamma_l < 0 leaves A, g_l < 0 joins A) and repeats, at most
+ * max_pass times (0 = 20). gamma: [c->count] device, IN: the solve's
+ * output, OUT: the polished point if a pass ends with no violator, else
+ * unchanged. g: [c->count] device, OUT: M gamma + q of the returned gamma.
+ * f_c, u_c: [n][6] or NULL, OUT: D gamma and Mob D gamma of it. st (host,
+ * OUT): status SC_OK when polished, SC_NOT_CONVERGED when no pass settled
+ * or an active block's CG did not converge (outputs are then the input's),
+ * or the CG's error; iters = CG iterations over all passes; mvops = passes;
+ * n_active = |A| of the polished point; residual = ||min(gamma, g)||_2 of
+ * the returned point; kernel_ms = GPU time of the CG launches. ws: device
+ * workspace of at least sc_workspace_bytes(n, c->capacity, SC_WS_ADJOINT)
+ * bytes, 256-byte aligned. Synchronises `stream` once per pass. */
+int sc_polish_lcp(const sc_particles *p, const sc_contacts *c, double *gamma, double *g,
+                  double *f_c, double *u_c, const sc_adjoint_opts *opts, int32_t max_pass,
+                  sc_stats *st, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------- batched */
 

@@ -155,6 +155,9 @@ SIGNATURES = {
                                             c_dp, ctypes.c_double, c_dp, c_dp, c_dp,
                                             c_dp, c_dp, P(sc_adjoint_opts), P(sc_stats),
                                             c_dp, ctypes.c_size_t, c_dp]),
+    "sc_polish_lcp": (ctypes.c_int, [P(sc_particles), P(sc_contacts), c_dp, c_dp, c_dp, c_dp,
+                                     P(sc_adjoint_opts), ctypes.c_int32, P(sc_stats), c_dp,
+                                     ctypes.c_size_t, c_dp]),
     "sc_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, P(sc_batch_item),
                                                    P(sc_batch_opts)]),
     "sc_batch_create": (ctypes.c_int, [ctypes.c_int32, P(sc_batch_item), P(sc_batch_opts),

@@ -404,6 +404,33 @@ def solve_lcp_adjoint(particles: Particles, box: Box, contacts: Contacts,
     return dq[:nc], dpos, st.as_dict()
 
 
+def polish_lcp(particles: Particles, contacts: Contacts, gamma: torch.Tensor,
+               tol: float = 1e-12, max_iter: int = 100000, max_pass: int = 0,
+               want_fc: bool = False, op: int = 0, workspace: Optional[Workspace] = None):
+    """Active-set polish of a solve (sc_polish_lcp): the exact LCP solution
+    on the active set of ``gamma`` (solved by conjugate gradients to ``tol``),
+    violators moved between passes. Returns (gamma, g, stats, f_c, u_c): the
+    polished point and M gamma + q if stats["status"] is SC_OK, else the input
+    and its g; f_c and u_c are None unless want_fc."""
+    nc, n = contacts.count, particles.n
+    gam = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
+    if nc:
+        gam[:nc] = _dev(gamma)[:nc]
+    g = torch.empty(max(1, nc), dtype=torch.float64, device="cuda")
+    f_c = torch.empty((n, 6), dtype=torch.float64, device="cuda") if want_fc else None
+    u_c = torch.empty((n, 6), dtype=torch.float64, device="cuda") if want_fc else None
+    opts = A.sc_adjoint_opts(float(tol), int(max_iter), 0, 0, 0, int(op), 0, 0)
+    st = A.sc_stats()
+    ws = workspace or default_workspace()
+    wsp, wsn = ws.get(n, contacts.capacity)
+    pc, cc = particles.c(), contacts.c()
+    rc = A.lib().sc_polish_lcp(ctypes.byref(pc), ctypes.byref(cc), _ptr(gam), _ptr(g),
+                               _ptr(f_c), _ptr(u_c), ctypes.byref(opts), int(max_pass),
+                               ctypes.byref(st), wsp, wsn, _stream())
+    _check("sc_polish_lcp", rc, (A.SC_OK, A.SC_NOT_CONVERGED))
+    return gam[:nc], g[:nc], st.as_dict(), f_c, u_c
+
+
 class RPY:
     """Rotne-Prager-Yamakawa mobility of spheres in unbounded fluid
     (``sc_rpy``): translational pair couplings for unequal radii with the

@@ -15,6 +15,9 @@
 // the fly and forms U = Mob D r, pass B forms w = A r and both dot products.
 // The geometric derivatives are then formed per contact and gathered per
 // particle (no floating-point atomics).
+#include <cmath>
+#include <vector>
+
 #include "sc_chain.hpp"
 #include "sc_common.hpp"
 #include "sc_geometry.hpp"
@@ -209,6 +212,157 @@ CgKernel cg_kernel(int lpp, int block) {
                         : block == 512 ? cg_kernel_bs<512>(lpp) : cg_kernel_bs<1024>(lpp);
 }
 
+// The adjoint's (and the polish's) workspace, carved in one order.
+struct CgBufs {
+    double *zrec, *r0, *r1, *s0, *s1, *wv, *pv, *x, *grad, *U, *Vw, *Uc, *part;
+    GridSync *sync;
+    CgCtrl *ctrl;
+};
+
+bool carve_cg(void *ws, size_t ws_bytes, int n, long long cap, CgBufs &B) {
+    Carver cv{static_cast<char *>(ws), ws_bytes};
+    // one contiguous block: the chain CG's vectors r0 r1 s0 s1 w, or the
+    // matrix CG's two arrays of (r, w, s, pad) records
+    B.zrec = cv.take<double>(8 * cap);
+    B.r0 = B.zrec;
+    B.r1 = B.zrec + cap;
+    B.s0 = B.zrec + 2 * cap;
+    B.s1 = B.zrec + 3 * cap;
+    B.wv = B.zrec + 4 * cap;
+    B.pv = cv.take<double>(cap);
+    B.x = cv.take<double>(cap);
+    B.grad = cv.take<double>(3 * cap);
+    B.U = cv.take<double>(8 * static_cast<size_t>(n));
+    B.Vw = cv.take<double>(8 * static_cast<size_t>(n));
+    B.Uc = cv.take<double>(8 * static_cast<size_t>(n));
+    B.part = cv.take<double>(2 * kPartHalf);
+    B.sync = cv.take<GridSync>(1);
+    B.ctrl = cv.take<CgCtrl>(1);
+    return cv.ok;
+}
+
+bool cg_opts_ok(const sc_adjoint_opts *o, const sc_contacts *c) {
+    return o->tol > 0.0 && o->max_iter >= 0 && lanes_ok(o->lanes_per_particle) &&
+           spw_ok(o->slices_per_wave) && o->lds_entries_per_wave >= -1 && o->grid >= 0 &&
+           block_ok(o->block) && o->op >= 0 && o->op <= SC_OP_MATRIX &&
+           !(o->op == SC_OP_MATRIX && !c->mat_ready);
+}
+
+// The launch a masked CG used.
+struct CgRun {
+    bool use_mat = false;
+    int lpp = 4, spw = 1, block = 1024, G = 1, cache_used = 0;
+};
+
+// Enqueues M_AA x_A = b_A by conjugate gradients into B.x (x = 0 off A),
+// with A = {mask > 0} and b = dLdg + D^T dLdF (either may be null), timed
+// by e0/e1 around the persistent kernel; ctrl->n_active counts A.
+hipError_t enqueue_masked_cg(const sc_particles *p, const sc_contacts *c, const Plan &pl,
+                             const double *mask, const double *dLdg, const double *dLdF,
+                             const sc_adjoint_opts *opts, const CgBufs &B, CgRun &R,
+                             hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
+    const int nc = c->count;
+    R.use_mat = opts->op == SC_OP_MATRIX || (opts->op == SC_OP_AUTO && c->mat_ready);
+    R.lpp = opts->lanes_per_particle ? opts->lanes_per_particle : 4;
+    R.spw = opts->slices_per_wave ? opts->slices_per_wave : 1;
+    R.block = opts->block ? opts->block : 1024;
+    MatBufs mb{};
+    if (R.use_mat && !carve_matrix(c->mat, c->mat_bytes, nc, c->nnz, mb))
+        return hipErrorInvalidValue;
+    CgKernel kern = cg_kernel(R.lpp, R.block);
+    R.G = R.use_mat ? 1 : persistent_grid(reinterpret_cast<const void *>(kern), R.block, opts->grid);
+    if (R.G < 1) return hipErrorInvalidConfiguration;
+    hipError_t e;
+    if ((e = hipMemsetAsync(B.ctrl, 0, sizeof(CgCtrl), s)) != hipSuccess ||
+        (e = hipMemsetAsync(B.sync, 0, sizeof(GridSync), s)) != hipSuccess ||
+        (e = hipMemsetAsync(B.s0, 0, sizeof(double) * nc, s)) != hipSuccess ||
+        (e = hipMemsetAsync(B.pv, 0, sizeof(double) * nc, s)) != hipSuccess ||
+        (e = hipMemsetAsync(B.x, 0, sizeof(double) * nc, s)) != hipSuccess)
+        return e;
+    if (R.use_mat && (e = hipMemsetAsync(B.zrec, 0, sizeof(double) * 4 * nc, s)) != hipSuccess)
+        return e;
+    int nb = grid_for(nc);
+    if (nb > kMaxReduceBlocks) nb = kMaxReduceBlocks;
+    k_cg_rhs<<<nb, kBlock, 0, s>>>(nc, c->ci, c->cj, c->frame, mask, dLdg, dLdF, B.r0,
+                                   R.use_mat ? 4 : 1, &B.ctrl->n_active);
+    if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+    if (R.use_mat) {
+        e = launch_cg_mat(mat_view(nc, mb), mask, B.zrec, B.pv, B.x, B.part, B.sync, B.ctrl,
+                          opts->tol, opts->max_iter, R.spw, opts->lds_entries_per_wave, R.block,
+                          opts->grid, s, &R.G, &R.cache_used);
+    } else {
+        CgArgs A;
+        A.C = chain_view(p, c, pl, B.U);
+        A.gamma = mask;
+        A.r[0] = B.r0;
+        A.r[1] = B.r1;
+        A.s[0] = B.s0;
+        A.s[1] = B.s1;
+        A.p = B.pv;
+        A.x = B.x;
+        A.w = B.wv;
+        A.part = B.part;
+        A.sync = B.sync;
+        A.ctrl = B.ctrl;
+        A.tol = opts->tol;
+        A.max_iter = opts->max_iter;
+        void *args[] = {&A};
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(R.G),
+                                       dim3(R.block), args, 0, s);
+    }
+    if (e != hipSuccess) return e;
+    return hipEventRecord(e1, s);
+}
+
+// --------------------------------------------------- active-set polish
+//
+// mask = 1 on A = {gamma > 0}, else 0.
+__global__ void k_polish_mask(int nc, const double *gamma, double *mask) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < nc) mask[l] = gamma[l] > 0.0 ? 1.0 : 0.0;
+}
+
+// gamma_A = -x_A (x solves M_AA x_A = q_A), 0 off A
+__global__ void k_polish_gamma(int nc, const double *mask, const double *x, double *gam) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < nc) gam[l] = mask[l] > 0.0 ? -x[l] : 0.0;
+}
+
+// g = y + q with y = M gamma (from the two-pass product)
+__global__ void k_add_q(int nc, const double *q, double *y) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < nc) y[l] += q[l];
+}
+
+// Violators of the candidate (gamma, g) on A: gamma_l < 0 in A (leaves A),
+// g_l < 0 off A (joins A); the mask is moved to the next active set in
+// place, the violators counted, and each block's sum of min(gamma, g)^2
+// written to part[block] (summed in block order on the host). Grid-stride,
+// so a fixed number of blocks covers any count.
+__global__ void k_polish_check(int nc, double *mask, const double *gam, const double *g,
+                               int *nviol, double *part) {
+    __shared__ double red[kBlock];
+    double m2 = 0.0;
+    int v = 0;
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < nc; l += gridDim.x * blockDim.x) {
+        const bool act = mask[l] > 0.0;
+        const bool leave = act && gam[l] < 0.0, join = !act && g[l] < 0.0;
+        v += leave || join;
+        if (leave || join) mask[l] = act ? 0.0 : 1.0;
+        const double mm = gam[l] < g[l] ? gam[l] : g[l];
+        m2 += mm * mm;
+    }
+    red[threadIdx.x] = m2;
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if (threadIdx.x % kWave == 0 && v) atomicAdd(nviol, v);
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 }  // namespace
 
 size_t adjoint_ws_bytes(int32_t n, int32_t cap) {
@@ -237,15 +391,9 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     if (!p || !box || !c || !opts || !st || p->n < 0 || c->count < 0 ||
         c->count > c->capacity)
         return SC_ERR_INVALID;
-    if (!(dt > 0.0) || !(opts->tol > 0.0) || opts->max_iter < 0 ||
-        !lanes_ok(opts->lanes_per_particle) || !spw_ok(opts->slices_per_wave) ||
-        opts->lds_entries_per_wave < -1 || opts->grid < 0 ||
-        !block_ok(opts->block) || opts->op < 0 ||
-        opts->op > SC_OP_MATRIX || (opts->op == SC_OP_MATRIX && !c->mat_ready))
-        return SC_ERR_INVALID;
+    if (!(dt > 0.0) || !cg_opts_ok(opts, c)) return SC_ERR_INVALID;
     *st = sc_stats{};
     const int n = p->n, nc = c->count;
-    const bool use_mat = opts->op == SC_OP_MATRIX || (opts->op == SC_OP_AUTO && c->mat_ready);
     Plan pl;
     if (!carve_plan(c->plan, c->plan_bytes, n, c->capacity, pl)) return SC_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream_);
@@ -261,71 +409,14 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
         st->status = SC_OK;
         return SC_OK;
     }
-    const long long cap = c->capacity;
-    Carver cv{static_cast<char *>(ws), ws_bytes};
-    // one contiguous block: the chain CG's vectors r0 r1 s0 s1 w, or the
-    // matrix CG's two arrays of (r, w, s, pad) records
-    double *zrec = cv.take<double>(8 * cap);
-    double *r0 = zrec, *r1 = zrec + cap, *s0 = zrec + 2 * cap, *s1 = zrec + 3 * cap;
-    double *wv = zrec + 4 * cap;
-    double *pv = cv.take<double>(cap), *x = cv.take<double>(cap);
-    double *grad = cv.take<double>(3 * cap);
-    double *U = cv.take<double>(8 * static_cast<size_t>(n));
-    double *Vw = cv.take<double>(8 * static_cast<size_t>(n));
-    double *Uc = cv.take<double>(8 * static_cast<size_t>(n));
-    double *part = cv.take<double>(2 * kPartHalf);
-    GridSync *sync = cv.take<GridSync>(1);
-    CgCtrl *ctrl = cv.take<CgCtrl>(1);
-    if (!cv.ok) return SC_ERR_WORKSPACE;
-
-    const int lpp = opts->lanes_per_particle ? opts->lanes_per_particle : 4;
-    const int spw = opts->slices_per_wave ? opts->slices_per_wave : 1;
-    int cache_used = 0;
-    const int block = opts->block ? opts->block : 1024;
-    MatBufs mb{};
-    if (use_mat && !carve_matrix(c->mat, c->mat_bytes, nc, c->nnz, mb)) return SC_ERR_INVALID;
-    CgKernel kern = cg_kernel(lpp, block);
-    int G = use_mat ? 1 : persistent_grid(reinterpret_cast<const void *>(kern), block, opts->grid);
-    if (G < 1) return SC_ERR_HIP;
-
-    SC_HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(CgCtrl), s));
-    SC_HIP_TRY(hipMemsetAsync(sync, 0, sizeof(GridSync), s));
-    SC_HIP_TRY(hipMemsetAsync(s0, 0, sizeof(double) * nc, s));
-    SC_HIP_TRY(hipMemsetAsync(pv, 0, sizeof(double) * nc, s));
-    SC_HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * nc, s));
-    int nb = grid_for(nc);
-    if (nb > kMaxReduceBlocks) nb = kMaxReduceBlocks;
-    if (use_mat) SC_HIP_TRY(hipMemsetAsync(zrec, 0, sizeof(double) * 4 * nc, s));
-    k_cg_rhs<<<nb, kBlock, 0, s>>>(nc, c->ci, c->cj, c->frame, gamma, dL_dgamma, dL_df, r0,
-                                   use_mat ? 4 : 1, &ctrl->n_active);
-    CgArgs A;
-    A.C = chain_view(p, c, pl, U);
-    A.gamma = gamma;
-    A.r[0] = r0;
-    A.r[1] = r1;
-    A.s[0] = s0;
-    A.s[1] = s1;
-    A.p = pv;
-    A.x = x;
-    A.w = wv;
-    A.part = part;
-    A.sync = sync;
-    A.ctrl = ctrl;
-    A.tol = opts->tol;
-    A.max_iter = opts->max_iter;
-    void *args[] = {&A};
+    CgBufs B;
+    if (!carve_cg(ws, ws_bytes, n, c->capacity, B)) return SC_ERR_WORKSPACE;
+    double *x = B.x, *grad = B.grad, *Vw = B.Vw, *Uc = B.Uc;
+    CgCtrl *ctrl = B.ctrl;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!thread_events(&e0, &e1)) return SC_ERR_HIP;
-    SC_HIP_TRY(hipEventRecord(e0, s));
-    if (use_mat) {
-        SC_HIP_TRY(launch_cg_mat(mat_view(nc, mb), gamma, zrec, pv, x, part, sync, ctrl,
-                                 opts->tol, opts->max_iter, spw, opts->lds_entries_per_wave,
-                                 block, opts->grid, s, &G, &cache_used));
-    } else {
-        SC_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G),
-                                              dim3(block), args, 0, s));
-    }
-    SC_HIP_TRY(hipEventRecord(e1, s));
+    CgRun R;
+    SC_HIP_TRY(enqueue_masked_cg(p, c, pl, gamma, dL_dgamma, dL_df, opts, B, R, e0, e1, s));
     // dL/dq = -w on A; V_w = Mob D w; U_c = Mob D gamma; geometric terms
     k_neg_masked<<<grid_for(nc), kBlock, 0, s>>>(nc, gamma, x, dL_dq);
     ChainView Cv = chain_view(p, c, pl, Vw), Cc = chain_view(p, c, pl, Uc);
@@ -349,11 +440,118 @@ extern "C" int sc_solve_lcp_adjoint(const sc_particles *p, const sc_box *box,
     st->n_active = hc.n_active;
     st->residual = hc.res;
     st->alpha = hc.alpha;
-    st->grid = G;
-    st->block = block;
-    st->lanes_per_particle = use_mat ? 0 : lpp;
-    st->slices_per_wave = use_mat ? spw : 0;
-    st->lds_entries_per_wave = cache_used;
-    st->op = use_mat ? SC_OP_MATRIX : SC_OP_CHAIN;
+    st->grid = R.G;
+    st->block = R.block;
+    st->lanes_per_particle = R.use_mat ? 0 : R.lpp;
+    st->slices_per_wave = R.use_mat ? R.spw : 0;
+    st->lds_entries_per_wave = R.cache_used;
+    st->op = R.use_mat ? SC_OP_MATRIX : SC_OP_CHAIN;
     return hc.status;
+}
+
+extern "C" int sc_polish_lcp(const sc_particles *p, const sc_contacts *c, double *gamma,
+                             double *g, double *f_c, double *u_c, const sc_adjoint_opts *opts,
+                             int32_t max_pass, sc_stats *st, void *ws, size_t ws_bytes,
+                             void *stream_) {
+    if (!p || !c || !opts || !st || p->n < 0 || c->count < 0 || c->count > c->capacity ||
+        max_pass < 0 || !cg_opts_ok(opts, c))
+        return SC_ERR_INVALID;
+    const int n = p->n, nc = c->count;
+    Plan pl;
+    if (!carve_plan(c->plan, c->plan_bytes, n, c->capacity, pl)) return SC_ERR_INVALID;
+    if (nc > 0 && (!gamma || !g || !c->ci || !c->cj || !c->frame || !c->q))
+        return SC_ERR_INVALID;
+    if (n > 0 && !p->mob) return SC_ERR_INVALID;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 ||
+        ws_bytes < adjoint_ws_bytes(n, c->capacity))
+        return SC_ERR_WORKSPACE;
+    *st = sc_stats{};
+    hipStream_t s = static_cast<hipStream_t>(stream_);
+    if (nc == 0) {
+        if (f_c && n > 0) SC_HIP_TRY(hipMemsetAsync(f_c, 0, 6 * sizeof(double) * n, s));
+        if (u_c && n > 0) SC_HIP_TRY(hipMemsetAsync(u_c, 0, 6 * sizeof(double) * n, s));
+        SC_HIP_TRY(hipStreamSynchronize(s));
+        st->status = SC_OK;
+        return SC_OK;
+    }
+    CgBufs B;
+    if (!carve_cg(ws, ws_bytes, n, c->capacity, B)) return SC_ERR_WORKSPACE;
+    const long long cap = c->capacity;
+    double *gnew = B.grad, *mask = B.grad + cap, *ynew = B.grad + 2 * cap;
+    int *nviol = &B.ctrl->pad;  // the CG leaves this word alone
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!thread_events(&e0, &e1)) return SC_ERR_HIP;
+    const ChainView C = chain_view(p, c, pl, B.U);
+    const int nb = grid_for(nc);
+    const int nr = nb < kMaxReduceBlocks ? nb : kMaxReduceBlocks;  // blocks of the check
+    std::vector<double> hp(static_cast<size_t>(nr));
+    const int passes_max = max_pass ? max_pass : 20;
+    k_polish_mask<<<nb, kBlock, 0, s>>>(nc, gamma, mask);
+    CgRun R;
+    int passes = 0, iters = 0, status = SC_NOT_CONVERGED;
+    float ms_total = 0.0f;
+    double res2 = 0.0;
+    for (; passes < passes_max;) {
+        SC_HIP_TRY(enqueue_masked_cg(p, c, pl, mask, c->q, nullptr, opts, B, R, e0, e1, s));
+        k_polish_gamma<<<nb, kBlock, 0, s>>>(nc, mask, B.x, gnew);
+        launch_mob_d(C, gnew, pl.order, nullptr, nullptr, s);
+        launch_dt(C, ynew, s);
+        k_add_q<<<nb, kBlock, 0, s>>>(nc, c->q, ynew);
+        SC_HIP_TRY(hipMemsetAsync(nviol, 0, sizeof(int), s));
+        k_polish_check<<<nr, kBlock, 0, s>>>(nc, mask, gnew, ynew, nviol, B.part);
+        CgCtrl hc;
+        SC_HIP_TRY(hipMemcpyAsync(&hc, B.ctrl, sizeof(CgCtrl), hipMemcpyDeviceToHost, s));
+        SC_HIP_TRY(hipMemcpyAsync(hp.data(), B.part, sizeof(double) * nr, hipMemcpyDeviceToHost,
+                                  s));
+        SC_HIP_TRY(hipStreamSynchronize(s));
+        SC_HIP_TRY(hipGetLastError());
+        float ms = 0.0f;
+        SC_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms_total += ms;
+        ++passes;
+        iters += hc.iters;
+        if (hc.status != SC_OK) {  // the active block's solve did not converge (or failed)
+            status = hc.status;
+            break;
+        }
+        if (hc.pad == 0) {  // no violator: the candidate solves the LCP on its active set
+            res2 = 0.0;
+            for (int b = 0; b < nr; ++b) res2 += hp[b];
+            st->n_active = hc.n_active;
+            status = SC_OK;
+            break;
+        }
+    }
+    if (status == SC_OK) {
+        SC_HIP_TRY(hipMemcpyAsync(gamma, gnew, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+        SC_HIP_TRY(hipMemcpyAsync(g, ynew, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+    } else {
+        // not settled: keep the input, and give g = M gamma + q for it
+        launch_mob_d(C, gamma, pl.order, nullptr, nullptr, s);
+        launch_dt(C, g, s);
+        k_add_q<<<nb, kBlock, 0, s>>>(nc, c->q, g);
+        k_polish_mask<<<nb, kBlock, 0, s>>>(nc, gamma, mask);
+        SC_HIP_TRY(hipMemsetAsync(nviol, 0, sizeof(int), s));
+        k_polish_check<<<nr, kBlock, 0, s>>>(nc, mask, gamma, g, nviol, B.part);
+        SC_HIP_TRY(hipMemcpyAsync(hp.data(), B.part, sizeof(double) * nr, hipMemcpyDeviceToHost,
+                                  s));
+        SC_HIP_TRY(hipStreamSynchronize(s));
+        res2 = 0.0;
+        for (int b = 0; b < nr; ++b) res2 += hp[b];
+    }
+    if (f_c || u_c) launch_mob_d(C, gamma, pl.order, f_c, u_c, s);
+    SC_HIP_TRY(hipStreamSynchronize(s));
+    SC_HIP_TRY(hipGetLastError());
+    st->status = status;
+    st->iters = iters;
+    st->mvops = passes;
+    st->residual = std::sqrt(res2);
+    st->kernel_ms = ms_total;
+    st->grid = R.G;
+    st->block = R.block;
+    st->lanes_per_particle = R.use_mat ? 0 : R.lpp;
+    st->slices_per_wave = R.use_mat ? R.spw : 0;
+    st->lds_entries_per_wave = R.cache_used;
+    st->op = R.use_mat ? SC_OP_MATRIX : SC_OP_CHAIN;
+    return status;
 }

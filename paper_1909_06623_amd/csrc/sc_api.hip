@@ -41,4 +41,4 @@ extern "C" int sc_release(void) {
     return SC_OK;
 }
 
-extern "C" int sc_version(void) { return 360; }
+extern "C" int sc_version(void) { return 370; }

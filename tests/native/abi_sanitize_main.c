@@ -171,6 +171,10 @@ static void host_checks(void) {
         EXPECT(sc_rpy_apply(NULL, 4, NULL, NULL, NULL) == SC_ERR_INVALID);
         EXPECT(sc_dry_apply(NULL, 4, NULL, NULL, NULL) == SC_ERR_INVALID);
     }
+    EXPECT(sc_polish_lcp(NULL, &c, NULL, NULL, NULL, NULL, &ao, 0, &st, NULL, 0, NULL) ==
+           SC_ERR_INVALID);
+    EXPECT(sc_polish_lcp(&p0, &c, NULL, NULL, NULL, NULL, &ao, -1, &st, NULL, 0, NULL) ==
+           SC_ERR_INVALID);
     EXPECT(sc_advance(-1, NULL, NULL, NULL, NULL, NULL, 0.1, NULL) == SC_ERR_INVALID);
     EXPECT(sc_advance(4, NULL, NULL, NULL, NULL, NULL, 0.0, NULL) == SC_ERR_INVALID);
     EXPECT(sc_advance(4, NULL, NULL, NULL, NULL, NULL, 0.1, NULL) == SC_ERR_INVALID);
@@ -374,7 +378,13 @@ static void gpu_dry(hipStream_t s) {
     SOLVED(sc_solve_lcp_adjoint(&S.p, &box, &K.c, u_nc, dt, gamma, gamma, NULL, dq, dpos, &ao,
                                 &st, K.ws, K.ws_bytes, s));
 
-    printf("[dry] adjoints done\n");
+    {
+        /* the active-set polish of the solve, in place on a copy */
+        sc_adjoint_opts po = {1e-13, 10000, 0, 0, 0, 0, 0, 0};
+        HIP(hipMemcpy(gamma2, gamma, sizeof(double) * nc, hipMemcpyDeviceToDevice));
+        SOLVED(sc_polish_lcp(&S.p, &K.c, gamma2, g2, f_c, u_c, &po, 0, &st, K.ws, K.ws_bytes, s));
+    }
+    printf("[dry] adjoints and polish done\n");
     /* the dry mobility through the function interface */
     {
         size_t wb = sc_solve_mob_work_bytes(n, cap), wa = sc_adjoint_mob_work_bytes(n, cap);

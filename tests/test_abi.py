@@ -274,3 +274,30 @@ def test_tuned_policy_recreates_each_launch():
             "adjoint_nnz_per_workgroup": 16384}
     assert Batch.tuned_policy(info) == {"team": 16, "nnz_per_workgroup": 0,
                                         "adjoint_team": 0, "adjoint_nnz_per_workgroup": 16384}
+
+
+def test_polish_rejects_bad_arguments_without_device_work():
+    """sc_polish_lcp checks its arguments on the host before any launch."""
+    from paper_1909_06623_amd import _abi as A
+    L = A.lib()
+    p0 = A.sc_particles(0, 0, 0, 0, 0, 0, 0)
+    c = A.sc_contacts()
+    c.capacity, c.count = 5, 10  # count beyond capacity
+    o = A.sc_adjoint_opts(1e-12, 100, 0, 0, 0, 0, 0, 0)
+    st = A.sc_stats()
+    args = lambda pp, cc, oo, mp, ss: L.sc_polish_lcp(pp, cc, None, None, None, None, oo, mp,
+                                                      ss, None, 0, None)
+    assert args(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(o), 0,
+                ctypes.byref(st)) == A.SC_ERR_INVALID
+    c.count = 0
+    assert args(None, ctypes.byref(c), ctypes.byref(o), 0, ctypes.byref(st)) == A.SC_ERR_INVALID
+    assert args(ctypes.byref(p0), ctypes.byref(c), None, 0, ctypes.byref(st)) == A.SC_ERR_INVALID
+    assert args(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(o), -1,
+                ctypes.byref(st)) == A.SC_ERR_INVALID
+    assert args(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(o), 0, None) == A.SC_ERR_INVALID
+    for field, value in (("tol", 0.0), ("max_iter", -1), ("block", 300), ("op", 3),
+                         ("lanes_per_particle", 3)):
+        bad = A.sc_adjoint_opts(1e-12, 100, 0, 0, 0, 0, 0, 0)
+        setattr(bad, field, value)
+        assert args(ctypes.byref(p0), ctypes.byref(c), ctypes.byref(bad), 0,
+                    ctypes.byref(st)) == A.SC_ERR_INVALID, field
