@@ -674,6 +674,17 @@ def main():
                                            "masked product on the active set)",
                             "bytes_per_launch": cg_bytes, "launch_ms": sta["kernel_ms"],
                             "us_per_iteration": 1e3 * sta["kernel_ms"] / max(1, sta["iters"])}}
+        # the active-set polish of the same solve (exact on its active set)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        gpol, gpg, stp, _, _ = sc.polish_lcp(P, con, gam, tol=1e-13, workspace=ws)
+        torch.cuda.synchronize()
+        adj["polish"] = {"ms": 1e3 * (time.perf_counter() - t2), "status": stp["status"],
+                         "passes": stp["mvops"], "cg_iters": stp["iters"],
+                         "cg_kernel_ms": stp["kernel_ms"], "residual_before": st2["residual"],
+                         "residual_after": stp["residual"],
+                         "rel_gamma_change": float(torch.linalg.norm(gpol - gam)
+                                                   / torch.linalg.norm(gpol))}
 
     batch = None if args.no_batch else batched(sc, W, torch, np, args.batch_count)
     big = None if args.no_large else large(sc, W, torch, np, args.large_steps)

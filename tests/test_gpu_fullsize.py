@@ -74,6 +74,13 @@ def test_rods100k_bench_configuration():
          f"{rel6:.2e} (tol 1e-6)")
     assert rel9 <= 1e-6
     assert rel6 <= 1e-6
+    # the GPU's active-set polish of the benchmark's tol-1e-6 solve reaches
+    # the oracle's polished solution
+    gpp, gpg6, stp, _, _ = sc.polish_lcp(P, con, gam6, tol=1e-13)
+    relp = np.linalg.norm(gpp.cpu().numpy()[pm] - gp) / np.linalg.norm(gp)
+    _say(f"polish of the tol-1e-6 solve: {stp['mvops']} passes, {stp['iters']} CG iterations, "
+         f"{stp['kernel_ms']:.1f} ms of CG; rel gamma err vs the oracle's polish {relp:.2e}")
+    assert stp["status"] == 0 and relp <= 1e-10
     # adjoint of L = 1/2 ||D gamma||^2 (the adjoint configuration)
     if not np.array_equal(ga9 > 0, gp > 0):
         pytest.skip("active sets differ (weakly active contacts)")
