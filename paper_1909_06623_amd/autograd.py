@@ -35,8 +35,9 @@ import torch
 from torch.autograd.function import once_differentiable
 
 from . import _abi as A
-from .api import (RPY, Box, Contacts, Particles, build_contacts, require_solution, solve_lcp,
-                  solve_lcp_adjoint, solve_lcp_adjoint_mob, solve_lcp_mob, solve_lcp_rpy)
+from .api import (RPY, Box, Contacts, Particles, build_contacts, polish_lcp, require_solution,
+                  solve_lcp, solve_lcp_adjoint, solve_lcp_adjoint_mob, solve_lcp_mob,
+                  solve_lcp_rpy)
 
 
 # Largest system whose RPY solve runs as one persistent launch.
@@ -50,16 +51,22 @@ class SolveInfo:
     stats: Optional[dict] = None
     dL_dq: Optional[torch.Tensor] = None          # filled by backward
     adjoint_stats: Optional[dict] = None          # filled by backward
+    polish_stats: Optional[dict] = None           # with polish=True
 
 
 class _CollisionSolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, pos, particles, box, u_nc, dt, delta, tol, adjoint_tol, info, kw):
+    def forward(ctx, pos, particles, box, u_nc, dt, delta, tol, adjoint_tol, info, kw, polish):
         P = dataclasses.replace(particles, pos=pos.detach().to(torch.float64).contiguous())
         con = build_contacts(P, box, delta, u_nc, dt)
         gamma, g, st, f_c, u_c = solve_lcp(P, con, tol=tol, want_fc=True, **kw)
         info.contacts, info.stats = con, st
         require_solution("sc_solve_lcp", st)
+        if polish:
+            # the exact LCP solution on the solve's active set (the input
+            # itself if no pass settles: info.polish_stats["status"] says which)
+            gamma, g, info.polish_stats, f_c, u_c = polish_lcp(P, con, gamma, tol=adjoint_tol,
+                                                               want_fc=True)
         ctx.state = (P, box, con, u_nc, dt, adjoint_tol, info, kw)
         ctx.save_for_backward(gamma)
         return gamma, f_c
@@ -74,7 +81,7 @@ class _CollisionSolve(torch.autograd.Function):
                                           **_adjoint_kw(kw))
         info.dL_dq, info.adjoint_stats = dq, sta
         _require_adjoint("sc_solve_lcp_adjoint", sta)
-        return dpos, None, None, None, None, None, None, None, None, None
+        return dpos, None, None, None, None, None, None, None, None, None, None
 
 
 class _LcpSolve(torch.autograd.Function):
@@ -148,13 +155,16 @@ def _adjoint_kw(kw):
 
 def collision_solve(pos: torch.Tensor, particles: Particles, box: Box, u_nc: torch.Tensor,
                     dt: float, delta: float, tol: float = 1e-6, adjoint_tol: float = 1e-10,
-                    info: Optional[SolveInfo] = None, **solve_kw):
+                    info: Optional[SolveInfo] = None, polish: bool = False, **solve_kw):
     """(gamma, F_c, info) for centres ``pos`` [n, 3] (float64, CUDA). The
     other particle properties come from ``particles``; gamma is in the
-    library's contact order (``info.contacts``)."""
+    library's contact order (``info.contacts``). ``polish``: replace the
+    solve's iterate by the exact solution on its active set (sc_polish_lcp,
+    to ``adjoint_tol``) before returning and differentiating."""
     info = SolveInfo() if info is None else info
     gamma, f_c = _CollisionSolve.apply(pos, particles, box, u_nc, float(dt), float(delta),
-                                       float(tol), float(adjoint_tol), info, solve_kw)
+                                       float(tol), float(adjoint_tol), info, solve_kw,
+                                       bool(polish))
     return gamma, f_c, info
 
 

@@ -95,6 +95,41 @@ def test_positions_gradient_matches_adjoint_and_oracle(kind):
                                atol=1e-6 * np.abs(rq).max())
 
 
+def test_polished_collision_solve_matches_the_oracle_tightly():
+    """collision_solve(polish=True) returns the exact solution on the solve's
+    active set (bitwise the library's polish of the same solve), and its
+    gradients agree with the oracle's adjoint at the oracle's polished
+    solution far more tightly than an unpolished iterate allows."""
+    import paper_1909_06623_amd as sc
+    from paper_1909_06623_amd.autograd import collision_solve
+    s = W.rods(1500, seed=81)
+    _say(f"autograd with polish N={s.n}")
+    P = sc.Particles.from_suspension(s)
+    box = sc.Box(tuple(s.box))
+    u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
+    pos = P.pos.clone().requires_grad_(True)
+    gamma, f_c, info = collision_solve(pos, P, box, u_nc, s.dt, s.delta, tol=1e-6,
+                                       adjoint_tol=1e-13, polish=True)
+    assert info.stats["status"] == 0 and info.polish_stats["status"] == 0
+    g0, _, _, _, _ = sc.solve_lcp(P, info.contacts, tol=1e-6)
+    gp_lib, _, _, _, _ = sc.polish_lcp(P, info.contacts, g0, tol=1e-13)
+    assert torch.equal(gamma.detach(), gp_lib)
+    loss = 0.5 * (f_c * f_c).sum()
+    loss.backward()
+    c, u_orc, q = O.setup(s)
+    pm = info.contacts.canonical_order().cpu().numpy()
+    go, _, _ = O.bbpgd(s, c, q, tol=1e-6)
+    gp, _, _ = O.polish(s, c, q, go)
+    ga = gamma.detach().cpu().numpy()[pm]
+    assert np.linalg.norm(ga - gp) <= 1e-10 * np.linalg.norm(gp)
+    np.testing.assert_array_equal(ga > 0, gp > 0)
+    rq, rpos, _ = O.adjoint(s, c, q, u_orc, gp, dL_dF=O.D_apply(s.n, c, gp))
+    np.testing.assert_allclose(pos.grad.cpu().numpy(), rpos, rtol=0,
+                               atol=1e-9 * np.abs(rpos).max())
+    np.testing.assert_allclose(info.dL_dq.cpu().numpy()[pm], rq, rtol=0,
+                               atol=1e-9 * np.abs(rq).max())
+
+
 def test_q_gradient_matches_oracle():
     import paper_1909_06623_amd as sc
     from paper_1909_06623_amd.autograd import lcp_solve
