@@ -222,7 +222,8 @@ int sc_apply_mobility(const sc_particles *p, const double *f, double *u,
  * u_nc: [n][6] non-collisional velocities. Writes c->count; if it exceeds
  * c->capacity returns SC_ERR_CAPACITY with c->count = the required rows and
  * no contact written. SC_ERR_BOX if periodic and a side is below twice the
- * interaction range 2 max(R + h) + delta. Synchronises `stream`. */
+ * interaction range 2 max(R + h) + delta. Synchronises `stream` (a batch of
+ * one system created with build = 1 builds without host synchronisation). */
 int sc_build_contacts(const sc_particles *p, const sc_box *box, double delta,
                       const double *u_nc, double dt, sc_contacts *c,
                       void *ws, size_t ws_bytes, void *stream);
