@@ -157,3 +157,40 @@ def test_built_batch_status_per_instance():
     assert b2.counts()[0][2] == A.SC_ERR_CAPACITY
     b2.close()
     b.close()
+
+
+
+def test_one_system_step_without_host_synchronisation():
+    """A batch of one system with build=True is one whole step (contact
+    build, M, solve and adjoint) with no host synchronisation inside: its
+    graph, captured once and replayed after the particles moved, equals a
+    fresh build_contacts and a prebuilt-contacts solve at the new positions,
+    and the forces D gamma meet the oracle's (unique at the LCP solution)."""
+    import paper_1909_06623_amd as sc
+    s = W.rods(2000, seed=W.SEED_BASE + 707)
+    P = sc.Particles.from_suspension(s)
+    box = sc.Box(tuple(s.box))
+    u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
+    inst = [(s, P, box, u_nc)]
+    _say(f"one-system built batch: N {s.n}")
+    b = sc.Batch([(P, box, s.delta, u_nc, s.dt)], tol=1e-9, team=4, build=True, adjoint=1,
+                 adjoint_tol=1e-12)
+    rng = np.random.default_rng(707)
+    for step in range(2):
+        b.graph_solve()
+        torch.cuda.synchronize()
+        st, adj, _ = b.stats()
+        assert st[0]["status"] == 0 and adj[0]["status"] == 0
+        con, = _check_against_single(b, inst, 4, 1e-9, 1)
+        _say(f"replay {step}: contacts {con.count}, iterations {st[0]['iters']}")
+        c, _, q = O.setup(s)
+        pm = con.canonical_order().cpu().numpy()
+        assert np.array_equal(con.i.cpu().numpy()[pm], c.i)
+        assert np.array_equal(con.j.cpu().numpy()[pm], c.j)
+        go, _, _ = O.bbpgd(s, c, q, tol=1e-10)
+        F = O.D_apply(s.n, c, b.gamma[0][: con.count].cpu().numpy()[pm])
+        Fo = O.D_apply(s.n, c, go)
+        np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-6 * max(1.0, np.abs(Fo).max()))
+        s.pos = s.pos + 0.004 * rng.standard_normal(s.pos.shape)
+        P.pos.copy_(torch.from_numpy(s.pos))
+    b.close()
