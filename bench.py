@@ -118,8 +118,30 @@ def spheres1000(sc, W, torch, np, steps):
     kernel_ms = float(np.mean([x["kernel_ms"] for x in sts]))
     bytes_iter = iteration_bytes(con.count, s.n, rods=False)
     gbs = bytes_iter * products / (kernel_ms * 1e-3) / 1e9
+    # the same step with no host synchronisation: a batch of this one system
+    # built on the device, replayed as one HIP graph (build, M, solve), on a
+    # team of workgroups that share one XCD
+    graph = {}
+    for team in (4, 8):
+        b = sc.Batch([(P, box, s.delta, u_nc, s.dt)], tol=s.tol, team=team, build=True)
+        for _ in range(3):
+            b.graph_solve()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            b.graph_solve()
+        torch.cuda.synchronize()
+        gms = 1e3 * (time.perf_counter() - t1) / steps
+        bst, _, _ = b.stats()
+        (gnc, _, gstatus), = b.counts()
+        graph[f"team{team}"] = {"ms_per_step": gms, "iters": bst[0]["iters"],
+                                "status": max(bst[0]["status"], gstatus), "n_contacts": gnc}
+        b.close()
     return {"workload": "1000 spheres R=0.5, volume fraction 0.3, periodic box 12.04, delta 0.1, "
                         "dt 1e-3, BBPGD (BB1) to 1e-6",
+            "graph_step": dict(graph, note="one-system batch with build=True replayed as a HIP "
+                                           "graph: contact build, M and the solve with no host "
+                                           "synchronisation, on one XCD's team"),
             "n": s.n, "n_contacts": con.count, "iters": st["iters"], "status": st["status"],
             "ms_per_step": ms, "particles_per_s": s.n / (ms * 1e-3), "solve_kernel_ms": kernel_ms,
             "us_per_product": 1e3 * kernel_ms / products, "grid": st["grid"],
