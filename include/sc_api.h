@@ -149,8 +149,10 @@ typedef struct sc_solve_opts {
     int32_t slices_per_wave; /* assembled-M product: 0 (default 1), 1, 2 or 4 slices of 64
                                 rows that one wave works on at once */
     int32_t lds_entries_per_wave; /* assembled-M product: entries of M each wave keeps in
-                                LDS for the whole solve; 0 = as many as fit, -1 = none,
-                                > 0 = at most that many */
+                                LDS for the whole solve; matrix-free chain: incidences
+                                (code and D column) per wave of the workgroup's share
+                                kept in LDS; 0 = as many as fit, -1 = none, > 0 = at
+                                most that many. Iterates do not depend on it. */
     int32_t spin_limit;     /* 0: a wait at a grid barrier gives up after 2^21 polls
                                (SC_ERR_TIMEOUT, every workgroup leaves its loop);
                                > 0: after this many (a small value forces the timeout
@@ -171,7 +173,8 @@ typedef struct sc_stats {
     int32_t block;          /* threads per workgroup used */
     int32_t op;             /* SC_OP_CHAIN or SC_OP_MATRIX: the product used */
     int32_t slices_per_wave; /* slices per wave (matrix; 0 for the chain) */
-    int32_t lds_entries_per_wave; /* entries of M per wave held in LDS (matrix) */
+    int32_t lds_entries_per_wave; /* entries of M (matrix) or incidences (chain) per wave
+                                     held in LDS */
     int32_t reserved;
 } sc_stats;
 

@@ -232,6 +232,41 @@ def test_bitwise_reproducible(op):
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
+def test_chain_lds_share_changes_nothing():
+    """The matrix-free chain keeps each workgroup's incidence ranges, codes
+    and D columns in LDS, up to a capacity; past it they are read from global
+    memory, and with lds_entries_per_wave = -1 all of them are. The
+    arithmetic and its order are the same either way, so iterates, step sizes
+    and residuals are bitwise equal for every share, and a few fixed steps
+    meet the oracle's."""
+    s = W.rods(3000, seed=31)
+    _say("chain LDS shares")
+    sc = _sc()
+    P, box, u_nc, con = _setup_gpu(s)
+    c, u_orc, q_orc = O.setup(s)
+    pm = _perm(con)
+    go, gg, sto = O.bbpgd(s, c, q_orc, max_iter=8)
+    ref = None
+    for grid, cache in ((0, 0), (0, -1), (0, 3), (0, 17), (40, 0), (40, 5), (40, -1)):
+        gam, g, st, _, _ = sc.solve_lcp(P, con, max_iter=8, op=1, grid=grid,
+                                        lds_entries_per_wave=cache)
+        assert st["op"] == 1 and st["iters"] == 8
+        if cache > 0:
+            assert st["lds_entries_per_wave"] == cache
+        elif cache < 0:
+            assert st["lds_entries_per_wave"] == 0
+        else:
+            assert st["lds_entries_per_wave"] > 0
+        np.testing.assert_allclose(gam.cpu().numpy()[pm], go, rtol=1e-9,
+                                   atol=1e-9 * np.abs(go).max())
+        key = (st["grid"], st["lanes_per_particle"])
+        if ref is None or ref[0] != key:
+            ref = (key, gam.clone(), g.clone(), st["alpha"], st["residual"])
+        else:
+            assert torch.equal(gam, ref[1]) and torch.equal(g, ref[2]), (grid, cache)
+            assert (st["alpha"], st["residual"]) == (ref[3], ref[4]), (grid, cache)
+
+
 @pytest.mark.parametrize("spw", [1, 2, 4])
 def test_matrix_launch_shapes_agree(spw):
     """Every launch shape of the one-pass solve runs the same algorithm: a
