@@ -91,6 +91,18 @@ def large(sc, W, torch, np, steps=3):
             "rods_per_s": s.n / (kernel_ms * 1e-3), "roofline": roof}
 
 
+def chain_roofline(st, bytes_iter):
+    """Roofline of the matrix-free two-pass solve (k_bbpgd) under the same
+    model as the main leg; its counter bytes are in profiles/k_bbpgd_rods100k.md."""
+    products = st["iters"] + 2
+    gbs = bytes_iter * products / (st["kernel_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_bbpgd (persistent BBPGD, matrix-free two-pass product)",
+            "bytes_per_product": bytes_iter, "products_per_launch": products,
+            "launch_ms": st["kernel_ms"], "lds_entries_per_wave": st["lds_entries_per_wave"]}
+
+
 def spheres1000(sc, W, torch, np, steps):
     """The 1000-sphere suspension (radius 0.5, volume fraction 0.3, delta
     0.1, dt 1e-3): contact build + BBPGD to 1e-6 per step, as the main leg;
@@ -762,7 +774,8 @@ def main():
                      "lanes_per_particle": st["lanes_per_particle"]},
         "cpu_baseline": cpu,
         "chain_solve": {"iters": chain["iters"], "kernel_ms": chain["kernel_ms"],
-                        "us_per_iter": 1e3 * chain["kernel_ms"] / (chain["iters"] + 2)},
+                        "us_per_iter": 1e3 * chain["kernel_ms"] / (chain["iters"] + 2),
+                        "roofline": chain_roofline(chain, bytes_iter)},
         "operator": "assembled M" if st["op"] == 2 else "matrix-free chain",
         "nnz_M": con.nnz,
         "build_ms": build_ms,
