@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "sc_chain.hpp"
+#include "sc_chain_lds.hpp"
 #include "sc_common.hpp"
 #include "sc_geometry.hpp"
 #include "sc_matrix.hpp"
@@ -39,6 +40,7 @@ struct CgArgs {
     CgCtrl *ctrl;
     double tol;
     int max_iter;
+    int rank_cap, inc_cap;  // pass A's static data in LDS (sc_chain_lds.hpp)
 };
 
 template <int LPP, int BS>
@@ -49,11 +51,12 @@ __global__ void __launch_bounds__(BS) k_cg(CgArgs A) {
     int k0, k1, l0, l1;
     chunk(C.n, k0, k1);
     chunk(C.nc, l0, l1);
+    const ChainLds L = chain_lds_fill(C, A.rank_cap, A.inc_cap, k0, k1);
     bool ok;
     double tot[2];
 
     // first product: w = A r0 and the dot products (r0, r0), (w, r0)
-    pass_a<LPP, BS>(C, k0, k1, [&](int code, int) { return A.r[0][code >> 1]; });
+    pass_a_lds<LPP, BS>(C, L, k0, k1, [&](int code, int) { return A.r[0][code >> 1]; });
     ok = bar.sync();
     {
         double acc[2] = {0.0, 0.0};
@@ -86,7 +89,7 @@ __global__ void __launch_bounds__(BS) k_cg(CgArgs A) {
             const double *rc = A.r[cur], *sc_ = A.s[cur];
             double *rn_out = A.r[nxt], *sn_out = A.s[nxt];
             // p <- r + beta p, s <- w + beta s, x <- x + alpha p, r <- r - alpha s
-            pass_a<LPP, BS>(C, k0, k1, [&](int code, int) {
+            pass_a_lds<LPP, BS>(C, L, k0, k1, [&](int code, int) {
                 const int l = code >> 1;
                 const double sl = A.w[l] + beta * sc_[l];
                 const double rn = rc[l] - alpha * sl;
@@ -270,7 +273,10 @@ hipError_t enqueue_masked_cg(const sc_particles *p, const sc_contacts *c, const 
     if (R.use_mat && !carve_matrix(c->mat, c->mat_bytes, nc, c->nnz, mb))
         return hipErrorInvalidValue;
     CgKernel kern = cg_kernel(R.lpp, R.block);
-    R.G = R.use_mat ? 1 : persistent_grid(reinterpret_cast<const void *>(kern), R.block, opts->grid);
+    const size_t dyn = chain_lds_dyn(opts->lds_entries_per_wave);
+    R.G = R.use_mat ? 1
+                    : persistent_grid(reinterpret_cast<const void *>(kern), R.block, opts->grid,
+                                      dyn);
     if (R.G < 1) return hipErrorInvalidConfiguration;
     hipError_t e;
     if ((e = hipMemsetAsync(B.ctrl, 0, sizeof(CgCtrl), s)) != hipSuccess ||
@@ -306,9 +312,14 @@ hipError_t enqueue_masked_cg(const sc_particles *p, const sc_contacts *c, const 
         A.ctrl = B.ctrl;
         A.tol = opts->tol;
         A.max_iter = opts->max_iter;
+        const ChainLdsPlan lp = chain_lds_plan(p->n, nc, R.G, R.block,
+                                               opts->lds_entries_per_wave, dyn);
+        A.rank_cap = lp.rank_cap;
+        A.inc_cap = lp.inc_cap;
+        R.cache_used = lp.per_wave;
         void *args[] = {&A};
         e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(R.G),
-                                       dim3(R.block), args, 0, s);
+                                       dim3(R.block), args, dyn, s);
     }
     if (e != hipSuccess) return e;
     return hipEventRecord(e1, s);

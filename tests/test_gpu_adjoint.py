@@ -84,3 +84,33 @@ def test_against_oracle_adjoint(kind, op):
     np.testing.assert_allclose(dq.cpu().numpy()[pm], rq, rtol=0, atol=1e-6 * np.abs(rq).max())
     np.testing.assert_allclose(dpos.cpu().numpy(), rpos, rtol=0,
                                atol=1e-6 * np.abs(rpos).max())
+
+
+def test_chain_cg_lds_share_changes_nothing():
+    """The matrix-free CG keeps pass A's incidence data in LDS up to a
+    capacity (lds_entries_per_wave caps it, -1 turns it off); the arithmetic
+    and its order do not change, so the gradients are bitwise equal for every
+    share."""
+    import paper_1909_06623_amd as sc
+    s = W.rods(2500, seed=83)
+    _say("chain CG LDS shares")
+    P = sc.Particles.from_suspension(s)
+    box = sc.Box(tuple(s.box))
+    u_nc = sc.apply_mobility(P, torch.from_numpy(s.f_ext).cuda())
+    con = sc.build_contacts(P, box, s.delta, u_nc, s.dt)
+    gam, g, st, f_c, u_c = sc.solve_lcp(P, con, tol=1e-10, want_fc=True)
+    assert st["status"] == 0
+    ref = None
+    for cache in (0, -1, 2, 11):
+        dq, dpos, sta = sc.solve_lcp_adjoint(P, box, con, u_nc, s.dt, gam, dL_df=f_c, tol=1e-10,
+                                             op=1, lds_entries_per_wave=cache)
+        assert sta["status"] == 0 and sta["op"] == 1
+        if cache > 0:
+            assert sta["lds_entries_per_wave"] == cache
+        elif cache < 0:
+            assert sta["lds_entries_per_wave"] == 0
+        if ref is None:
+            ref = (dq.clone(), dpos.clone(), sta["iters"])
+        else:
+            assert sta["iters"] == ref[2]
+            assert torch.equal(dq, ref[0]) and torch.equal(dpos, ref[1]), cache
