@@ -267,6 +267,27 @@ def test_chain_lds_share_changes_nothing():
             assert (st["alpha"], st["residual"]) == (ref[3], ref[4]), (grid, cache)
 
 
+def test_chain_rank_ranges_past_lds():
+    """On one workgroup, 40,000 rods have more incidence ranges than LDS
+    holds: the chain reads the ranges from global memory and still keeps as
+    many incidences as fit in LDS. Iterates are bitwise those without any
+    LDS copy, and a few fixed steps meet the oracle's."""
+    s = W.rods(40000, seed=32)
+    _say("chain: ranges past LDS (one workgroup, 40,000 rods)")
+    sc = _sc()
+    P, box, u_nc, con = _setup_gpu(s)
+    c, u_orc, q_orc = O.setup(s)
+    pm = _perm(con)
+    go, gg, sto = O.bbpgd(s, c, q_orc, max_iter=4)
+    a = sc.solve_lcp(P, con, max_iter=4, op=1, grid=1)
+    b = sc.solve_lcp(P, con, max_iter=4, op=1, grid=1, lds_entries_per_wave=-1)
+    assert a[2]["grid"] == 1 and a[2]["lds_entries_per_wave"] > 0
+    assert b[2]["lds_entries_per_wave"] == 0
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    np.testing.assert_allclose(a[0].cpu().numpy()[pm], go, rtol=1e-9,
+                               atol=1e-9 * np.abs(go).max())
+
+
 @pytest.mark.parametrize("spw", [1, 2, 4])
 def test_matrix_launch_shapes_agree(spw):
     """Every launch shape of the one-pass solve runs the same algorithm: a
