@@ -345,6 +345,17 @@ static void gpu_dry(hipStream_t s) {
     o.bb = 1;
     o.op = SC_OP_CHAIN;
     SOLVED(sc_solve_lcp(&S.p, &K.c, &o, gamma2, g2, NULL, NULL, &st, K.ws, K.ws_bytes, s));
+    /* the chain's LDS copy of pass A's data: none, capped, one workgroup */
+    o.lds_entries_per_wave = -1;
+    SOLVED(sc_solve_lcp(&S.p, &K.c, &o, gamma2, g2, NULL, NULL, &st, K.ws, K.ws_bytes, s));
+    o.lds_entries_per_wave = 5;
+    SOLVED(sc_solve_lcp(&S.p, &K.c, &o, gamma2, g2, NULL, NULL, &st, K.ws, K.ws_bytes, s));
+    EXPECT(st.lds_entries_per_wave == 5);
+    o.lds_entries_per_wave = 0;
+    o.grid = 1;
+    SOLVED(sc_solve_lcp(&S.p, &K.c, &o, gamma2, g2, NULL, NULL, &st, K.ws, K.ws_bytes, s));
+    EXPECT(st.grid == 1);
+    o.grid = 0;
     o.op = SC_OP_AUTO;
     o.warm_start = 1;
     SOLVED(sc_solve_lcp(&S.p, &K.c, &o, gamma2, g2, NULL, NULL, &st, K.ws, K.ws_bytes, s));
