@@ -658,25 +658,22 @@ int sc::solve_lcp_on(const sc_particles *p, const sc_contacts *c, const sc_solve
     if (tm) SC_HIP_TRY(hipEventRecord(tm->t0, s));
     SC_HIP_TRY(launch_solver(P, c, opts, gamma, g, s));
     if (tm) SC_HIP_TRY(hipEventRecord(tm->t1, s));
+    // the active count into the control block (zeroed above), the outputs,
+    // then one copy and one synchronisation
+    int b = grid_for(nc);
+    if (b > kMaxReduceBlocks) b = kMaxReduceBlocks;
+    k_count_active<<<b, kBlock, 0, s>>>(nc, gamma, &P.ctrl->n_active);
+    if (f_c || u_c) launch_mob_d(P.A.C, gamma, P.pl.order, f_c, u_c, s);
     Ctrl hc;
     SC_HIP_TRY(hipMemcpyAsync(&hc, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     SC_HIP_TRY(hipStreamSynchronize(s));
+    SC_HIP_TRY(hipGetLastError());
     float kernel_ms = 0.0f;
     if (tm) SC_HIP_TRY(hipEventElapsedTime(&kernel_ms, tm->t0, tm->t1));
-    int *nact = reinterpret_cast<int *>(P.part);
-    SC_HIP_TRY(hipMemsetAsync(nact, 0, sizeof(int), s));
-    int b = grid_for(nc);
-    if (b > kMaxReduceBlocks) b = kMaxReduceBlocks;
-    k_count_active<<<b, kBlock, 0, s>>>(nc, gamma, nact);
-    if (f_c || u_c) launch_mob_d(P.A.C, gamma, P.pl.order, f_c, u_c, s);
-    int hact = 0;
-    SC_HIP_TRY(hipMemcpyAsync(&hact, nact, sizeof(int), hipMemcpyDeviceToHost, s));
-    SC_HIP_TRY(hipStreamSynchronize(s));
-    SC_HIP_TRY(hipGetLastError());
     st->status = hc.status;
     st->iters = hc.iters;
     st->mvops = hc.mvops;
-    st->n_active = hact;
+    st->n_active = hc.n_active;
     st->residual = hc.res;
     st->alpha = hc.alpha;
     st->n_degenerate = hc.ndegen;
